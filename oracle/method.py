@@ -1,0 +1,262 @@
+"""MultiPhaseshift (Section 4.1.2 listing, explained in Section 5.0), in FP64.
+
+One call recovers one signal.  Round i (1-based):
+
+  k*  = k - |R|                                         (listing; Section 5.0)
+  p   = i-th prime >= c k*                             (listing; prime rule)
+  m   = (i mod d2) + 1                                 (listing; projection axis)
+  sets: s = 0 unshifted; s = 1..d2 shifted by eps along unwrapped axis n = s;
+        with a ladder K > 1 also s = d2+1..2 d2 shifted by K eps along n = s - d2
+  v_s[h] = f(t_h) - g(t~_h),  t_h = (h/p) U e_m + eps_s U e_n   (eqs. (36), (41))
+           g(t~) = sum_{(y, a) in R} a exp(2 pi i y . t~)      (adaptive residual,
+                                                               Section 5.0)
+  F_s = DFT(v_s)                                               (Section 2.1)
+  candidates: the k* buckets of largest |F_0| (sorted, Section 5.0)
+  test:   | |F_s[h]| / |F_0[h]| - 1 | < tau  for every shifted set (eq. (42))
+  decode: y_n = Arg(F_n[h] / F_0[h]) / (2 pi eps),  a = F_0[h] / p   (eq. (41))
+  R <- R u {(y, a)};  prune small coefficients;  i <- i + 1
+  finally wrap each y back to w (inverse of eq. (35))
+
+The readings taken where the paper is silent or inconsistent are listed in
+READINGS and cited in the code by their key.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .transforms import dft
+from .philox import sample_noise
+from .primes import ith_prime_at_least
+from .signal import evaluate, sample_points
+from .unwrapping import wrap, y_range
+
+READINGS = {
+    "R1": "Phaseshift listing labels the shifted and unshifted sample vectors the other "
+          "way round from eq. (2); the eps-labelled set is the shifted one.",
+    "R2": "Sample index h runs over 0..p-1 at h/p (eq. (2)); the listings' (h-1)/p, h=1..p "
+          "is the same point set.",
+    "R3": "Unwrapping powers are N^0..N^(d1-1) (eq. (35)); the sampling line of the listing "
+          "writes N^1..N^d1.",
+    "R4": "Block of coordinate l (1-based) is floor((l-1)/d1)+1, consistent with eq. (38).",
+    "R5": "Collision ratio is |F_shifted| / |F_0| as in eqs. (8), (42) (the listings invert "
+          "it; the test is symmetric to first order).",
+    "R6": "Test tolerance tau is a parameter; the listing compares against eps, which is the "
+          "default.  Noisy inputs add tau_noise*sqrt(p)/|F_0[h]| (not in the paper).",
+    "R7": "SORT orders buckets by |F_0| descending, ties by ascending h; the first k* are "
+          "tested; the same permutation applies to every shifted set.",
+    "R8": "'Prune small coefficients' drops |a| < eta; buckets with |F_0[h]|/p < eta are "
+          "not candidates.",
+    "R9": "p is the i-th prime >= max(ceil(c k*), p_min) in round i (p_min = 0 is the "
+          "paper's rule; the smooth rule keeps primes with 7-smooth p-1).",
+    "R10": "R is a map from y to a; accepting an existing y adds the coefficients, in "
+           "ascending bucket order.",
+    "R11": "Decoded frequencies are rounded to the nearest integer, ties away from zero.",
+    "R12": "Arg takes values in [-pi, pi): atan2's +pi maps to -pi.",
+    "R13": "The loop also stops after max_rounds rounds (status NOT_CONVERGED).",
+    "R15": "The unshifted set does not depend on n (eq. (41)) and is sampled once per round.",
+    "R16": "A decoded coordinate outside the unwrapped band [-(N/2) S, (N/2-1) S], "
+           "S = sum N^r, cannot be a frequency of the signal model (eq. (32)) and the bucket "
+           "is rejected.",
+    "R17": "Robust mode (not in the paper): also reject a bucket unless y_m = h (mod p) and "
+           "the coarse decode lies within N^d1/(4K) of the ladder-refined one.",
+    "R18": "Noise ladder (not in the paper): with K > 1 each axis also gets a K eps shift; "
+           "y = y_c + round(wrap(theta_K - 2 pi K eps y_c) / (2 pi K eps)).",
+    "R19": "Noise (not in the paper): sigma/sqrt(2) (g1 + i g2) per sample from "
+           "Philox4x64-10, key (seed, signal), counter (h, set, round, 0).",
+}
+
+STATUS_OK = 0
+STATUS_NOT_CONVERGED = 1
+
+
+@dataclass
+class Params:
+    d: int
+    N: int
+    k: int
+    d1: int = 1
+    c: float = 5.0
+    ladder_K: int = 1
+    tau: float | None = None
+    tau_noise: float = 0.0
+    eta: float = 1e-3
+    max_rounds: int = 64
+    prime_rule: str = "paper"
+    p_min: int = 0
+    robust: bool = False
+
+    @property
+    def d2(self) -> int:
+        return self.d // self.d1
+
+    @property
+    def NB(self) -> int:
+        """Bandwidth of one unwrapped coordinate, N^d1."""
+        return int(self.N) ** self.d1
+
+    @property
+    def eps(self) -> float:
+        """Shift eps = 1 / (2 N^d1) (Section 5)."""
+        return 1.0 / (2.0 * self.NB)
+
+    @property
+    def tau_eff(self) -> float:
+        return self.eps if self.tau is None else float(self.tau)
+
+    def validate(self):
+        if self.d < 1 or self.d1 < 1 or self.d % self.d1:
+            raise ValueError("d must be a positive multiple of d1")
+        if self.N < 2 or self.N % 2:
+            raise ValueError("N must be even and >= 2")
+        if self.k < 1 or self.c <= 1.0 or self.ladder_K < 1:
+            raise ValueError("bad k, c or ladder_K")
+
+
+def shift_table(d2: int, ladder_K: int):
+    """[(n, K)] for sets s = 1..S: coarse eps on each axis, then K eps on each axis."""
+    tab = [(n, 1) for n in range(1, d2 + 1)]
+    if ladder_K > 1:
+        tab += [(n, int(ladder_K)) for n in range(1, d2 + 1)]
+    return tab
+
+
+@dataclass
+class Result:
+    freqs: np.ndarray          # int64 [kf, d], lexicographic order
+    coeffs: np.ndarray         # complex128 [kf]
+    y: np.ndarray              # int64 [kf, d2] unwrapped, same order
+    status: int
+    rounds: int
+    samples: int
+    trace: list = field(default_factory=list)
+    spectra: list = field(default_factory=list)
+    registry: list = field(default_factory=list)
+
+
+def _round_half_away(x: float) -> int:
+    """R11."""
+    return int(math.copysign(math.floor(abs(x) + 0.5), x))
+
+
+def _arg(z: complex) -> float:
+    """R12: Arg in [-pi, pi)."""
+    th = math.atan2(z.imag, z.real)
+    return -math.pi if th >= math.pi else th
+
+
+def _wrap_pi(x: float) -> float:
+    return x - 2.0 * math.pi * math.floor((x + math.pi) / (2.0 * math.pi))
+
+
+def _residual(yR, aR, p, m, n, shift):
+    """g(t~_h) = sum_{(y, a) in R} a exp(2 pi i ((h/p) y_m + shift y_n)) for h = 0..p-1."""
+    h = np.arange(p, dtype=np.float64)
+    ph = np.outer(h / p, yR[:, m - 1].astype(np.float64))
+    ph = ph + shift * yR[:, n - 1].astype(np.float64)[None, :]
+    return np.exp(2j * np.pi * ph) @ aR
+
+
+def _test_and_decode(F, h, p, m, P: Params, tab):
+    """Collision test (eq. (42)) and phase-ratio decode (eq. (41)) of bucket h."""
+    F0 = complex(F[0][h])
+    absF0 = abs(F0)
+    thr = P.tau_eff + (P.tau_noise * math.sqrt(p) / absF0 if P.tau_noise > 0 else 0.0)
+    ratios = [complex(F[s][h]) / F0 for s in range(1, len(tab) + 1)]
+    for r in ratios:
+        if not abs(abs(r) - 1.0) < thr:
+            return None
+    NB = P.NB
+    y = np.zeros(P.d2, dtype=np.int64)
+    for n in range(1, P.d2 + 1):
+        th = _arg(ratios[n - 1])
+        yc_real = th * NB / math.pi            # Arg / (2 pi eps) with eps = 1/(2 NB)
+        yn = _round_half_away(yc_real)
+        if P.ladder_K > 1:                     # R18
+            K = P.ladder_K
+            thf = _arg(ratios[P.d2 + n - 1])
+            q = (K * yn) % (2 * NB)            # 2 pi K eps yn, reduced exactly
+            delta = _wrap_pi(thf - math.pi * q / NB)
+            yn = yn + _round_half_away(delta * NB / (math.pi * K))
+            if P.robust and abs(yc_real - yn) > NB / (4.0 * K):
+                return None
+        y[n - 1] = yn
+    lo, hi = y_range(P.N, P.d1)                # R16: out-of-band decodes are no mode
+    if np.any(y < lo) or np.any(y > hi):
+        return None
+    if P.robust and (int(y[m - 1]) % p) != h:  # R17
+        return None
+    return tuple(int(v) for v in y), F0 / p
+
+
+def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
+                    signal: int = 0, keep_spectra: bool = False) -> Result:
+    """Recover the spectrum of the planted signal sum_j coeffs[j] e^{2 pi i freqs[j] . t}.
+
+    The signal is only evaluated as a black box at the sampling points; the
+    planted lists are never read otherwise.
+    """
+    P.validate()
+    freqs = np.asarray(freqs, dtype=np.int64)
+    coeffs = np.asarray(coeffs, dtype=np.complex128)
+    d, d1, d2, N = P.d, P.d1, P.d2, P.N
+    eps = P.eps
+    tab = shift_table(d2, P.ladder_K)
+    R: dict = {}
+    trace, spectra, registry = [], [], []
+    samples = 0
+    i = 1
+    while len(R) < P.k and i <= P.max_rounds:              # R13
+        kstar = P.k - len(R)
+        p = ith_prime_at_least(max(math.ceil(P.c * kstar), P.p_min), i,
+                               smooth=(P.prime_rule == "smooth"))
+        m = (i % d2) + 1
+        h = np.arange(p)
+        snapshot = (np.array(list(R.keys()), dtype=np.int64).reshape(-1, d2),
+                    np.array(list(R.values()), dtype=np.complex128))
+        if R:
+            yR = np.array(list(R.keys()), dtype=np.int64)
+            aR = np.array(list(R.values()), dtype=np.complex128)
+        F = []
+        for s, (n, K) in enumerate([(1, 0)] + tab):        # R15: set 0 once per round
+            shift = eps * K
+            t = sample_points(d, d1, N, p, m, n, shift)
+            v = evaluate(freqs, coeffs, t)
+            v = v + sample_noise(seed, signal, i, s, h, sigma)
+            if R:                                          # adaptive subtraction of g
+                v = v - _residual(yR, aR, p, m, n, shift)
+            F.append(dft(v))
+        samples += len(F) * p
+        F0 = F[0]
+        order = np.argsort(-np.abs(F0), kind="stable")[:kstar]          # R7
+        cand = sorted(int(x) for x in order if abs(F0[x]) / p >= P.eta)  # R8
+        accepted = []
+        for hb in cand:
+            out = _test_and_decode(F, hb, p, m, P, tab)
+            if out is not None:
+                accepted.append(out)
+        for y, a in accepted:                                            # R10
+            R[y] = R.get(y, 0.0) + a
+        R = {y: a for y, a in R.items() if abs(a) >= P.eta}              # R8
+        trace.append(dict(i=i, kstar=kstar, p=p, m=m, n_cand=len(cand),
+                          n_acc=len(accepted), n_R=len(R)))
+        if keep_spectra:
+            spectra.append(np.array(F))
+            registry.append(snapshot)
+        i += 1
+    status = STATUS_OK if len(R) >= P.k else STATUS_NOT_CONVERGED
+    if R:
+        ys = np.array(list(R.keys()), dtype=np.int64).reshape(-1, d2)
+        a = np.array(list(R.values()), dtype=np.complex128)
+        w = wrap(ys, d1, N)
+        order = np.lexsort(w.T[::-1])
+        w, a, ys = w[order], a[order], ys[order]
+    else:
+        w = np.zeros((0, d), np.int64)
+        a = np.zeros(0, np.complex128)
+        ys = np.zeros((0, d2), np.int64)
+    return Result(freqs=w, coeffs=a, y=ys, status=status, rounds=i - 1,
+                  samples=samples, trace=trace, spectra=spectra,
+                  registry=registry)
