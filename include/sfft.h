@@ -1,0 +1,156 @@
+/*
+ * sfft.h -- C ABI of the MI355X (gfx950) sparse Fourier recovery library.
+ *
+ * The library recovers k-sparse spectra of d-dimensional signals
+ *     f(t) = sum_j a_j exp(2 pi i w_j . t),  w_j in [-N/2, N/2)^d integer,
+ * (the problem statement of "High-Dimensional Sparse Fourier Algorithms",
+ * Choi, Christlieb, Wang: Section 2.2 eq. (9), Section 4.1.2 eq. (32)) with
+ * the MultiPhaseshift method of Section 4.1.2: partial unwrapping of the d
+ * coordinates into d2 = d/d1 coordinates of bandwidth N^d1 (eq. (35)),
+ * sampling along the unwrapped axis m at h/p and at the same points shifted
+ * by eps along each axis n (eq. (41)), prime-length DFTs, the collision test
+ * of eq. (42), phase-ratio decoding of eq. (41), and adaptive subtraction of
+ * the modes already found (Section 5.0).
+ *
+ * Conventions (every entry point):
+ *   - Plain C types only.  "device" pointers are HIP device memory on the
+ *     current device; "host" pointers are ordinary host memory.
+ *   - The caller owns every buffer it passes.  A plan owns its workspace.
+ *   - Argument errors are detected on the host before any launch and
+ *     returned synchronously; sfft_last_error() then describes them.  Launch
+ *     failures return SFFT_EDEVICE.  Data-dependent outcomes (a signal that
+ *     did not converge) are written to the per-signal status output.
+ *   - Entry points taking a `stream` (a hipStream_t, NULL = default stream)
+ *     only enqueue work; outputs are valid after the stream synchronises.
+ *   - A plan may be used by one stream at a time; calls on one plan that
+ *     overlap in time race on its workspace.
+ */
+#ifndef SFFT_H
+#define SFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfft_plan_s* sfft_plan;
+
+typedef enum {
+  SFFT_OK = 0,
+  SFFT_NOT_CONVERGED = 1, /* per-signal: max_rounds reached with |R| < k          */
+  SFFT_EINVAL = -1,       /* invalid argument (see sfft_last_error())             */
+  SFFT_ERANGE = -2,       /* sizes beyond what the plan or the device supports    */
+  SFFT_ENOMEM = -3,       /* device allocation failed                             */
+  SFFT_EDEVICE = -4       /* HIP runtime error                                    */
+} sfft_status;
+
+enum { SFFT_PRIME_PAPER = 0, SFFT_PRIME_SMOOTH = 1 };
+enum { SFFT_FP64 = 0, SFFT_FP32 = 1 };
+enum { SFFT_CLS_PLAIN = 0 };
+
+/* Method parameters (the inputs c, k, N, d, d1, d2, eps of the MultiPhaseshift
+ * listing, plus the readings the paper leaves open). */
+typedef struct {
+  int32_t d;          /* dimension, >= 1                                            */
+  int32_t d1;         /* unwrapping block size; d % d1 == 0; d2 = d / d1            */
+  int64_t N;          /* per-dimension bandwidth, even, >= 2; N^d1 <= 2^40          */
+  int32_t k_max;      /* largest sparsity of any signal recovered with this plan    */
+  double c;           /* p_i = i-th prime >= max(ceil(c k*), p_min); c > 1          */
+  int32_t prime_rule; /* SFFT_PRIME_PAPER, or SFFT_PRIME_SMOOTH (p - 1 7-smooth)    */
+  int32_t p_min;      /* floor on c k* (0 = the paper's rule)                       */
+  int32_t ladder_K;   /* 1: one shift eps per axis (paper).  K > 1: also K*eps      */
+  double tau;         /* collision-test tolerance; <= 0 means tau = eps            */
+  double tau_noise;   /* extra tolerance tau_noise * sqrt(p) / |F_0[h]| (>= 0)      */
+  double eta;         /* prune |a| < eta; buckets with |F_0|/p < eta are skipped    */
+  int32_t max_rounds; /* round cap, 1..256                                          */
+  int32_t precision;  /* SFFT_FP64: FP64 end to end.  SFFT_FP32: FP32 samples,
+                         exponential sums and DFTs, FP64 decode and registry        */
+  int32_t robust;     /* 0: paper's test.  1: also residue y_m = h (mod p) and
+                         ladder-consistency checks                                  */
+  int32_t classifier; /* SFFT_CLS_PLAIN (the ratio-magnitude test of eq. (42))      */
+} sfft_params;
+
+/* A batch of synthetic black-box signals with planted spectra.  All pointers
+ * are device pointers.  Signal b is sum_{j in [mode_off[b], mode_off[b+1])}
+ * coeffs[j] exp(2 pi i freqs[j] . t) plus complex Gaussian noise of standard
+ * deviation sigma[b] per sample (noise from Philox4x64-10, key (seed, b),
+ * counter (h, sample set, round, 0); Box-Muller in FP64). */
+typedef struct {
+  int32_t B;                /* number of signals, 1..max_batch                    */
+  const int64_t* mode_off;  /* [B + 1], mode_off[0] = 0, non-decreasing           */
+  const int64_t* freqs;     /* [mode_off[B]][d] integer frequencies in band       */
+  const double* coeffs;     /* [mode_off[B]][2] complex coefficients (re, im)     */
+  const int32_t* k;         /* [B] sparsity given to the method, 1..k_max         */
+  const double* sigma;      /* [B] noise standard deviation, >= 0                 */
+  uint64_t seed;            /* noise key material                                 */
+} sfft_signal_batch;
+
+#define SFFT_TRACE_W 8 /* per round: i, k*, p, m, candidates, accepted, |R|, 0 */
+
+/* Outputs of sfft_recover (device pointers; the optional ones may be NULL). */
+typedef struct {
+  int64_t* freqs;    /* [B][k_max][d] recovered w, lexicographic order, zero-padded */
+  double* coeffs;    /* [B][k_max][2] recovered a (re, im), same order              */
+  int32_t* k_found;  /* [B] number of modes written (|R| at the end)                */
+  int32_t* status;   /* [B] SFFT_OK or SFFT_NOT_CONVERGED (or SFFT_ERANGE)          */
+  int32_t* rounds;   /* [B] rounds run (optional)                                   */
+  int64_t* samples;  /* [B] signal samples taken (optional)                         */
+  int32_t* trace;    /* [B][max_rounds][SFFT_TRACE_W] per-round record (optional)   */
+} sfft_outputs;
+
+/* Create a plan: validates `params` (SFFT_EINVAL / SFFT_ERANGE), derives the
+ * prime tables, the largest prime any round can use and the DFT sizes, and
+ * allocates all device workspace for up to `max_batch` signals on the
+ * current device (SFFT_ENOMEM).  `*out` is set only on SFFT_OK. */
+sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_plan* out);
+
+/* Release a plan and its workspace (synchronises the device first).  NULL is
+ * accepted. */
+sfft_status sfft_plan_destroy(sfft_plan plan);
+
+/* Recover every signal of `batch` (MultiPhaseshift, Section 4.1.2 listing):
+ * one persistent launch in which each work-group takes signals from a queue
+ * and runs all rounds of one signal (sample, DFT, select, test, decode,
+ * registry update) before taking the next.  Allocates nothing. */
+sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch,
+                         const sfft_outputs* out, void* stream);
+
+/* The line sampler on its own (eqs. (36), (41), adaptive residual of
+ * Section 5.0): for each signal b writes the S+1 sample sets of round `round`
+ * (1-based; keys the noise counter) along unwrapped axis m (1-based) with
+ * prime p:
+ *   V[b][s][h] = f_b(t_{s,h}) - sum_{e} res_coeffs[e] exp(2 pi i y_e . t~_{s,h})
+ * for h < p, where set 0 is unshifted and set s >= 1 is shifted by K_s eps
+ * along axis n_s (s = 1..d2: K = 1, n = s; s = d2+1..2 d2: K = ladder_K,
+ * n = s - d2).  res_off[b]..res_off[b+1] index the residual modes of signal b
+ * (res_y: [*][d2] int64 unwrapped frequencies, res_coeffs: [*][2] double);
+ * res_off may be NULL (no residual).  V is complex of the plan's precision
+ * (float2 or double2), [B][S+1][p], device.  p must be prime and at most the
+ * plan's largest prime. */
+sfft_status sfft_sample_lines(sfft_plan plan, const sfft_signal_batch* batch, int32_t round,
+                              int32_t p, int32_t m, const int64_t* res_off,
+                              const int64_t* res_y, const double* res_coeffs, void* V,
+                              void* stream);
+
+/* Batched DFT of Section 2.1, X[h] = sum_j x[j] exp(-2 pi i h j / p), on
+ * `count` sequences of length p stored back to back in `data` (complex of the
+ * plan's precision, device), in place.  Any p in [2, plan's largest prime]. */
+sfft_status sfft_dft(sfft_plan plan, void* data, int32_t count, int32_t p, void* stream);
+
+/* Largest prime a round of this plan can use, and the number of sample sets
+ * per round (S+1). */
+int32_t sfft_plan_max_prime(sfft_plan plan);
+int32_t sfft_plan_num_sets(sfft_plan plan);
+
+/* Text of the last error on this thread ("" if none). */
+const char* sfft_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t sfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFFT_H */

@@ -24,12 +24,12 @@ from .philox import philox4x64_10, sample_noise
 from .signal import evaluate, sample_points
 from .transforms import dft_direct, dft
 from .phaseshift import phaseshift_1d
-from .method import Params, Result, multiphaseshift, shift_table, READINGS
+from .method import Params, Result, multiphaseshift, round_samples, shift_table, READINGS
 
 __all__ = [
     "is_prime", "ith_prime_at_least", "primes_upto",
     "unwrap_matrix", "unwrap", "wrap", "y_range",
     "philox4x64_10", "sample_noise", "evaluate", "sample_points",
     "dft_direct", "dft", "phaseshift_1d",
-    "Params", "Result", "multiphaseshift", "shift_table", "READINGS",
+    "Params", "Result", "multiphaseshift", "round_samples", "shift_table", "READINGS",
 ]

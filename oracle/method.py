@@ -191,6 +191,29 @@ def _test_and_decode(F, h, p, m, P: Params, tab):
     return tuple(int(v) for v in y), F0 / p
 
 
+def round_samples(freqs, coeffs, P: Params, p: int, m: int, i: int, yR, aR,
+                  sigma: float = 0.0, seed: int = 0, signal: int = 0) -> np.ndarray:
+    """The S+1 sample sets of round i: v_s[h] = f(t_h) + noise - g(t~_h), complex [S+1, p].
+
+    t_h = (h/p) U e_m + eps_s U e_n (eqs. (36), (41)); g is the registry
+    {(yR[e], aR[e])} evaluated on the unwrapped line (Section 5.0).  Set 0 is
+    unshifted and is sampled once per round (R15).
+    """
+    d, d1, N = P.d, P.d1, P.N
+    tab = shift_table(P.d2, P.ladder_K)
+    h = np.arange(p)
+    V = []
+    for s, (n, K) in enumerate([(1, 0)] + tab):
+        shift = P.eps * K
+        t = sample_points(d, d1, N, p, m, n, shift)
+        v = evaluate(freqs, coeffs, t)
+        v = v + sample_noise(seed, signal, i, s, h, sigma)
+        if len(aR):                                        # adaptive subtraction of g
+            v = v - _residual(np.asarray(yR), np.asarray(aR), p, m, n, shift)
+        V.append(v)
+    return np.array(V)
+
+
 def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
                     signal: int = 0, keep_spectra: bool = False) -> Result:
     """Recover the spectrum of the planted signal sum_j coeffs[j] e^{2 pi i freqs[j] . t}.
@@ -202,7 +225,6 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
     freqs = np.asarray(freqs, dtype=np.int64)
     coeffs = np.asarray(coeffs, dtype=np.complex128)
     d, d1, d2, N = P.d, P.d1, P.d2, P.N
-    eps = P.eps
     tab = shift_table(d2, P.ladder_K)
     R: dict = {}
     trace, spectra, registry = [], [], []
@@ -213,21 +235,11 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
         p = ith_prime_at_least(max(math.ceil(P.c * kstar), P.p_min), i,
                                smooth=(P.prime_rule == "smooth"))
         m = (i % d2) + 1
-        h = np.arange(p)
         snapshot = (np.array(list(R.keys()), dtype=np.int64).reshape(-1, d2),
                     np.array(list(R.values()), dtype=np.complex128))
-        if R:
-            yR = np.array(list(R.keys()), dtype=np.int64)
-            aR = np.array(list(R.values()), dtype=np.complex128)
-        F = []
-        for s, (n, K) in enumerate([(1, 0)] + tab):        # R15: set 0 once per round
-            shift = eps * K
-            t = sample_points(d, d1, N, p, m, n, shift)
-            v = evaluate(freqs, coeffs, t)
-            v = v + sample_noise(seed, signal, i, s, h, sigma)
-            if R:                                          # adaptive subtraction of g
-                v = v - _residual(yR, aR, p, m, n, shift)
-            F.append(dft(v))
+        V = round_samples(freqs, coeffs, P, p, m, i, snapshot[0], snapshot[1],
+                          sigma=sigma, seed=seed, signal=signal)
+        F = [dft(v) for v in V]
         samples += len(F) * p
         F0 = F[0]
         order = np.argsort(-np.abs(F0), kind="stable")[:kstar]          # R7

@@ -1,0 +1,366 @@
+// Host side of the C ABI: parameter validation, plan construction (prime
+// tables, DFT sizes, workspace) and the launch entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sfft.h"
+#include "sfft_internal.hpp"
+
+using namespace sfft;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+sfft_status fail(sfft_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+sfft_status hip_fail(hipError_t e, const char* what) {
+  return fail(SFFT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_prime_host(int64_t n) {
+  if (n < 2) return false;
+  if (n < 4) return true;
+  if (n % 2 == 0) return false;
+  for (int64_t f = 3; f * f <= n; f += 2)
+    if (n % f == 0) return false;
+  return true;
+}
+
+bool smooth7(int64_t n) {
+  if (n < 1) return false;
+  for (int64_t f : {2, 3, 5, 7})
+    while (n % f == 0) n /= f;
+  return n == 1;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct sfft_plan_s {
+  sfft_params prm;
+  int device = 0;
+  int max_batch = 0;
+  KParams kp;
+  int32_t* d_primes = nullptr;
+  void* d_twL = nullptr;
+  char* d_ws = nullptr;
+  int* d_queue = nullptr;
+};
+
+static sfft_status validate_params(const sfft_params* p) {
+  if (!p) return fail(SFFT_EINVAL, "params is NULL");
+  if (p->d < 1 || p->d1 < 1 || p->d % p->d1 != 0)
+    return fail(SFFT_EINVAL, "d (%d) must be a positive multiple of d1 (%d)", p->d, p->d1);
+  if (p->d / p->d1 > kMaxD2) return fail(SFFT_ERANGE, "d2 = d/d1 exceeds %d", kMaxD2);
+  if (p->N < 2 || p->N % 2 != 0) return fail(SFFT_EINVAL, "N must be even and >= 2");
+  double nb = 1.0;
+  for (int r = 0; r < p->d1; ++r) nb *= (double)p->N;
+  if (nb > 1099511627776.0) return fail(SFFT_ERANGE, "N^d1 exceeds 2^40");
+  if (p->k_max < 1) return fail(SFFT_EINVAL, "k_max must be >= 1");
+  if (!(p->c > 1.0) || !std::isfinite(p->c)) return fail(SFFT_EINVAL, "c must be > 1");
+  if (p->prime_rule != SFFT_PRIME_PAPER && p->prime_rule != SFFT_PRIME_SMOOTH)
+    return fail(SFFT_EINVAL, "unknown prime_rule");
+  if (p->p_min < 0) return fail(SFFT_EINVAL, "p_min must be >= 0");
+  if (p->ladder_K < 1) return fail(SFFT_EINVAL, "ladder_K must be >= 1");
+  if (p->ladder_K > 1 && (double)p->ladder_K * nb > 4.0e18)
+    return fail(SFFT_ERANGE, "ladder_K * N^d1 overflows");
+  if (!std::isfinite(p->tau)) return fail(SFFT_EINVAL, "tau must be finite");
+  if (!(p->tau_noise >= 0.0) || !std::isfinite(p->tau_noise))
+    return fail(SFFT_EINVAL, "tau_noise must be >= 0");
+  if (!(p->eta > 0.0) || !std::isfinite(p->eta)) return fail(SFFT_EINVAL, "eta must be > 0");
+  if (p->max_rounds < 1 || p->max_rounds > 256)
+    return fail(SFFT_EINVAL, "max_rounds must be in 1..256");
+  if (p->precision != SFFT_FP64 && p->precision != SFFT_FP32)
+    return fail(SFFT_EINVAL, "unknown precision");
+  if (p->robust != 0 && p->robust != 1) return fail(SFFT_EINVAL, "robust must be 0 or 1");
+  if (p->classifier != SFFT_CLS_PLAIN) return fail(SFFT_EINVAL, "unknown classifier");
+  return SFFT_OK;
+}
+
+extern "C" {
+
+const char* sfft_last_error(void) { return g_err; }
+
+int32_t sfft_version(void) { return 100; }
+
+sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_plan* out) {
+  g_err[0] = 0;
+  if (!out) return fail(SFFT_EINVAL, "out is NULL");
+  sfft_status st = validate_params(params);
+  if (st != SFFT_OK) return st;
+  if (max_batch < 1) return fail(SFFT_EINVAL, "max_batch must be >= 1");
+  const sfft_params& P = *params;
+
+  KParams kp;
+  memset(&kp, 0, sizeof(kp));
+  kp.d = P.d;
+  kp.d1 = P.d1;
+  kp.d2 = P.d / P.d1;
+  kp.S = (P.ladder_K > 1) ? 2 * kp.d2 : kp.d2;
+  kp.S1 = kp.S + 1;
+  kp.RT = (2 * kp.S1 + 15) / 16;
+  if (P.precision == SFFT_FP32 && kp.RT > kMaxRT)
+    return fail(SFFT_ERANGE, "2 (S+1) = %d real rows exceed the %d MFMA row tiles", 2 * kp.S1,
+                kMaxRT);
+  kp.N = P.N;
+  kp.NB = 1;
+  for (int r = 0; r < P.d1; ++r) kp.NB *= P.N;
+  kp.k_max = P.k_max;
+  kp.cap = P.k_max;
+  kp.pairs_max = (kp.k_max + 1) / 2 + (kp.cap + 1) / 2;
+  kp.m_max = 2 * kp.pairs_max;
+  kp.max_rounds = P.max_rounds;
+  kp.prime_rule = P.prime_rule;
+  kp.p_min = P.p_min;
+  kp.ladder_K = P.ladder_K;
+  kp.robust = P.robust;
+  kp.precision = P.precision;
+  kp.c = P.c;
+  kp.tau = (P.tau > 0.0) ? P.tau : 1.0 / (2.0 * (double)kp.NB);
+  kp.tau_noise = P.tau_noise;
+  kp.eta = P.eta;
+
+  // Largest prime any round can use: the max_rounds-th rule prime >= max(ceil(c k_max), p_min).
+  const double xd = std::max(std::ceil(P.c * (double)P.k_max), (double)P.p_min);
+  if (xd > 40000.0) return fail(SFFT_ERANGE, "c * k_max = %.0f is beyond the prime range", xd);
+  const int64_t x = (int64_t)xd;
+  std::vector<int32_t> primes;
+  const bool smooth = (P.prime_rule == SFFT_PRIME_SMOOTH);
+  int found = 0;
+  int64_t pmax = 0;
+  for (int64_t q = 2; found < P.max_rounds; ++q) {
+    if (q > 46000) return fail(SFFT_ERANGE, "prime schedule exceeds 46000");
+    if (is_prime_host(q) && (!smooth || smooth7(q - 1))) {
+      primes.push_back((int32_t)q);
+      if (q >= x) {
+        ++found;
+        pmax = q;
+      }
+    }
+  }
+  kp.p_max = (int)pmax;
+  int L = 1, lg = 0;
+  while (L < 2 * kp.p_max - 1) {
+    L <<= 1;
+    ++lg;
+  }
+  const int maxL = (P.precision == SFFT_FP32) ? 8192 : 4096;
+  if (L > maxL)
+    return fail(SFFT_ERANGE,
+                "largest prime %d needs a %d-point Bluestein DFT; the LDS DFT holds %d points",
+                kp.p_max, L, maxL);
+  kp.L_max = L;
+  kp.log2_Lmax = lg;
+  kp.vstride = kp.p_max;
+  const size_t cs = (P.precision == SFFT_FP32) ? 8 : 16;  // complex element size
+
+  // LDS: the largest of the per-step carve-ups.
+  size_t lds = 0;
+  lds = std::max(lds, (size_t)L * cs);                                    // DFT buffer
+  lds = std::max(lds, align16((size_t)kp.p_max * cs) + 4 * (size_t)kp.m_max);  // sampler
+  lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
+  lds = std::max(lds, merge_lds(kp.k_max, kp.cap).bytes);                // registry merge
+  lds = std::max(lds, 4 * (size_t)kp.k_max);                             // decode / output
+  lds = align16(lds);
+  if (lds > 160 * 1024 - 4096)
+    return fail(SFFT_ERANGE, "plan needs %zu bytes of LDS per work-group", lds);
+  kp.lds_bytes = (int)lds;
+
+  // Workspace layout of one slot.
+  WsLayout lay;
+  size_t o = 0;
+  const int d2 = kp.d2, S = kp.S, S1 = kp.S1;
+  lay.ypl = o;   o = al256(o + 8 * (size_t)kp.k_max * d2);
+  lay.ccomp = o; o = al256(o + cs * (size_t)(kp.m_max + 2) * S1);
+  lay.afrag = o; o = al256(o + (P.precision == SFFT_FP32 ? 4 * (size_t)kp.pairs_max * kp.RT * 64 : 0));
+  for (int b = 0; b < 2; ++b) {
+    lay.ry[b] = o; o = al256(o + 8 * (size_t)kp.cap * d2);
+    lay.ra[b] = o; o = al256(o + 16 * (size_t)kp.cap);
+    lay.rE[b] = o; o = al256(o + 16 * (size_t)kp.cap * S);
+  }
+  lay.V = o;      o = al256(o + cs * (size_t)S1 * kp.vstride);
+  lay.chirp = o;  o = al256(o + cs * (size_t)kp.p_max);
+  lay.bhat = o;   o = al256(o + cs * (size_t)L);
+  lay.cand = o;   o = al256(o + 4 * (size_t)kp.k_max);
+  lay.acc_y = o;  o = al256(o + 8 * (size_t)kp.k_max * d2);
+  lay.acc_a = o;  o = al256(o + 16 * (size_t)kp.k_max);
+  lay.acc_ok = o; o = al256(o + 4 * (size_t)kp.k_max);
+  lay.run = o;    o = al256(o + 4 * (size_t)kp.k_max);
+  lay.bytes = o;
+  kp.lay = lay;
+  kp.ws_slot = lay.bytes;
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  const int per_cu = (lds <= 80 * 1024) ? 2 : 1;
+  kp.n_slots = std::min(max_batch, prop.multiProcessorCount * per_cu);
+  if (kp.n_slots < 1) kp.n_slots = 1;
+
+  sfft_plan plan = new (std::nothrow) sfft_plan_s();
+  if (!plan) return fail(SFFT_ENOMEM, "host allocation failed");
+  plan->prm = P;
+  plan->device = dev;
+  plan->max_batch = max_batch;
+
+  // twiddles exp(-2 pi i t / L) in the plan's precision
+  std::vector<double> tw(2 * (size_t)L);
+  for (int t = 0; t < L; ++t) {
+    const double ang = -2.0 * M_PI * (double)t / (double)L;
+    tw[2 * t] = std::cos(ang);
+    tw[2 * t + 1] = std::sin(ang);
+  }
+  std::vector<float> twf;
+  const void* tw_src = tw.data();
+  size_t tw_bytes = tw.size() * sizeof(double);
+  if (P.precision == SFFT_FP32) {
+    twf.assign(tw.begin(), tw.end());
+    tw_src = twf.data();
+    tw_bytes = twf.size() * sizeof(float);
+  }
+  const size_t ws_bytes = (size_t)kp.n_slots * kp.ws_slot;
+  if ((e = hipMalloc((void**)&plan->d_primes, primes.size() * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc(&plan->d_twL, tw_bytes)) != hipSuccess ||
+      (e = hipMalloc((void**)&plan->d_ws, ws_bytes)) != hipSuccess ||
+      (e = hipMalloc((void**)&plan->d_queue, 256)) != hipSuccess) {
+    sfft_plan_destroy(plan);
+    return fail(SFFT_ENOMEM, "device allocation of %zu bytes failed: %s", ws_bytes,
+                hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(plan->d_primes, primes.data(), primes.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(plan->d_twL, tw_src, tw_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(plan->d_ws, 0, ws_bytes)) != hipSuccess ||
+      (e = hipMemset(plan->d_queue, 0, 256)) != hipSuccess) {
+    sfft_plan_destroy(plan);
+    return hip_fail(e, "plan upload");
+  }
+  const int le = set_kernel_lds_limits((int)lds);
+  if (le != 0) {
+    sfft_plan_destroy(plan);
+    return hip_fail((hipError_t)le, "hipFuncSetAttribute");
+  }
+  kp.primes = plan->d_primes;
+  kp.n_primes = (int)primes.size();
+  kp.twL = plan->d_twL;
+  kp.ws = plan->d_ws;
+  kp.queue = plan->d_queue;
+  plan->kp = kp;
+  *out = plan;
+  return SFFT_OK;
+}
+
+sfft_status sfft_plan_destroy(sfft_plan plan) {
+  if (!plan) return SFFT_OK;
+  (void)hipDeviceSynchronize();
+  if (plan->d_primes) (void)hipFree(plan->d_primes);
+  if (plan->d_twL) (void)hipFree(plan->d_twL);
+  if (plan->d_ws) (void)hipFree(plan->d_ws);
+  if (plan->d_queue) (void)hipFree(plan->d_queue);
+  delete plan;
+  return SFFT_OK;
+}
+
+int32_t sfft_plan_max_prime(sfft_plan plan) { return plan ? plan->kp.p_max : 0; }
+
+int32_t sfft_plan_num_sets(sfft_plan plan) { return plan ? plan->kp.S1 : 0; }
+
+static sfft_status check_batch(sfft_plan plan, const sfft_signal_batch* b) {
+  if (!plan) return fail(SFFT_EINVAL, "plan is NULL");
+  if (!b) return fail(SFFT_EINVAL, "batch is NULL");
+  if (b->B < 1 || b->B > plan->max_batch)
+    return fail(SFFT_EINVAL, "batch size %d outside 1..%d", b->B, plan->max_batch);
+  if (!b->mode_off || !b->freqs || !b->coeffs || !b->k || !b->sigma)
+    return fail(SFFT_EINVAL, "batch has a NULL array");
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  if (dev != plan->device)
+    return fail(SFFT_EINVAL, "current device %d is not the plan's device %d", dev, plan->device);
+  return SFFT_OK;
+}
+
+static KBatch to_kbatch(const sfft_signal_batch* b) {
+  KBatch kb;
+  kb.B = b->B;
+  kb.mode_off = b->mode_off;
+  kb.freqs = b->freqs;
+  kb.coeffs = b->coeffs;
+  kb.k = b->k;
+  kb.sigma = b->sigma;
+  kb.seed = b->seed;
+  return kb;
+}
+
+sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const sfft_outputs* out,
+                         void* stream) {
+  g_err[0] = 0;
+  sfft_status st = check_batch(plan, batch);
+  if (st != SFFT_OK) return st;
+  if (!out || !out->freqs || !out->coeffs || !out->k_found || !out->status)
+    return fail(SFFT_EINVAL, "outputs need freqs, coeffs, k_found and status");
+  KOut ko;
+  ko.freqs = out->freqs;
+  ko.coeffs = out->coeffs;
+  ko.k_found = out->k_found;
+  ko.status = out->status;
+  ko.rounds = out->rounds;
+  ko.samples = out->samples;
+  ko.trace = out->trace;
+  int e = launch_zero_queue(plan->kp, stream);
+  if (e) return hip_fail((hipError_t)e, "queue reset launch");
+  const int grid = std::min(batch->B, plan->kp.n_slots);
+  e = launch_recover(plan->kp, to_kbatch(batch), ko, grid, stream);
+  if (e) return hip_fail((hipError_t)e, "recover launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_sample_lines(sfft_plan plan, const sfft_signal_batch* batch, int32_t round,
+                              int32_t p, int32_t m, const int64_t* res_off, const int64_t* res_y,
+                              const double* res_coeffs, void* V, void* stream) {
+  g_err[0] = 0;
+  sfft_status st = check_batch(plan, batch);
+  if (st != SFFT_OK) return st;
+  if (!V) return fail(SFFT_EINVAL, "V is NULL");
+  if (round < 1) return fail(SFFT_EINVAL, "round is 1-based");
+  if (p < 2 || p > plan->kp.p_max || !is_prime_host(p))
+    return fail(SFFT_EINVAL, "p = %d must be a prime in 2..%d", p, plan->kp.p_max);
+  if (m < 1 || m > plan->kp.d2) return fail(SFFT_EINVAL, "m must be in 1..d2");
+  if (res_off && (!res_y || !res_coeffs))
+    return fail(SFFT_EINVAL, "res_off given without res_y / res_coeffs");
+  const int e = launch_sample_lines(plan->kp, to_kbatch(batch), round, p, m, res_off, res_y,
+                                    res_coeffs, V, stream);
+  if (e) return hip_fail((hipError_t)e, "sampler launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_dft(sfft_plan plan, void* data, int32_t count, int32_t p, void* stream) {
+  g_err[0] = 0;
+  if (!plan) return fail(SFFT_EINVAL, "plan is NULL");
+  if (!data) return fail(SFFT_EINVAL, "data is NULL");
+  if (count < 1) return fail(SFFT_EINVAL, "count must be >= 1");
+  if (p < 2 || p > plan->kp.p_max)
+    return fail(SFFT_EINVAL, "p = %d outside 2..%d", p, plan->kp.p_max);
+  const int e = launch_dft(plan->kp, data, count, p, stream);
+  if (e) return hip_fail((hipError_t)e, "dft launch");
+  return SFFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,385 @@
+// Device building blocks: complex arithmetic, Philox4x64-10 noise, block
+// scans, the LDS Stockham FFT used by the Bluestein prime-length DFT, and the
+// exponential-sum (line sampler) kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sfft_internal.hpp"
+
+namespace sfft {
+
+// ----------------------------------------------------------------- complex --
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cmk(T a, T b) {
+  cpx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) {
+  return cmk<T>(a.x + b.x, a.y + b.y);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) {
+  return cmk<T>(a.x - b.x, a.y - b.y);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return cmk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) {
+  return cmk<T>(a.x * s, a.y * s);
+}
+
+// Largest power-of-two DFT length kept in LDS for each precision.
+template <typename T>
+struct MaxL;
+template <>
+struct MaxL<float> {
+  static constexpr int value = 8192;
+};
+template <>
+struct MaxL<double> {
+  static constexpr int value = 4096;
+};
+
+// exp(i pi x) in FP64 for a dyadic/rational x given as q / den, q exact.
+__device__ __forceinline__ void expipi(double q_over_den, double* c, double* s) {
+  sincospi(q_over_den, s, c);
+}
+
+// ------------------------------------------------------- Philox4x64-10 -----
+// Salmon, Moraes, Dror, Shaw (SC 2011): round function
+// (c0,c1,c2,c3) <- (hi(M1 c2)^c1^k0, lo(M1 c2), hi(M0 c0)^c3^k1, lo(M0 c0)),
+// key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0;
+    const uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Complex Gaussian noise of one sample: sigma/sqrt(2) * sqrt(-2 ln(1-u1)) e^{2 pi i u2}
+// with u1, u2 the top 53 bits of Philox output words 0 and 1.
+__device__ __forceinline__ cpx<double> sample_noise(uint64_t seed, uint64_t signal,
+                                                    uint64_t round, uint64_t set, uint64_t h,
+                                                    double sigma) {
+  uint64_t c[4] = {h, set, round, 0ull};
+  philox4x64_10(c, seed, signal);
+  const double u1 = (double)(c[0] >> 11) * 0x1p-53;
+  const double u2 = (double)(c[1] >> 11) * 0x1p-53;
+  const double rad = sqrt(-2.0 * log1p(-u1));
+  const double ang = 2.0 * M_PI * u2;
+  const double gx = rad * cos(ang), gy = rad * sin(ang);
+  const double sc = sigma / sqrt(2.0);
+  return cmk<double>(sc * gx, sc * gy);
+}
+
+// ------------------------------------------------------------ block scans --
+// In-place exclusive prefix sum of n ints in LDS; returns the total.  Every
+// thread of the work-group must call it.  `part` is LDS scratch of kWG ints.
+__device__ inline int block_exscan(int* a, int n, int* part) {
+  const int tid = threadIdx.x;
+  const int chunk = (n + kWG - 1) / kWG;
+  const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += a[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < kWG; off <<= 1) {
+    const int v = (tid >= off) ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int base = (tid == 0) ? 0 : part[tid - 1];
+  const int total = part[kWG - 1];
+  for (int i = lo; i < hi; ++i) {
+    const int v = a[i];
+    a[i] = base;
+    base += v;
+  }
+  __syncthreads();
+  return total;
+}
+
+__device__ inline int block_sum(int v, int* part) {
+  const int tid = threadIdx.x;
+  part[tid] = v;
+  __syncthreads();
+  for (int off = kWG / 2; off > 0; off >>= 1) {
+    if (tid < off) part[tid] += part[tid + off];
+    __syncthreads();
+  }
+  const int r = part[0];
+  __syncthreads();
+  return r;
+}
+
+// ----------------------------------------------------- LDS Stockham FFT ----
+// One radix-R pass of the Stockham autosort FFT over L points in LDS:
+// item j (k = j mod Ns) reads x_r = buf[j + r L/R], multiplies by
+// w^{r k} with w = exp(-+2 pi i / (Ns R)), applies the R-point DFT and writes
+// buf[(j - k) R + k + r Ns].  All items are read before any is written.
+template <typename T, int R>
+__device__ __forceinline__ void butterfly(cpx<T>* x, bool inv) {
+  if (R == 2) {
+    const cpx<T> a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else {
+    const cpx<T> t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]);
+    const cpx<T> t2 = cadd(x[1], x[3]), t3 = csub(x[1], x[3]);
+    // -i * t3 = (t3.y, -t3.x)
+    const cpx<T> mi_t3 = cmk<T>(t3.y, -t3.x);
+    x[0] = cadd(t0, t2);
+    x[2] = csub(t0, t2);
+    if (!inv) {
+      x[1] = cadd(t1, mi_t3);
+      x[3] = csub(t1, mi_t3);
+    } else {
+      x[1] = csub(t1, mi_t3);
+      x[3] = cadd(t1, mi_t3);
+    }
+  }
+}
+
+template <typename T, int R>
+__device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* __restrict__ twL,
+                              int tw_mul, bool inv) {
+  constexpr int MAXV = MaxL<T>::value / kWG;
+  constexpr int NQ = MAXV / R;
+  cpx<T> v[MAXV];
+  const int nitems = L / R;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int j = tid + q * kWG;
+    if (j < nitems) {
+      const int k = j & (Ns - 1);
+      cpx<T> x[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = buf[j + r * nitems];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cpx<T> w = twL[r * k * tw_mul];
+        if (inv) w.y = -w.y;
+        x[r] = cmul(x[r], w);
+      }
+      butterfly<T, R>(x, inv);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q * R + r] = x[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int j = tid + q * kWG;
+    if (j < nitems) {
+      const int k = j & (Ns - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q * R + r];
+    }
+  }
+  __syncthreads();
+}
+
+// Unnormalised power-of-two FFT of L <= MaxL<T> points in LDS, forward
+// (exp(-2 pi i ...)) or inverse (exp(+2 pi i ...)).  twL holds
+// exp(-2 pi i t / Lmax) for t < Lmax.
+template <typename T>
+__device__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx<T>* __restrict__ twL, int Lmax,
+                        bool inv) {
+  int Ns = 1;
+  if (log2L & 1) {
+    stockham_pass<T, 2>(buf, L, Ns, twL, Lmax / 2, inv);
+    Ns = 2;
+  }
+  while (Ns < L) {
+    stockham_pass<T, 4>(buf, L, Ns, twL, Lmax / (Ns * 4), inv);
+    Ns *= 4;
+  }
+}
+
+// Bluestein set-up for prime length p and power-of-two L >= 2p - 1:
+// chirp[n] = exp(-i pi (n^2 mod 2p) / p) and bhat = FFT_L(b),
+// b[n] = conj(chirp[n]) for |n| < p (wrapped mod L), 0 elsewhere.
+template <typename T>
+__device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
+                                cpx<T>* buf, const cpx<T>* twL, int Lmax) {
+  const int tid = threadIdx.x;
+  for (int n = tid; n < p; n += kWG) {
+    const int64_t q = ((int64_t)n * n) % (2 * (int64_t)p);
+    double c, s;
+    expipi(-(double)q / (double)p, &c, &s);
+    chirp[n] = cmk<T>((T)c, (T)s);
+  }
+  __syncthreads();
+  for (int n = tid; n < L; n += kWG) {
+    cpx<T> v = cmk<T>(0, 0);
+    if (n < p) {
+      v = chirp[n];
+    } else if (n > L - p) {
+      v = chirp[L - n];
+    }
+    v.y = -v.y;
+    buf[n] = v;
+  }
+  __syncthreads();
+  fft_lds<T>(buf, L, log2L, twL, Lmax, false);
+  for (int n = tid; n < L; n += kWG) bhat[n] = buf[n];
+  __syncthreads();
+}
+
+// In-place DFT of one prime-length sequence x (global) via Bluestein:
+// X[k] = chirp[k] * IFFT_L(FFT_L(x . chirp) . bhat)[k] / L.
+template <typename T>
+__device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* chirp,
+                              const cpx<T>* bhat, cpx<T>* buf, const cpx<T>* twL, int Lmax) {
+  const int tid = threadIdx.x;
+  for (int n = tid; n < L; n += kWG) buf[n] = (n < p) ? cmul(x[n], chirp[n]) : cmk<T>(0, 0);
+  __syncthreads();
+  fft_lds<T>(buf, L, log2L, twL, Lmax, false);
+  for (int n = tid; n < L; n += kWG) buf[n] = cmul(buf[n], bhat[n]);
+  __syncthreads();
+  fft_lds<T>(buf, L, log2L, twL, Lmax, true);
+  const T invL = (T)1 / (T)L;
+  for (int n = tid; n < p; n += kWG) x[n] = cscale(cmul(buf[n], chirp[n]), invL);
+  __syncthreads();
+}
+
+// ------------------------------------------------- exponential sums -------
+// (h * r) mod p for 0 <= h, r and h * r < 2^32, exactly.
+__device__ __forceinline__ int mulmod(uint32_t h, uint32_t r, int p, double inv_p) {
+  const uint32_t x = h * r;
+  int q = (int)((double)x * inv_p);
+  int rem = (int)(x - (uint32_t)q * (uint32_t)p);
+  if (rem < 0) rem += p;
+  if (rem >= p) rem -= p;
+  return rem;
+}
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// FP32 line sampler on the matrix cores.  The S1 sample sets of one round
+// share the points h/p along the unwrapped axis m, so
+//   V[s][h] = sum_j C[j][s] * omega_p^{(h r_j) mod p},  r_j = y_{j,m} mod p,
+// is a complex product C (S1 x M) times T (M x p) with T generated from the
+// integer-reduced index.  As a real product, row 2s / 2s+1 hold Re / Im of set
+// s and K index 2j / 2j+1 hold Re / Im of mode j; it runs as
+// v_mfma_f32_16x16x4_f32 tiles: RT row tiles of 16 rows, NT column tiles of
+// 16 points per wave, two modes per K step.  `afrag` holds A in lane order
+// ([pair][RT][64]); `rr` (LDS) holds r_j; `tw` (LDS) holds omega_p^x.
+template <int RT, int NT>
+__device__ void expsum_mfma(const float* __restrict__ afrag, const int* rr,
+                            const cpx<float>* tw, int npairs, int p, int S1,
+                            cpx<float>* __restrict__ V, int vstride) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  constexpr int NWAVES = kWG / 64;
+  constexpr int NCOL = 16 * NT;
+  const int ntiles = (p + NCOL - 1) / NCOL;
+  const double inv_p = 1.0 / (double)p;
+  const int kk = lane >> 4;       // K row of the B fragment
+  const int col = lane & 15;      // column (point) of the B fragment
+  const int jsel = kk >> 1;       // which mode of the pair
+  const int tpart = kk & 1;       // Re / Im of the twiddle
+  const float* twf = reinterpret_cast<const float*>(tw);
+  for (int tile = wave; tile < ntiles; tile += NWAVES) {
+    const int hbase = tile * NCOL;
+    floatx4 acc[RT][NT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const uint32_t h0 = (uint32_t)(hbase + col);
+    for (int pr = 0; pr < npairs; ++pr) {
+      float a[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[t] = afrag[((size_t)pr * RT + t) * 64 + lane];
+      const uint32_t r = (uint32_t)rr[2 * pr + jsel];
+      int idx = mulmod(h0, r, p, inv_p);
+      const int step = mulmod(16u, r, p, inv_p);
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const float b = twf[2 * idx + tpart];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b, acc[t][u], 0, 0, 0);
+        idx += step;
+        if (idx >= p) idx -= p;
+      }
+    }
+    // D layout: lane holds rows 4*(lane/16) + i (i = 0..3) of column lane%16;
+    // rows 4*kk, 4*kk+1 are Re, Im of set 2*kk (+ 8 t), rows 4*kk+2, +3 of the next set.
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int s0 = 8 * t + 2 * kk;
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int h = hbase + 16 * u + col;
+        if (h < p) {
+          if (s0 < S1) V[(size_t)s0 * vstride + h] = cmk<float>(acc[t][u][0], acc[t][u][1]);
+          if (s0 + 1 < S1)
+            V[(size_t)(s0 + 1) * vstride + h] = cmk<float>(acc[t][u][2], acc[t][u][3]);
+        }
+      }
+    }
+  }
+}
+
+// Noise of the synthetic black box, added to every sample of the round.
+template <typename T>
+__device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int S1, uint64_t seed,
+                          uint64_t signal, int round, double sigma) {
+  if (!(sigma > 0.0)) return;
+  for (int q = threadIdx.x; q < S1 * p; q += kWG) {
+    const int s = q / p, h = q - s * p;
+    const cpx<double> n = sample_noise(seed, signal, (uint64_t)round, (uint64_t)s, (uint64_t)h,
+                                       sigma);
+    cpx<T>& v = V[(size_t)s * vstride + h];
+    v.x = (T)((double)v.x + n.x);
+    v.y = (T)((double)v.y + n.y);
+  }
+}
+
+// FP64 line sampler on the vector units: one thread per (set, point).
+__device__ inline void expsum_valu_f64(const cpx<double>* __restrict__ C, const int* rr,
+                                       const cpx<double>* tw, int M, int p, int S1,
+                                       cpx<double>* __restrict__ V, int vstride) {
+  const double inv_p = 1.0 / (double)p;
+  for (int q = threadIdx.x; q < S1 * p; q += kWG) {
+    const int s = q / p, h = q - s * p;
+    cpx<double> acc = cmk<double>(0.0, 0.0);
+    for (int j = 0; j < M; ++j) {
+      const int idx = mulmod((uint32_t)h, (uint32_t)rr[j], p, inv_p);
+      acc = cadd(acc, cmul(C[(size_t)j * S1 + s], tw[idx]));
+    }
+    V[(size_t)s * vstride + h] = acc;
+  }
+}
+
+}  // namespace sfft

@@ -1,0 +1,103 @@
+// Internal structures shared by the host plan code and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sfft {
+
+constexpr int kWG = 256;          // threads per work-group (4 waves of 64)
+constexpr int kMaxD2 = 64;        // largest number of unwrapped coordinates
+constexpr int kMaxSets = 2 * kMaxD2 + 1;
+constexpr int kMaxRT = 8;         // MFMA row tiles: 2 (S+1) real rows <= 128
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS carve-up of the registry merge step (shared by host sizing and device).
+struct MergeLds {
+  size_t accpos, ids, key0, runflag, runpos, cnt, matchrun, keep, bytes;
+};
+__host__ __device__ inline MergeLds merge_lds(int k_max, int cap) {
+  MergeLds m;
+  size_t o = 0;
+  m.accpos = o;   o = align16(o + 4 * (size_t)k_max);
+  m.ids = o;      o = align16(o + 4 * (size_t)(2 * k_max + 2));
+  m.key0 = o;     o = align16(o + 8 * (size_t)(2 * k_max + 2));
+  m.runflag = o;  o = align16(o + 4 * (size_t)k_max);
+  m.runpos = o;   o = align16(o + 4 * (size_t)k_max);
+  m.cnt = o;      o = align16(o + 4 * (size_t)(cap + 1));
+  m.matchrun = o; o = align16(o + 4 * (size_t)cap);
+  m.keep = o;     o = align16(o + 4 * (size_t)(2 * cap + 2));
+  m.bytes = o;
+  return m;
+}
+
+// Byte offsets of one work-group slot's workspace (each 256-byte aligned).
+struct WsLayout {
+  size_t ypl;      // int64  [k_max][d2]        planted modes, unwrapped
+  size_t ccomp;    // cplx T [m_max][S1]        per-mode coefficient rows
+  size_t afrag;    // float  [pairs_max][RT][64] MFMA A fragments (FP32 path)
+  size_t ry[2];    // int64  [cap][d2]          registry keys (two buffers)
+  size_t ra[2];    // double2[cap]              registry coefficients
+  size_t rE[2];    // double2[cap][S]           registry shift phases
+  size_t V;        // cplx T [S1][vstride]      samples, then spectra
+  size_t chirp;    // cplx T [p_max]            Bluestein chirp
+  size_t bhat;     // cplx T [L_max]            DFT of the chirp filter
+  size_t cand;     // int32  [k_max]            candidate buckets
+  size_t acc_y;    // int64  [k_max][d2]        decoded frequencies
+  size_t acc_a;    // double2[k_max]            decoded coefficients
+  size_t acc_ok;   // int32  [k_max]            accept flags, then ranks
+  size_t run;      // int32  [k_max]            merge bookkeeping
+  size_t bytes;    // size of one slot
+};
+
+// Everything a kernel needs about a plan (passed by value).
+struct KParams {
+  int d, d1, d2, S, S1, RT;
+  int64_t N, NB;          // NB = N^d1
+  int k_max, cap, m_max, pairs_max;
+  int max_rounds, prime_rule, p_min, ladder_K, robust, precision;
+  double c, tau, tau_noise, eta;
+  int p_max, L_max, log2_Lmax, vstride;
+  const int32_t* primes;  // ascending primes usable by the prime rule, up to p_max
+  int n_primes;
+  const void* twL;        // complex T [L_max]: exp(-2 pi i t / L_max)
+  char* ws;               // slots back to back
+  size_t ws_slot;
+  WsLayout lay;
+  int* queue;             // work-queue counter (zeroed before each launch)
+  int n_slots;
+  int lds_bytes;
+};
+
+struct KBatch {
+  int B;
+  const int64_t* mode_off;
+  const int64_t* freqs;
+  const double* coeffs;
+  const int32_t* k;
+  const double* sigma;
+  uint64_t seed;
+};
+
+struct KOut {
+  int64_t* freqs;
+  double* coeffs;
+  int32_t* k_found;
+  int32_t* status;
+  int32_t* rounds;
+  int64_t* samples;
+  int32_t* trace;
+};
+
+// Launchers (defined in the .hip file).  Return a hipError_t as int.
+int launch_zero_queue(const KParams& kp, void* stream);
+int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream);
+int launch_sample_lines(const KParams& kp, const KBatch& kb, int round, int p, int m,
+                        const int64_t* res_off, const int64_t* res_y, const double* res_c,
+                        void* V, void* stream);
+int launch_dft(const KParams& kp, void* data, int count, int p, void* stream);
+int set_kernel_lds_limits(int lds_bytes);
+
+}  // namespace sfft

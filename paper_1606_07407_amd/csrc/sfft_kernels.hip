@@ -1,0 +1,900 @@
+// HIP kernels of the MultiPhaseshift recovery (gfx950).
+//
+// recover_kernel: one persistent launch.  Each work-group takes a signal from
+// a work queue and runs every round of MultiPhaseshift for it (Section 4.1.2
+// listing):  plan the round (k*, p, m) -> mode preparation -> line sampler
+// (planted signal minus the registry as one exponential sum) -> S+1 prime
+// length DFTs (Bluestein in LDS) -> top-k* bucket selection -> collision test
+// and FP64 phase-ratio decode -> registry merge and prune, until |R| = k or
+// the round cap, then wraps the unwrapped frequencies back to d dimensions.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sfft_device.hpp"
+#include "sfft_internal.hpp"
+
+namespace sfft {
+
+// ------------------------------------------------------------ helpers -----
+__device__ __forceinline__ int64_t pmod64(int64_t a, int64_t m) {
+  int64_t r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+// Unwrapped shift phase exp(2 pi i eps K y) with eps = 1 / (2 NB):
+// q = K y mod 2 NB exactly, angle = pi q / NB.
+__device__ __forceinline__ cpx<double> shift_phase(int64_t y, int64_t K, int64_t NB) {
+  const int64_t q = pmod64(K * y, 2 * NB);
+  double c, s;
+  expipi((double)q / (double)NB, &c, &s);
+  return cmk<double>(c, s);
+}
+
+// Shift table: set s = 1..d2 -> (n = s, K = 1); s = d2+1..2 d2 -> (n = s - d2, K).
+__device__ __forceinline__ void shift_of(const KParams& kp, int s, int* n0, int64_t* K) {
+  if (s <= kp.d2) {
+    *n0 = s - 1;
+    *K = 1;
+  } else {
+    *n0 = s - kp.d2 - 1;
+    *K = kp.ladder_K;
+  }
+}
+
+// p = i-th prime >= max(ceil(c k*), p_min); -1 if beyond the table.
+__device__ inline int prime_for_round(const KParams& kp, int kstar, int i) {
+  double x = ceil(kp.c * (double)kstar);
+  if (x < (double)kp.p_min) x = (double)kp.p_min;
+  if (x > 2.0e9) return -1;
+  const int xi = (int)x;
+  int lo = 0, hi = kp.n_primes;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (kp.primes[mid] < xi)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  const int idx = lo + i - 1;
+  return (idx < kp.n_primes) ? kp.primes[idx] : -1;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T>* ws_cpx(char* slot, size_t off) {
+  return reinterpret_cast<cpx<T>*>(slot + off);
+}
+
+// Scatter coefficient rows of modes [j0, j1) into MFMA A-fragment order.
+// A[row][k] for K step `pair`: row = 16 t + (lane & 15) -> set row >> 1,
+// Re/Im row & 1; k = lane >> 4 -> mode 2 pair + (k >> 1), Re/Im k & 1;
+// value Re C, -Im C (row Re) or Im C, Re C (row Im).
+__device__ inline void scatter_afrag(const KParams& kp, const cpx<float>* ccomp, float* afrag,
+                                     int j0, int j1) {
+  const int RT = kp.RT, S1 = kp.S1;
+  const int per_mode = RT * 32;
+  const int n = (j1 - j0) * per_mode;
+  for (int q = threadIdx.x; q < n; q += kWG) {
+    const int j = j0 + q / per_mode;
+    const int rem = q - (j - j0) * per_mode;
+    const int t = rem >> 5;
+    const int li = rem & 31;
+    const int jsel = j & 1;
+    // lanes whose k >> 1 == jsel: k in {2 jsel, 2 jsel + 1}
+    const int k = 2 * jsel + (li >> 4);
+    const int lane = k * 16 + (li & 15);
+    const int row = 16 * t + (lane & 15);
+    const int s = row >> 1;
+    float v = 0.f;
+    if (s < S1) {
+      const cpx<float> c = ccomp[(size_t)j * S1 + s];
+      const int rpart = row & 1, tpart = k & 1;
+      v = (rpart == 0) ? (tpart == 0 ? c.x : -c.y) : (tpart == 0 ? c.y : c.x);
+    }
+    afrag[((size_t)(j >> 1) * RT + t) * 64 + lane] = v;
+  }
+}
+
+// lexicographic compare of two d2-vectors: -1, 0, 1
+__device__ __forceinline__ int lexcmp(const int64_t* a, const int64_t* b, int n) {
+  for (int i = 0; i < n; ++i) {
+    if (a[i] < b[i]) return -1;
+    if (a[i] > b[i]) return 1;
+  }
+  return 0;
+}
+
+// Shared per-work-group scalars.
+struct WgState {
+  int sig, k, M_pl, nR, cur, i, p, m0, kstar, ncand, nacc, status, L, log2L, nU, flag;
+  int64_t off, samples;
+  double sigma;
+  uint64_t prefix;
+  int need;
+};
+
+// --------------------------------------------------- per-signal set-up -----
+// Planted modes: y = U^T w (eq. (35)) and the coefficient rows
+// C[j][0] = a_j, C[j][s] = a_j exp(2 pi i eps K_s y_{j,n_s}).
+template <typename T>
+__device__ void planted_setup(const KParams& kp, const KBatch& kb, char* slot, WgState& st) {
+  int64_t* ypl = reinterpret_cast<int64_t*>(slot + kp.lay.ypl);
+  cpx<T>* cc = ws_cpx<T>(slot, kp.lay.ccomp);
+  const int d = kp.d, d1 = kp.d1, d2 = kp.d2, S1 = kp.S1;
+  for (int j = threadIdx.x; j < st.M_pl; j += kWG) {
+    const int64_t* w = kb.freqs + (st.off + j) * d;
+    for (int q = 0; q < d2; ++q) {
+      int64_t y = 0, pw = 1;
+      for (int r = 0; r < d1; ++r) {
+        y += w[d1 * q + r] * pw;
+        pw *= kp.N;
+      }
+      ypl[(size_t)j * d2 + q] = y;
+    }
+    const cpx<double> a = cmk<double>(kb.coeffs[2 * (st.off + j)], kb.coeffs[2 * (st.off + j) + 1]);
+    cc[(size_t)j * S1] = cmk<T>((T)a.x, (T)a.y);
+    for (int s = 1; s < S1; ++s) {
+      int n0;
+      int64_t K;
+      shift_of(kp, s, &n0, &K);
+      const cpx<double> e = shift_phase(ypl[(size_t)j * d2 + n0], K, kp.NB);
+      const cpx<double> v = cmul(a, e);
+      cc[(size_t)j * S1 + s] = cmk<T>((T)v.x, (T)v.y);
+    }
+  }
+  if (threadIdx.x == 0 && (st.M_pl & 1)) {
+    for (int s = 0; s < S1; ++s) cc[(size_t)st.M_pl * S1 + s] = cmk<T>(0, 0);
+  }
+  __syncthreads();
+}
+
+// Registry rows of the exponential sum: C[2 P0 + e][s] = -a_e E_e[s].
+template <typename T>
+__device__ void registry_rows(const KParams& kp, char* slot, WgState& st, int P0) {
+  cpx<T>* cc = ws_cpx<T>(slot, kp.lay.ccomp);
+  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[st.cur]);
+  const double2* rE = reinterpret_cast<const double2*>(slot + kp.lay.rE[st.cur]);
+  const int S1 = kp.S1, S = kp.S;
+  const int base = 2 * P0;
+  for (int q = threadIdx.x; q < st.nR * S1; q += kWG) {
+    const int e = q / S1, s = q - e * S1;
+    const cpx<double> a = cmk<double>(-ra[e].x, -ra[e].y);
+    cpx<double> v = a;
+    if (s > 0) v = cmul(a, cmk<double>(rE[(size_t)e * S + s - 1].x, rE[(size_t)e * S + s - 1].y));
+    cc[(size_t)(base + e) * S1 + s] = cmk<T>((T)v.x, (T)v.y);
+  }
+  if (threadIdx.x == 0 && (st.nR & 1)) {
+    for (int s = 0; s < S1; ++s) cc[(size_t)(base + st.nR) * S1 + s] = cmk<T>(0, 0);
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ sampling ----
+// Line sampler for round st.i with prime st.p along axis st.m0 (0-based):
+// writes V[s][h] for all sets.  Planted rows [0, 2 P0), registry rows
+// [2 P0, 2 P0 + 2 ceil(nR/2)).
+template <typename T, int RT>
+__device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, WgState& st,
+                             int P0, char* lds, cpx<T>* V, int vstride) {
+  const int p = st.p, m0 = st.m0, d2 = kp.d2;
+  const int PR = (st.nR + 1) / 2;
+  const int npairs = P0 + PR;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
+  int* rr = reinterpret_cast<int*>(lds + (size_t)kp.p_max * sizeof(cpx<T>));
+  const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
+  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
+  for (int x = threadIdx.x; x < p; x += kWG) {
+    double c, s;
+    expipi(2.0 * (double)x / (double)p, &c, &s);  // omega_p^x = exp(2 pi i x / p)
+    tw[x] = cmk<T>((T)c, (T)s);
+  }
+  for (int j = threadIdx.x; j < 2 * npairs; j += kWG) {
+    int r = 0;
+    if (j < st.M_pl) {
+      r = (int)pmod64(ypl[(size_t)j * d2 + m0], p);
+    } else if (j >= 2 * P0 && j - 2 * P0 < st.nR) {
+      r = (int)pmod64(ry[(size_t)(j - 2 * P0) * d2 + m0], p);
+    }
+    rr[j] = r;
+  }
+  __syncthreads();
+  if constexpr (sizeof(T) == 4) {
+    const float* af = reinterpret_cast<const float*>(slot + kp.lay.afrag);
+    constexpr int NT = (RT == 1) ? 16 : (RT == 2 || RT == 3) ? 8 : (RT == 4) ? 6 : (RT <= 6) ? 4 : 3;
+    expsum_mfma<RT, NT>(af, rr, (const cpx<float>*)tw, npairs, p, kp.S1, (cpx<float>*)V, vstride);
+  } else {
+    const cpx<double>* cc = reinterpret_cast<const cpx<double>*>(slot + kp.lay.ccomp);
+    expsum_valu_f64(cc, rr, (const cpx<double>*)tw, 2 * npairs, p, kp.S1, (cpx<double>*)V,
+                    vstride);
+  }
+  __syncthreads();
+  add_noise<T>(V, vstride, p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
+  __syncthreads();
+}
+
+// Prepare the exponential-sum operands of the registry for this round.
+template <typename T>
+__device__ void registry_operands(const KParams& kp, char* slot, WgState& st, int P0) {
+  registry_rows<T>(kp, slot, st, P0);
+  if constexpr (sizeof(T) == 4) {
+    const int PR = (st.nR + 1) / 2;
+    scatter_afrag(kp, ws_cpx<float>(slot, kp.lay.ccomp),
+                  reinterpret_cast<float*>(slot + kp.lay.afrag), 2 * P0, 2 * (P0 + PR));
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------- DFTs ------
+template <typename T>
+__device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds, cpx<T>* V,
+                          int vstride, int nsets) {
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
+  cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
+  cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
+  const cpx<T>* twL = reinterpret_cast<const cpx<T>*>(kp.twL);
+  bluestein_setup<T>(st.p, st.L, st.log2L, chirp, bhat, buf, twL, kp.L_max);
+  for (int s = 0; s < nsets; ++s)
+    bluestein_dft<T>(V + (size_t)s * vstride, st.p, st.L, st.log2L, chirp, bhat, buf, twL,
+                     kp.L_max);
+}
+
+// ------------------------------------------------ top-k* selection ---------
+// Candidates: buckets with |F_0[h]|/p >= eta, and among them the k* largest
+// |F_0| (ties by ascending h), written in ascending h to cand[].
+template <typename T>
+__device__ void select_round(const KParams& kp, char* slot, WgState& st, char* lds,
+                             const cpx<T>* F0, int* sh_part) {
+  const int p = st.p;
+  uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
+  int* flag = reinterpret_cast<int*>(lds + (size_t)kp.p_max * 8);
+  int* hist = flag + kp.p_max;  // 256 bins
+  int* cand = reinterpret_cast<int*>(slot + kp.lay.cand);
+  const double thr = kp.eta * (double)p;
+  int cnt = 0;
+  for (int h = threadIdx.x; h < p; h += kWG) {
+    const double mag = hypot((double)F0[h].x, (double)F0[h].y);
+    const int pass = (mag >= thr) ? 1 : 0;
+    uint64_t key;
+    if constexpr (sizeof(T) == 4) {
+      key = (uint64_t)__float_as_uint((float)mag);
+    } else {
+      key = (uint64_t)__double_as_longlong(mag);
+    }
+    keys[h] = pass ? key : 0ull;
+    flag[h] = pass;
+    cnt += pass;
+  }
+  cnt = block_sum(cnt, sh_part);
+  if (cnt > st.kstar) {
+    // radix select of the k*-th largest key among the passing buckets
+    if (threadIdx.x == 0) {
+      st.prefix = 0ull;
+      st.need = st.kstar;
+    }
+    __syncthreads();
+    for (int pass = 7; pass >= 0; --pass) {
+      const int shift = pass * 8;
+      for (int b = threadIdx.x; b < 256; b += kWG) hist[b] = 0;
+      __syncthreads();
+      const uint64_t himask = (pass == 7) ? 0ull : ~((1ull << (shift + 8)) - 1ull);
+      const uint64_t prefix = st.prefix;
+      for (int h = threadIdx.x; h < p; h += kWG) {
+        if (flag[h] && ((keys[h] ^ prefix) & himask) == 0ull)
+          atomicAdd(&hist[(int)((keys[h] >> shift) & 255ull)], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int cum = 0, need = st.need;
+        for (int b = 255; b >= 0; --b) {
+          if (cum + hist[b] >= need) {
+            st.prefix = prefix | ((uint64_t)b << shift);
+            st.need = need - cum;
+            break;
+          }
+          cum += hist[b];
+        }
+      }
+      __syncthreads();
+    }
+    const uint64_t T_ = st.prefix;
+    const int take = st.need;
+    // rank among keys equal to the threshold, by ascending h
+    for (int h = threadIdx.x; h < p; h += kWG) flag[h] = (flag[h] && keys[h] == T_) ? 1 : 0;
+    __syncthreads();
+    block_exscan(flag, p, sh_part);
+    for (int h = threadIdx.x; h < p; h += kWG) {
+      const bool eq = (keys[h] == T_) && keys[h] != 0ull;
+      const bool sel = (keys[h] > T_) || (eq && flag[h] < take);
+      flag[h] = sel ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  const int n = block_exscan(flag, p, sh_part);
+  // flag now holds the output position of each selected h; recompute selection
+  for (int h = threadIdx.x; h < p; h += kWG) {
+    const int pos = flag[h];
+    const int nxt = (h + 1 < p) ? flag[h + 1] : n;
+    if (nxt > pos) cand[pos] = h;
+  }
+  if (threadIdx.x == 0) st.ncand = n;
+  __syncthreads();
+}
+
+// ------------------------------------------- collision test and decode ------
+// eq. (42): | |F_s[h]| / |F_0[h]| - 1 | < tau (+ tau_noise sqrt(p) / |F_0[h]|)
+// for every shifted set; eq. (41): y_n = Arg(F_n / F_0) / (2 pi eps), refined
+// by the K eps ladder; a = F_0[h] / p.  FP64 throughout.
+template <typename T>
+__device__ void decode_round(const KParams& kp, char* slot, WgState& st, const cpx<T>* V,
+                             int vstride, int* acc_list, int* sh_part) {
+  const int* cand = reinterpret_cast<const int*>(slot + kp.lay.cand);
+  int64_t* acc_y = reinterpret_cast<int64_t*>(slot + kp.lay.acc_y);
+  double2* acc_a = reinterpret_cast<double2*>(slot + kp.lay.acc_a);
+  const int p = st.p, d2 = kp.d2, S = kp.S;
+  const int64_t NB = kp.NB;
+  const double NBd = (double)NB;
+  int64_t lo = 0, hi = 0;
+  {
+    int64_t Ssum = 0, pw = 1;
+    for (int r = 0; r < kp.d1; ++r) {
+      Ssum += pw;
+      pw *= kp.N;
+    }
+    lo = -(kp.N / 2) * Ssum;
+    hi = (kp.N / 2 - 1) * Ssum;
+  }
+  for (int c = threadIdx.x; c < st.ncand; c += kWG) {
+    const int h = cand[c];
+    const double f0x = (double)V[h].x, f0y = (double)V[h].y;
+    const double absF0 = hypot(f0x, f0y);
+    double thr = kp.tau;
+    if (kp.tau_noise > 0.0) thr += kp.tau_noise * sqrt((double)p) / absF0;
+    const double den = f0x * f0x + f0y * f0y;
+    bool ok = true;
+    for (int s = 1; s <= S && ok; ++s) {
+      const double fx = (double)V[(size_t)s * vstride + h].x;
+      const double fy = (double)V[(size_t)s * vstride + h].y;
+      const double rx = (fx * f0x + fy * f0y) / den, ry = (fy * f0x - fx * f0y) / den;
+      const double mag = hypot(rx, ry);
+      if (!(fabs(mag - 1.0) < thr)) ok = false;
+    }
+    int64_t* y = acc_y + (size_t)c * d2;
+    for (int n = 0; n < d2 && ok; ++n) {
+      const double fx = (double)V[(size_t)(n + 1) * vstride + h].x;
+      const double fy = (double)V[(size_t)(n + 1) * vstride + h].y;
+      const double rx = (fx * f0x + fy * f0y) / den, ry = (fy * f0x - fx * f0y) / den;
+      double th = atan2(ry, rx);
+      if (th >= M_PI) th = -M_PI;
+      const double yc_real = th * NBd / M_PI;
+      int64_t yn = llround(yc_real);
+      if (kp.ladder_K > 1) {
+        const int64_t K = kp.ladder_K;
+        const double gx = (double)V[(size_t)(d2 + n + 1) * vstride + h].x;
+        const double gy = (double)V[(size_t)(d2 + n + 1) * vstride + h].y;
+        const double sx = (gx * f0x + gy * f0y) / den, sy = (gy * f0x - gx * f0y) / den;
+        double thf = atan2(sy, sx);
+        if (thf >= M_PI) thf = -M_PI;
+        const int64_t q = pmod64(K * yn, 2 * NB);
+        double delta = thf - M_PI * (double)q / NBd;
+        delta = delta - 2.0 * M_PI * floor((delta + M_PI) / (2.0 * M_PI));
+        yn = yn + llround(delta * NBd / (M_PI * (double)K));
+        if (kp.robust && fabs(yc_real - (double)yn) > NBd / (4.0 * (double)K)) ok = false;
+      }
+      if (yn < lo || yn > hi) ok = false;
+      y[n] = yn;
+    }
+    if (ok && kp.robust && pmod64(y[st.m0], p) != h) ok = false;
+    acc_list[c] = ok ? 1 : 0;
+    acc_a[c] = make_double2(f0x / (double)p, f0y / (double)p);
+  }
+  __syncthreads();
+  const int n = block_exscan(acc_list, st.ncand, sh_part);
+  if (threadIdx.x == 0) st.nacc = n;
+  __syncthreads();
+}
+
+// ------------------------------------------------------ registry merge ------
+// R[y] += a for the accepted buckets (ascending h), then prune |a| < eta.
+// The registry is kept sorted by lexicographic y; the accepted entries are
+// sorted (stable) and merged by binary search.
+template <typename T>
+__device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* lds,
+                            int* sh_part) {
+  const int d2 = kp.d2, S = kp.S;
+  const int nC = st.ncand;
+  const MergeLds ml = merge_lds(kp.k_max, kp.cap);
+  int* accpos = reinterpret_cast<int*>(lds + ml.accpos);      // exscan of accept flags
+  int* ids = reinterpret_cast<int*>(lds + ml.ids);            // candidate index, sorted
+  int64_t* key0 = reinterpret_cast<int64_t*>(lds + ml.key0);  // first coordinate of y
+  int* runflag = reinterpret_cast<int*>(lds + ml.runflag);    // 1 matched run, 2 new run
+  int* runpos = reinterpret_cast<int*>(lds + ml.runpos);      // lower_bound in R
+  int* cnt = reinterpret_cast<int*>(lds + ml.cnt);            // new runs per position
+  int* matchrun = reinterpret_cast<int*>(lds + ml.matchrun);  // run updating entry e
+  int* keep = reinterpret_cast<int*>(lds + ml.keep);          // ranks, then prune flags
+  const int64_t* acc_y = reinterpret_cast<const int64_t*>(slot + kp.lay.acc_y);
+  const double2* acc_a = reinterpret_cast<const double2*>(slot + kp.lay.acc_a);
+  const int nA = st.nacc;
+  const int nR = st.nR;
+  const int cur = st.cur, nxt = cur ^ 1;
+  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[cur]);
+  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[cur]);
+  const double2* rE = reinterpret_cast<const double2*>(slot + kp.lay.rE[cur]);
+  int64_t* ry2 = reinterpret_cast<int64_t*>(slot + kp.lay.ry[nxt]);
+  double2* ra2 = reinterpret_cast<double2*>(slot + kp.lay.ra[nxt]);
+  double2* rE2 = reinterpret_cast<double2*>(slot + kp.lay.rE[nxt]);
+
+  // accepted candidate indices in ascending h
+  int N2 = 1;
+  while (N2 < nA) N2 <<= 1;
+  for (int c = threadIdx.x; c < nC; c += kWG) {
+    const int pos = accpos[c];
+    const int nextpos = (c + 1 < nC) ? accpos[c + 1] : nA;
+    if (nextpos > pos) {
+      ids[pos] = c;
+      key0[pos] = acc_y[(size_t)c * d2];
+    }
+  }
+  for (int q = nA + threadIdx.x; q < N2; q += kWG) {
+    ids[q] = 0x7fffffff;
+    key0[q] = INT64_MAX;
+  }
+  __syncthreads();
+  // bitonic sort by (y lexicographic, candidate index); padding sorts last
+  for (int size = 2; size <= N2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < N2 / 2; t += kWG) {
+        const int lo_i = 2 * t - (t & (stride - 1));
+        const int hi_i = lo_i + stride;
+        const bool asc = ((lo_i & size) == 0);
+        const int a = ids[lo_i], b = ids[hi_i];
+        int cmp;
+        if (key0[lo_i] != key0[hi_i]) {
+          cmp = key0[lo_i] < key0[hi_i] ? -1 : 1;
+        } else if (a == 0x7fffffff || b == 0x7fffffff) {
+          cmp = (a == b) ? 0 : (a < b ? -1 : 1);
+        } else {
+          cmp = lexcmp(acc_y + (size_t)a * d2, acc_y + (size_t)b * d2, d2);
+          if (cmp == 0) cmp = (a < b) ? -1 : (a > b ? 1 : 0);
+        }
+        if ((cmp > 0) == asc) {
+          ids[lo_i] = b;
+          ids[hi_i] = a;
+          const int64_t k0 = key0[lo_i];
+          key0[lo_i] = key0[hi_i];
+          key0[hi_i] = k0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // runs of equal y; lower_bound of each run in the registry
+  for (int e = threadIdx.x; e <= nR; e += kWG) cnt[e] = 0;
+  for (int e = threadIdx.x; e < nR; e += kWG) matchrun[e] = -1;
+  __syncthreads();
+  for (int u = threadIdx.x; u < nA; u += kWG) {
+    const int64_t* yu = acc_y + (size_t)ids[u] * d2;
+    const bool first = (u == 0) || lexcmp(acc_y + (size_t)ids[u - 1] * d2, yu, d2) != 0;
+    int flagv = 0, pos = 0;
+    if (first) {
+      int lo = 0, hi = nR;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lexcmp(ry + (size_t)mid * d2, yu, d2) < 0)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      pos = lo;
+      const bool matched = (pos < nR) && lexcmp(ry + (size_t)pos * d2, yu, d2) == 0;
+      if (matched) {
+        flagv = 1;
+        matchrun[pos] = u;
+      } else {
+        flagv = 2;
+        atomicAdd(&cnt[pos], 1);
+      }
+    }
+    runflag[u] = flagv;
+    runpos[u] = pos;
+  }
+  __syncthreads();
+  // unmatched ranks (reuse keep[] as scratch of nA ints)
+  for (int u = threadIdx.x; u < nA; u += kWG) keep[u] = (runflag[u] == 2) ? 1 : 0;
+  __syncthreads();
+  const int nU = block_exscan(keep, nA, sh_part);
+  // cnt -> exclusive scan over registry positions 0..nR
+  {
+    // cnt has nR + 1 entries; scan in place
+    block_exscan(cnt, nR + 1, sh_part);
+  }
+  // old entries move to e + #unmatched runs with pos <= e
+  for (int e = threadIdx.x; e < nR; e += kWG) {
+    // inclusive count: exclusive(e + 1) = sum_{x <= e}
+    const int incl = cnt[e + 1];
+    const int dst = e + incl;
+    for (int i = 0; i < d2; ++i) ry2[(size_t)dst * d2 + i] = ry[(size_t)e * d2 + i];
+    double ax = ra[e].x, ay = ra[e].y;
+    const int u0 = matchrun[e];
+    if (u0 >= 0) {
+      const int64_t* yu = acc_y + (size_t)ids[u0] * d2;
+      for (int u = u0; u < nA && lexcmp(acc_y + (size_t)ids[u] * d2, yu, d2) == 0; ++u) {
+        ax += acc_a[ids[u]].x;
+        ay += acc_a[ids[u]].y;
+      }
+    }
+    ra2[dst] = make_double2(ax, ay);
+    for (int s = 0; s < S; ++s) rE2[(size_t)dst * S + s] = rE[(size_t)e * S + s];
+  }
+  // new entries
+  for (int u = threadIdx.x; u < nA; u += kWG) {
+    if (runflag[u] != 2) continue;
+    const int dst = runpos[u] + keep[u];
+    const int64_t* yu = acc_y + (size_t)ids[u] * d2;
+    for (int i = 0; i < d2; ++i) ry2[(size_t)dst * d2 + i] = yu[i];
+    double ax = 0.0, ay = 0.0;
+    for (int v = u; v < nA && lexcmp(acc_y + (size_t)ids[v] * d2, yu, d2) == 0; ++v) {
+      ax += acc_a[ids[v]].x;
+      ay += acc_a[ids[v]].y;
+    }
+    ra2[dst] = make_double2(ax, ay);
+    for (int s = 1; s <= S; ++s) {
+      int n0;
+      int64_t K;
+      shift_of(kp, s, &n0, &K);
+      const cpx<double> e = shift_phase(yu[n0], K, kp.NB);
+      rE2[(size_t)dst * S + s - 1] = make_double2(e.x, e.y);
+    }
+  }
+  __syncthreads();
+  // prune |a| < eta (compact back into the other buffer only if needed)
+  const int nM = nR + nU;
+  int npr = 0;
+  for (int e = threadIdx.x; e < nM; e += kWG) {
+    const int k = (hypot(ra2[e].x, ra2[e].y) >= kp.eta) ? 1 : 0;
+    keep[e] = k;
+    npr += 1 - k;
+  }
+  npr = block_sum(npr, sh_part);
+  if (npr == 0) {
+    if (threadIdx.x == 0) {
+      st.cur = nxt;
+      st.nR = nM;
+    }
+  } else {
+    const int nK = block_exscan(keep, nM, sh_part);
+    int64_t* ry3 = reinterpret_cast<int64_t*>(slot + kp.lay.ry[cur]);
+    double2* ra3 = reinterpret_cast<double2*>(slot + kp.lay.ra[cur]);
+    double2* rE3 = reinterpret_cast<double2*>(slot + kp.lay.rE[cur]);
+    for (int e = threadIdx.x; e < nM; e += kWG) {
+      const int pos = keep[e];
+      const int nx = (e + 1 < nM) ? keep[e + 1] : nK;
+      if (nx > pos) {
+        for (int i = 0; i < d2; ++i) ry3[(size_t)pos * d2 + i] = ry2[(size_t)e * d2 + i];
+        ra3[pos] = ra2[e];
+        for (int s = 0; s < S; ++s) rE3[(size_t)pos * S + s] = rE2[(size_t)e * S + s];
+      }
+    }
+    if (threadIdx.x == 0) st.nR = nK;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------- output ------
+// Wrap y back to w with balanced base-N digits (inverse of eq. (35)) and
+// write the registry in lexicographic order of w.
+__device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgState& st,
+                                    char* lds) {
+  const int d = kp.d, d1 = kp.d1, d2 = kp.d2, nR = st.nR;
+  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
+  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[st.cur]);
+  int64_t* fo = ko.freqs + (size_t)st.sig * kp.k_max * d;
+  double* co = ko.coeffs + (size_t)st.sig * kp.k_max * 2;
+  const int nOut = min(nR, kp.k_max);
+  const int64_t half = kp.N / 2;
+  // entries in registry order first (lexicographic in y)
+  for (int e = threadIdx.x; e < nOut; e += kWG) {
+    for (int q = 0; q < d2; ++q) {
+      int64_t rest = ry[(size_t)e * d2 + q];
+      for (int r = 0; r < d1; ++r) {
+        const int64_t digit = pmod64(rest + half, kp.N) - half;
+        fo[(size_t)e * d + d1 * q + r] = digit;
+        rest = (rest - digit) / kp.N;
+      }
+    }
+  }
+  __syncthreads();
+  if (d1 > 1 && nOut > 1) {
+    // lexicographic order of w differs from that of y: rank and permute
+    int* rank = reinterpret_cast<int*>(lds);
+    for (int e = threadIdx.x; e < nOut; e += kWG) {
+      int rk = 0;
+      for (int f = 0; f < nOut; ++f)
+        if (lexcmp(fo + (size_t)f * d, fo + (size_t)e * d, d) < 0) ++rk;
+      rank[e] = rk;
+    }
+    __syncthreads();
+    // stash w of each entry in the candidate-decode area, then scatter
+    int64_t* tmp = reinterpret_cast<int64_t*>(slot + kp.lay.acc_y);  // k_max * d2 * 8 bytes
+    // acc_y is too small for d columns in general; permute column by column
+    for (int col = 0; col < d; ++col) {
+      for (int e = threadIdx.x; e < nOut; e += kWG) tmp[e] = fo[(size_t)e * d + col];
+      __syncthreads();
+      for (int e = threadIdx.x; e < nOut; e += kWG) fo[(size_t)rank[e] * d + col] = tmp[e];
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nOut; e += kWG) {
+      co[2 * rank[e]] = ra[e].x;
+      co[2 * rank[e] + 1] = ra[e].y;
+    }
+  } else {
+    for (int e = threadIdx.x; e < nOut; e += kWG) {
+      co[2 * e] = ra[e].x;
+      co[2 * e + 1] = ra[e].y;
+    }
+  }
+  for (int e = nOut + threadIdx.x; e < kp.k_max; e += kWG) {
+    for (int i = 0; i < d; ++i) fo[(size_t)e * d + i] = 0;
+    co[2 * e] = 0.0;
+    co[2 * e + 1] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    ko.k_found[st.sig] = nR;
+    ko.status[st.sig] = st.status;
+    if (ko.rounds) ko.rounds[st.sig] = st.i - 1;
+    if (ko.samples) ko.samples[st.sig] = st.samples;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------- the kernel ------
+template <typename T, int RT>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+recover_kernel(KParams kp, KBatch kb, KOut ko) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  __shared__ int sh_part[kWG];
+  char* slot = kp.ws + (size_t)blockIdx.x * kp.ws_slot;
+  cpx<T>* V = ws_cpx<T>(slot, kp.lay.V);
+  const int vstride = kp.vstride;
+  for (;;) {
+    if (threadIdx.x == 0) st.sig = atomicAdd(kp.queue, 1);
+    __syncthreads();
+    if (st.sig >= kb.B) break;
+    if (threadIdx.x == 0) {
+      const int sig = st.sig;
+      st.off = kb.mode_off[sig];
+      st.M_pl = (int)(kb.mode_off[sig + 1] - st.off);
+      st.k = kb.k[sig];
+      st.sigma = kb.sigma[sig];
+      st.nR = 0;
+      st.cur = 0;
+      st.i = 1;
+      st.samples = 0;
+      st.status = 0;
+      st.flag = 0;
+      if (st.M_pl > kp.k_max || st.M_pl < 0 || st.k < 1 || st.k > kp.k_max) st.flag = 1;
+    }
+    __syncthreads();
+    if (st.flag) {
+      if (threadIdx.x == 0) {
+        ko.k_found[st.sig] = 0;
+        ko.status[st.sig] = -1;  // SFFT_EINVAL
+        if (ko.rounds) ko.rounds[st.sig] = 0;
+        if (ko.samples) ko.samples[st.sig] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    planted_setup<T>(kp, kb, slot, st);
+    const int P0 = (st.M_pl + 1) / 2;
+    if constexpr (sizeof(T) == 4) {
+      scatter_afrag(kp, ws_cpx<float>(slot, kp.lay.ccomp),
+                    reinterpret_cast<float*>(slot + kp.lay.afrag), 0, 2 * P0);
+      __syncthreads();
+    }
+    while (st.nR < st.k && st.i <= kp.max_rounds) {
+      if (threadIdx.x == 0) {
+        st.kstar = st.k - st.nR;
+        st.p = prime_for_round(kp, st.kstar, st.i);
+        st.m0 = st.i % kp.d2;
+        if (st.p < 2 || st.p > kp.p_max) {
+          st.flag = 1;
+        } else {
+          int L = 1, lg = 0;
+          while (L < 2 * st.p - 1) {
+            L <<= 1;
+            ++lg;
+          }
+          st.L = L;
+          st.log2L = lg;
+        }
+      }
+      __syncthreads();
+      if (st.flag) {
+        if (threadIdx.x == 0) st.status = -2;  // SFFT_ERANGE
+        __syncthreads();
+        break;
+      }
+      registry_operands<T>(kp, slot, st, P0);
+      sample_round<T, RT>(kp, kb, slot, st, P0, lds, V, vstride);
+      dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
+      select_round<T>(kp, slot, st, lds, V, sh_part);
+      int* acc_list = reinterpret_cast<int*>(lds);
+      decode_round<T>(kp, slot, st, V, vstride, acc_list, sh_part);
+      merge_round<T>(kp, slot, st, lds, sh_part);
+      if (threadIdx.x == 0) {
+        st.samples += (int64_t)kp.S1 * st.p;
+        if (ko.trace) {
+          int32_t* tr = ko.trace + ((size_t)st.sig * kp.max_rounds + (st.i - 1)) * 8;
+          tr[0] = st.i;
+          tr[1] = st.kstar;
+          tr[2] = st.p;
+          tr[3] = st.m0 + 1;
+          tr[4] = st.ncand;
+          tr[5] = st.nacc;
+          tr[6] = st.nR;
+          tr[7] = 0;
+        }
+        st.i += 1;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && st.status == 0) st.status = (st.nR >= st.k) ? 0 : 1;
+    __syncthreads();
+    write_output(kp, ko, slot, st, lds);
+  }
+}
+
+// ----------------------------------------------- component: line sampler ----
+template <typename T, int RT>
+__global__ void __launch_bounds__(kWG) sample_kernel(KParams kp, KBatch kb, int round, int p,
+                                                     int m, const int64_t* res_off,
+                                                     const int64_t* res_y, const double* res_c,
+                                                     void* Vvoid) {
+  cpx<T>* Vout = reinterpret_cast<cpx<T>*>(Vvoid);
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  char* slot = kp.ws + (size_t)blockIdx.x * kp.ws_slot;
+  for (int sig = blockIdx.x; sig < kb.B; sig += gridDim.x) {
+    if (threadIdx.x == 0) {
+      st.sig = sig;
+      st.off = kb.mode_off[sig];
+      st.M_pl = min((int)(kb.mode_off[sig + 1] - st.off), kp.k_max);
+      st.sigma = kb.sigma[sig];
+      st.cur = 0;
+      st.i = round;
+      st.p = p;
+      st.m0 = m - 1;
+      int nres = 0;
+      if (res_off) nres = (int)(res_off[sig + 1] - res_off[sig]);
+      st.nR = max(0, min(nres, kp.cap));
+    }
+    __syncthreads();
+    planted_setup<T>(kp, kb, slot, st);
+    const int P0 = (st.M_pl + 1) / 2;
+    // copy the caller's residual modes into registry buffer 0
+    if (res_off) {
+      int64_t* ry = reinterpret_cast<int64_t*>(slot + kp.lay.ry[0]);
+      double2* ra = reinterpret_cast<double2*>(slot + kp.lay.ra[0]);
+      double2* rE = reinterpret_cast<double2*>(slot + kp.lay.rE[0]);
+      const int64_t r0 = res_off[sig];
+      for (int e = threadIdx.x; e < st.nR; e += kWG) {
+        for (int q = 0; q < kp.d2; ++q) ry[(size_t)e * kp.d2 + q] = res_y[(r0 + e) * kp.d2 + q];
+        ra[e] = make_double2(res_c[2 * (r0 + e)], res_c[2 * (r0 + e) + 1]);
+        for (int s = 1; s <= kp.S; ++s) {
+          int n0;
+          int64_t K;
+          shift_of(kp, s, &n0, &K);
+          const cpx<double> e2 = shift_phase(res_y[(r0 + e) * kp.d2 + n0], K, kp.NB);
+          rE[(size_t)e * kp.S + s - 1] = make_double2(e2.x, e2.y);
+        }
+      }
+      __syncthreads();
+    }
+    if constexpr (sizeof(T) == 4) {
+      scatter_afrag(kp, ws_cpx<float>(slot, kp.lay.ccomp),
+                    reinterpret_cast<float*>(slot + kp.lay.afrag), 0, 2 * P0);
+      __syncthreads();
+    }
+    registry_operands<T>(kp, slot, st, P0);
+    sample_round<T, RT>(kp, kb, slot, st, P0, lds, Vout + (size_t)sig * kp.S1 * p, p);
+  }
+}
+
+// ----------------------------------------------------- component: DFT ------
+template <typename T>
+__global__ void __launch_bounds__(kWG) dft_kernel(KParams kp, cpx<T>* data, int count, int p) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  char* slot = kp.ws + (size_t)blockIdx.x * kp.ws_slot;
+  if (threadIdx.x == 0) {
+    int L = 1, lg = 0;
+    while (L < 2 * p - 1) {
+      L <<= 1;
+      ++lg;
+    }
+    st.p = p;
+    st.L = L;
+    st.log2L = lg;
+  }
+  __syncthreads();
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
+  cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
+  cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
+  const cpx<T>* twL = reinterpret_cast<const cpx<T>*>(kp.twL);
+  bluestein_setup<T>(p, st.L, st.log2L, chirp, bhat, buf, twL, kp.L_max);
+  for (int q = blockIdx.x; q < count; q += gridDim.x)
+    bluestein_dft<T>(data + (size_t)q * p, p, st.L, st.log2L, chirp, bhat, buf, twL, kp.L_max);
+}
+
+__global__ void zero_queue_kernel(int* q) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
+}
+
+// ------------------------------------------------------------ launchers -----
+int launch_zero_queue(const KParams& kp, void* stream) {
+  hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, kp.queue);
+  return (int)hipGetLastError();
+}
+
+#define SFFT_RT_DISPATCH(KERNEL, ...)                                              \
+  switch (kp.precision == 1 ? kp.RT : 0) {                                        \
+    case 1: hipLaunchKernelGGL((KERNEL<float, 1>), __VA_ARGS__); break;           \
+    case 2: hipLaunchKernelGGL((KERNEL<float, 2>), __VA_ARGS__); break;           \
+    case 3: hipLaunchKernelGGL((KERNEL<float, 3>), __VA_ARGS__); break;           \
+    case 4: hipLaunchKernelGGL((KERNEL<float, 4>), __VA_ARGS__); break;           \
+    case 5: hipLaunchKernelGGL((KERNEL<float, 5>), __VA_ARGS__); break;           \
+    case 6: hipLaunchKernelGGL((KERNEL<float, 6>), __VA_ARGS__); break;           \
+    case 7: hipLaunchKernelGGL((KERNEL<float, 7>), __VA_ARGS__); break;           \
+    case 8: hipLaunchKernelGGL((KERNEL<float, 8>), __VA_ARGS__); break;           \
+    default: hipLaunchKernelGGL((KERNEL<double, 0>), __VA_ARGS__); break;         \
+  }
+
+int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream) {
+  SFFT_RT_DISPATCH(recover_kernel, dim3(grid), dim3(kWG), kp.lds_bytes, (hipStream_t)stream, kp,
+                   kb, ko);
+  return (int)hipGetLastError();
+}
+
+int launch_sample_lines(const KParams& kp, const KBatch& kb, int round, int p, int m,
+                        const int64_t* res_off, const int64_t* res_y, const double* res_c,
+                        void* V, void* stream) {
+  const int grid = min(kb.B, kp.n_slots);
+  // V is passed as void* and typed inside the kernel by its precision
+  SFFT_RT_DISPATCH(sample_kernel, dim3(grid), dim3(kWG), kp.lds_bytes, (hipStream_t)stream, kp,
+                   kb, round, p, m, res_off, res_y, res_c, V);
+  return (int)hipGetLastError();
+}
+
+int launch_dft(const KParams& kp, void* data, int count, int p, void* stream) {
+  const int grid = min(count, kp.n_slots);
+  if (kp.precision == 1) {
+    hipLaunchKernelGGL(dft_kernel<float>, dim3(grid), dim3(kWG), kp.lds_bytes,
+                       (hipStream_t)stream, kp, (cpx<float>*)data, count, p);
+  } else {
+    hipLaunchKernelGGL(dft_kernel<double>, dim3(grid), dim3(kWG), kp.lds_bytes,
+                       (hipStream_t)stream, kp, (cpx<double>*)data, count, p);
+  }
+  return (int)hipGetLastError();
+}
+
+int set_kernel_lds_limits(int lds_bytes) {
+  hipError_t e = hipSuccess;
+  const void* fns[] = {
+      (const void*)recover_kernel<float, 1>, (const void*)recover_kernel<float, 2>,
+      (const void*)recover_kernel<float, 3>, (const void*)recover_kernel<float, 4>,
+      (const void*)recover_kernel<float, 5>, (const void*)recover_kernel<float, 6>,
+      (const void*)recover_kernel<float, 7>, (const void*)recover_kernel<float, 8>,
+      (const void*)recover_kernel<double, 0>, (const void*)sample_kernel<float, 1>,
+      (const void*)sample_kernel<float, 2>,  (const void*)sample_kernel<float, 3>,
+      (const void*)sample_kernel<float, 4>,  (const void*)sample_kernel<float, 5>,
+      (const void*)sample_kernel<float, 6>,  (const void*)sample_kernel<float, 7>,
+      (const void*)sample_kernel<float, 8>,  (const void*)sample_kernel<double, 0>,
+      (const void*)dft_kernel<float>,        (const void*)dft_kernel<double>};
+  for (const void* f : fns) {
+    hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (r != hipSuccess) e = r;
+  }
+  return (int)e;
+}
+
+}  // namespace sfft

@@ -1,0 +1,290 @@
+"""Python binding of libsfft (ctypes).  Argument marshalling only.
+
+The names mirror the C ABI of include/sfft.h: sfft_plan_create,
+sfft_plan_destroy, sfft_recover, sfft_sample_lines, sfft_dft,
+sfft_plan_max_prime, sfft_plan_num_sets, sfft_last_error, sfft_version.
+PyTorch provides device memory and the current stream; every step of the
+recovery runs in the HIP kernels of libsfft.so.  Loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfft.so")
+
+SFFT_OK, SFFT_NOT_CONVERGED = 0, 1
+SFFT_EINVAL, SFFT_ERANGE, SFFT_ENOMEM, SFFT_EDEVICE = -1, -2, -3, -4
+SFFT_PRIME_PAPER, SFFT_PRIME_SMOOTH = 0, 1
+SFFT_FP64, SFFT_FP32 = 0, 1
+SFFT_CLS_PLAIN = 0
+SFFT_TRACE_W = 8
+
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ERANGE", -3: "ENOMEM",
+                -4: "EDEVICE"}
+
+
+class sfft_params(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("d1", ctypes.c_int32), ("N", ctypes.c_int64),
+        ("k_max", ctypes.c_int32), ("c", ctypes.c_double), ("prime_rule", ctypes.c_int32),
+        ("p_min", ctypes.c_int32), ("ladder_K", ctypes.c_int32), ("tau", ctypes.c_double),
+        ("tau_noise", ctypes.c_double), ("eta", ctypes.c_double),
+        ("max_rounds", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("robust", ctypes.c_int32), ("classifier", ctypes.c_int32),
+    ]
+
+
+class sfft_signal_batch(ctypes.Structure):
+    _fields_ = [
+        ("B", ctypes.c_int32), ("mode_off", ctypes.c_void_p), ("freqs", ctypes.c_void_p),
+        ("coeffs", ctypes.c_void_p), ("k", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class sfft_outputs(ctypes.Structure):
+    _fields_ = [
+        ("freqs", ctypes.c_void_p), ("coeffs", ctypes.c_void_p), ("k_found", ctypes.c_void_p),
+        ("status", ctypes.c_void_p), ("rounds", ctypes.c_void_p), ("samples", ctypes.c_void_p),
+        ("trace", ctypes.c_void_p),
+    ]
+
+
+class SfftError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libsfft.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.sfft_plan_create.argtypes = [ctypes.POINTER(sfft_params), i32, ctypes.POINTER(vp)]
+        L.sfft_plan_create.restype = i32
+        L.sfft_plan_destroy.argtypes = [vp]
+        L.sfft_plan_destroy.restype = i32
+        L.sfft_recover.argtypes = [vp, ctypes.POINTER(sfft_signal_batch),
+                                   ctypes.POINTER(sfft_outputs), vp]
+        L.sfft_recover.restype = i32
+        L.sfft_sample_lines.argtypes = [vp, ctypes.POINTER(sfft_signal_batch), i32, i32, i32,
+                                        vp, vp, vp, vp, vp]
+        L.sfft_sample_lines.restype = i32
+        L.sfft_dft.argtypes = [vp, vp, i32, i32, vp]
+        L.sfft_dft.restype = i32
+        L.sfft_plan_max_prime.argtypes = [vp]
+        L.sfft_plan_max_prime.restype = i32
+        L.sfft_plan_num_sets.argtypes = [vp]
+        L.sfft_plan_num_sets.restype = i32
+        L.sfft_last_error.argtypes = []
+        L.sfft_last_error.restype = ctypes.c_char_p
+        L.sfft_version.argtypes = []
+        L.sfft_version.restype = i32
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/sfft.h."""
+    hdr = os.path.join(os.path.dirname(_HERE), "include", "sfft.h")
+    text = open(hdr).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\*]+\s+)+\**(sfft_\w+)\s*\(", text, re.M)))
+
+
+def sfft_last_error() -> str:
+    return lib().sfft_last_error().decode()
+
+
+def sfft_version() -> int:
+    return int(lib().sfft_version())
+
+
+def _check(st: int, where: str):
+    if st != SFFT_OK:
+        raise SfftError(st, where, sfft_last_error())
+
+
+@dataclass
+class Params:
+    """Mirror of sfft_params with the paper's defaults (c = 5, one eps shift per axis)."""
+    d: int
+    N: int
+    k_max: int
+    d1: int = 1
+    c: float = 5.0
+    prime_rule: int = SFFT_PRIME_PAPER
+    p_min: int = 0
+    ladder_K: int = 1
+    tau: float = 0.0
+    tau_noise: float = 0.0
+    eta: float = 1e-3
+    max_rounds: int = 64
+    precision: int = SFFT_FP32
+    robust: int = 0
+    classifier: int = SFFT_CLS_PLAIN
+
+    def to_c(self) -> sfft_params:
+        return sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
+                           self.p_min, self.ladder_K, self.tau, self.tau_noise, self.eta,
+                           self.max_rounds, self.precision, self.robust, self.classifier)
+
+
+class Plan:
+    def __init__(self, handle: int, params: Params, max_batch: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.params = params
+        self.max_batch = max_batch
+
+    @property
+    def max_prime(self) -> int:
+        return sfft_plan_max_prime(self)
+
+    @property
+    def num_sets(self) -> int:
+        return sfft_plan_num_sets(self)
+
+    def close(self):
+        if self.handle:
+            sfft_plan_destroy(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sfft_plan_create(params: Params, max_batch: int = 1) -> Plan:
+    h = ctypes.c_void_p()
+    p = params.to_c()
+    _check(lib().sfft_plan_create(ctypes.byref(p), int(max_batch), ctypes.byref(h)),
+           "sfft_plan_create")
+    return Plan(h.value, params, max_batch)
+
+
+def sfft_plan_destroy(plan: Plan):
+    if plan.handle:
+        _check(lib().sfft_plan_destroy(plan.handle), "sfft_plan_destroy")
+        plan.handle = ctypes.c_void_p()
+
+
+def sfft_plan_max_prime(plan: Plan) -> int:
+    return int(lib().sfft_plan_max_prime(plan.handle))
+
+
+def sfft_plan_num_sets(plan: Plan) -> int:
+    return int(lib().sfft_plan_num_sets(plan.handle))
+
+
+# ------------------------------------------------------------- device data --
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else stream
+
+
+class DeviceBatch:
+    """Device copies of a planted batch (workloads.PlantedBatch or equivalent arrays)."""
+
+    def __init__(self, freqs, coeffs, mode_off, k, sigma, seed: int, device="cuda"):
+        torch = _torch()
+        c = np.asarray(coeffs, dtype=np.complex128)
+        self.freqs = torch.as_tensor(np.ascontiguousarray(freqs, dtype=np.int64), device=device)
+        self.coeffs = torch.as_tensor(np.ascontiguousarray(np.stack([c.real, c.imag], -1)),
+                                      device=device)
+        self.mode_off = torch.as_tensor(np.asarray(mode_off, dtype=np.int64), device=device)
+        self.k = torch.as_tensor(np.asarray(k, dtype=np.int32), device=device)
+        self.sigma = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
+        self.seed = int(seed)
+        self.B = int(self.k.shape[0])
+
+    @classmethod
+    def from_planted(cls, pb, device="cuda"):
+        return cls(pb.freqs, pb.coeffs, pb.mode_off, pb.k, pb.sigma, pb.seed, device)
+
+    def to_c(self) -> sfft_signal_batch:
+        return sfft_signal_batch(self.B, _ptr(self.mode_off), _ptr(self.freqs),
+                                 _ptr(self.coeffs), _ptr(self.k), _ptr(self.sigma),
+                                 self.seed & 0xFFFFFFFFFFFFFFFF)
+
+
+def alloc_outputs(plan: Plan, B: int, trace: bool = True, device="cuda") -> dict:
+    torch = _torch()
+    P = plan.params
+    out = dict(
+        freqs=torch.zeros((B, P.k_max, P.d), dtype=torch.int64, device=device),
+        coeffs=torch.zeros((B, P.k_max, 2), dtype=torch.float64, device=device),
+        k_found=torch.zeros(B, dtype=torch.int32, device=device),
+        status=torch.zeros(B, dtype=torch.int32, device=device),
+        rounds=torch.zeros(B, dtype=torch.int32, device=device),
+        samples=torch.zeros(B, dtype=torch.int64, device=device),
+        trace=(torch.zeros((B, P.max_rounds, SFFT_TRACE_W), dtype=torch.int32, device=device)
+               if trace else None),
+    )
+    return out
+
+
+def sfft_recover(plan: Plan, batch: DeviceBatch, out: dict | None = None, stream=None) -> dict:
+    if out is None:
+        out = alloc_outputs(plan, batch.B)
+    o = sfft_outputs(_ptr(out["freqs"]), _ptr(out["coeffs"]), _ptr(out["k_found"]),
+                     _ptr(out["status"]), _ptr(out.get("rounds")), _ptr(out.get("samples")),
+                     _ptr(out.get("trace")))
+    b = batch.to_c()
+    _check(lib().sfft_recover(plan.handle, ctypes.byref(b), ctypes.byref(o), _stream(stream)),
+           "sfft_recover")
+    return out
+
+
+def sfft_sample_lines(plan: Plan, batch: DeviceBatch, round_i: int, p: int, m: int,
+                      res_off=None, res_y=None, res_coeffs=None, V=None, stream=None):
+    """Samples of one round: complex tensor [B, S+1, p] of the plan's precision."""
+    torch = _torch()
+    S1 = plan.num_sets
+    if V is None:
+        dt = torch.complex64 if plan.params.precision == SFFT_FP32 else torch.complex128
+        V = torch.zeros((batch.B, S1, p), dtype=dt, device=batch.k.device)
+    b = batch.to_c()
+    _check(lib().sfft_sample_lines(plan.handle, ctypes.byref(b), int(round_i), int(p), int(m),
+                                   _ptr(res_off), _ptr(res_y), _ptr(res_coeffs), _ptr(V),
+                                   _stream(stream)), "sfft_sample_lines")
+    return V
+
+
+def sfft_dft(plan: Plan, data, stream=None):
+    """In-place DFT of each row of a contiguous complex tensor [count, p]."""
+    count, p = int(data.shape[0]), int(data.shape[1])
+    _check(lib().sfft_dft(plan.handle, _ptr(data), count, p, _stream(stream)), "sfft_dft")
+    return data
+
+
+def outputs_to_host(out: dict) -> dict:
+    """numpy copies; coefficients as complex128."""
+    h = {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+    h["coeffs"] = h["coeffs"][..., 0] + 1j * h["coeffs"][..., 1]
+    return h

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Component level: the line sampler (planted signal, noise and residual) and the
+prime-length DFT.  End to end: sfft_recover against oracle.multiphaseshift on
+the same seeded signals -- recovered integer frequencies bit-exact, statuses
+and per-round traces equal, coefficients within 1e-5 relative (FP32 path) or
+1e-9 (FP64 path).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24  # unit roundoff of FP32
+
+
+def _sfft():
+    from paper_1606_07407_amd import sfft
+    return sfft
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _params(cfg, k_max, precision=None):
+    sfft = _sfft()
+    prec = cfg["precision"] if precision is None else precision
+    return sfft.Params(d=cfg["d"], N=cfg["N"], k_max=k_max, d1=cfg["d1"], c=cfg["c"],
+                       p_min=cfg["p_min"], ladder_K=cfg["ladder_K"],
+                       tau=(cfg["tau"] or 0.0), eta=cfg["eta"], max_rounds=cfg.get("max_rounds", 64),
+                       precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64,
+                       robust=int(cfg["robust"]))
+
+
+def _oracle_params(cfg, k):
+    return oracle.Params(d=cfg["d"], N=cfg["N"], k=int(k), d1=cfg["d1"], c=cfg["c"],
+                         ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
+                         p_min=cfg["p_min"], robust=cfg["robust"],
+                         max_rounds=cfg.get("max_rounds", 64))
+
+
+# ------------------------------------------------------------ sampler -------
+
+SAMPLER_CASES = [
+    # name, config overrides, k, p, m, residual count
+    ("c1_fp64", "c1", {}, 8, 41, 2, 3),
+    ("e4_fp64", "e4", {}, 100, 503, 3, 20),
+    ("c2_fp32", "c2", {}, 256, 1283, 2, 40),
+    ("c3_fp32_ladder_noise", "c3b", {}, 200, 601, 4, 50),
+    ("c3_fp32_full_p", "c3b", {}, 1000, 3001, 2, 0),
+]
+
+
+@pytest.mark.parametrize("name,cname,over,k,p,m,nres", SAMPLER_CASES)
+def test_sampler_matches_oracle(name, cname, over, k, p, m, nres):
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config(cname, **over)
+    _say(f"[sampler] {name} k={k} p={p} m={m} nres={nres}")
+    B = 2
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], k, cfg["mag"],
+                                 cfg["sigma"])
+    plan = sfft.sfft_plan_create(_params(cfg, k), max_batch=B)
+    assert p <= plan.max_prime
+    db = sfft.DeviceBatch.from_planted(pb)
+    P = _oracle_params(cfg, k)
+    # residual: some planted modes with perturbed coefficients plus unrelated modes
+    rng = np.random.default_rng(7)
+    res_y, res_a, res_off = [], [], [0]
+    for b in range(B):
+        w, a = pb.signal(b)
+        y = oracle.unwrap(w, P.d1, P.N)
+        sel = rng.choice(k, size=min(nres, k), replace=False)
+        ys = y[sel].copy()
+        ys[::2, 0] = np.clip(ys[::2, 0] + 1, *oracle.y_range(P.N, P.d1))
+        res_y.append(ys)
+        res_a.append(a[sel] * 0.9)
+        res_off.append(res_off[-1] + len(sel))
+    RY = np.concatenate(res_y) if nres else np.zeros((0, P.d2), np.int64)
+    RA = np.concatenate(res_a) if nres else np.zeros(0, np.complex128)
+    dev = "cuda"
+    t_off = torch.as_tensor(np.array(res_off, np.int64), device=dev)
+    t_y = torch.as_tensor(np.ascontiguousarray(RY, np.int64), device=dev)
+    t_a = torch.as_tensor(np.ascontiguousarray(np.stack([RA.real, RA.imag], -1)), device=dev)
+    round_i = 3
+    V = sfft.sfft_sample_lines(plan, db, round_i, p, m, t_off if nres else None,
+                               t_y if nres else None, t_a if nres else None)
+    torch.cuda.synchronize()
+    V = V.cpu().numpy()
+    for b in range(B):
+        w, a = pb.signal(b)
+        lo, hi = res_off[b], res_off[b + 1]
+        ref = oracle.round_samples(w, a, P, p, m, round_i, RY[lo:hi], RA[lo:hi],
+                                   sigma=float(pb.sigma[b]), seed=pb.seed, signal=b)
+        err = np.abs(V[b] - ref).max()
+        M = len(a) + (hi - lo)
+        amax = max(np.abs(a).max(), np.abs(RA[lo:hi]).max() if hi > lo else 0.0)
+        tol = (1e-11 if cfg["precision"] == "fp64" else 8 * U32) * M * amax
+        if P.NB > 1e5 and cfg["precision"] == "fp64":
+            tol = 1e-9 * M * amax   # the oracle's own FP64 phase rounding at large t
+        _say(f"    signal {b}: max |V - oracle| = {err:.3e} (tol {tol:.3e})")
+        assert err <= tol
+    plan.close()
+
+
+# ---------------------------------------------------------------- DFT -------
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_dft_matches_numpy(prec):
+    import torch
+    sfft = _sfft()
+    params = sfft.Params(d=2, N=64, k_max=400 if prec == "fp32" else 200, c=5.0,
+                         precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64)
+    plan = sfft.sfft_plan_create(params, max_batch=4)
+    pmax = plan.max_prime
+    rng = np.random.default_rng(11)
+    for p in sorted({2, 3, 5, 13, 41, 127, 1283, pmax}):
+        _say(f"[dft] {prec} p={p}")
+        x = rng.normal(size=(5, p)) + 1j * rng.normal(size=(5, p))
+        dt = torch.complex64 if prec == "fp32" else torch.complex128
+        t = torch.as_tensor(x, dtype=dt, device="cuda").contiguous()
+        sfft.sfft_dft(plan, t)
+        torch.cuda.synchronize()
+        got = t.cpu().numpy()
+        ref = np.fft.fft(x, axis=-1)
+        L = 1 << int(math.ceil(math.log2(2 * p - 1)))
+        norm = np.sqrt((np.abs(x) ** 2).sum(axis=-1)).max()
+        u = U32 if prec == "fp32" else 2.0 ** -53
+        tol = 8 * u * math.log2(L) * norm
+        err = np.abs(got - ref).max()
+        _say(f"    max err {err:.3e} tol {tol:.3e}")
+        assert err <= tol
+    plan.close()
+
+
+# ------------------------------------------------------------ recover -------
+
+def _compare(cfg, pb, h, rel_tol, check_trace=True):
+    res = []
+    for b in range(pb.B):
+        w, a = pb.signal(b)
+        P = _oracle_params(cfg, pb.k[b])
+        ref = oracle.multiphaseshift(w, a, P, sigma=float(pb.sigma[b]), seed=pb.seed, signal=b)
+        kf = int(h["k_found"][b])
+        assert int(h["status"][b]) == ref.status, (b, h["status"][b], ref.status)
+        assert kf == ref.freqs.shape[0], (b, kf, ref.freqs.shape[0])
+        assert np.array_equal(h["freqs"][b, :kf], ref.freqs), b
+        assert not np.any(h["freqs"][b, kf:]) and not np.any(h["coeffs"][b, kf:])
+        if kf:
+            rel = (np.abs(h["coeffs"][b, :kf] - ref.coeffs) / np.abs(ref.coeffs)).max()
+            assert rel <= rel_tol, (b, rel)
+            res.append(rel)
+        assert int(h["rounds"][b]) == ref.rounds
+        assert int(h["samples"][b]) == ref.samples
+        if check_trace:
+            tr = h["trace"][b, :ref.rounds]
+            want = np.array([[t["i"], t["kstar"], t["p"], t["m"], t["n_cand"], t["n_acc"],
+                              t["n_R"], 0] for t in ref.trace])
+            assert np.array_equal(tr, want), (b, tr, want)
+    return max(res) if res else 0.0
+
+
+RECOVER_CASES = [
+    # name, config, overrides, B, k (int or (lo, hi)), coefficient tolerance
+    ("c1_fp64_d1", "c1", {}, 16, 8, 1e-9),
+    ("c1_fp64_d2", "c1", {"d1": 2}, 8, 8, 1e-9),
+    ("e4_fp64", "e4", {}, 2, 100, 1e-8),
+    ("c2_fp32", "c2", {}, 2, 256, 1e-5),
+    ("c2_fp32_single_mode", "c2", {}, 3, 1, 1e-5),
+    ("c3_fp32_noisy_small", "c3b", {}, 3, 150, 1e-5),
+    ("c3_fp32_uneven_k", "c3b", {}, 5, (20, 260), 1e-5),
+    ("c2_fp32_round_cap", "c2", {"max_rounds": 1}, 2, 256, 1e-5),
+    ("c1_fp64_round_cap", "c1", {"max_rounds": 1}, 4, 8, 1e-9),
+]
+
+
+@pytest.mark.parametrize("name,cname,over,B,k,tol", RECOVER_CASES)
+def test_recover_matches_oracle(name, cname, over, B, k, tol):
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config(cname, **over)
+    ks = workloads.planted.uneven_k(cfg["seed"], B, *k) if isinstance(k, tuple) else k
+    _say(f"[recover] {name} B={B} k={k}")
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], ks, cfg["mag"],
+                                 cfg["sigma"])
+    k_max = int(np.max(pb.k))
+    plan = sfft.sfft_plan_create(_params(cfg, k_max), max_batch=B)
+    out = sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb))
+    torch.cuda.synchronize()
+    h = sfft.outputs_to_host(out)
+    rel = _compare(cfg, pb, h, tol)
+    _say(f"    statuses {h['status'].tolist()} rounds {h['rounds'].tolist()} max rel {rel:.2e}")
+    plan.close()
+
+
+def test_recover_deterministic_and_reusable():
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config("c3b")
+    pb = workloads.planted_batch(cfg["seed"], 4, cfg["d"], cfg["N"], 100, cfg["mag"],
+                                 cfg["sigma"])
+    plan = sfft.sfft_plan_create(_params(cfg, 120), max_batch=8)
+    db = sfft.DeviceBatch.from_planted(pb)
+    o1 = sfft.outputs_to_host(sfft.sfft_recover(plan, db))
+    o2 = sfft.outputs_to_host(sfft.sfft_recover(plan, db))
+    torch.cuda.synchronize()
+    for key in ("freqs", "coeffs", "k_found", "status", "trace"):
+        assert np.array_equal(o1[key], o2[key]), key
+    plan.close()
