@@ -57,7 +57,6 @@ struct sfft_plan_s {
   int max_batch = 0;
   KParams kp;
   int32_t* d_primes = nullptr;
-  void* d_twL = nullptr;
   char* d_ws = nullptr;
   int* d_queue = nullptr;
 };
@@ -171,8 +170,9 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
 
   // LDS: the largest of the per-step carve-ups.
   size_t lds = 0;
-  lds = std::max(lds, (size_t)L * cs);                                    // DFT buffer
-  lds = std::max(lds, align16((size_t)kp.p_max * cs) + 4 * (size_t)kp.m_max);  // sampler
+  lds = std::max(lds, (size_t)L * cs + (size_t)kTwiddleEntries * cs);     // DFT buffer + twiddles
+  lds = std::max(lds, align16((size_t)kp.p_max * cs) + align16(4 * (size_t)(kp.m_max + 4)) +
+                          (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0));  // sampler
   lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
   lds = std::max(lds, merge_lds(kp.k_max, kp.cap).bytes);                // registry merge
   lds = std::max(lds, 4 * (size_t)kp.k_max);                             // decode / output
@@ -187,7 +187,8 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   const int d2 = kp.d2, S = kp.S, S1 = kp.S1;
   lay.ypl = o;   o = al256(o + 8 * (size_t)kp.k_max * d2);
   lay.ccomp = o; o = al256(o + cs * (size_t)(kp.m_max + 2) * S1);
-  lay.afrag = o; o = al256(o + (P.precision == SFFT_FP32 ? 4 * (size_t)kp.pairs_max * kp.RT * 64 : 0));
+  // slack: the sampler copies whole chunks of A fragments past npairs
+  lay.afrag = o; o = al256(o + (P.precision == SFFT_FP32 ? 4 * (size_t)(kp.pairs_max + kChunk + 2) * kp.RT * 64 : 0));
   for (int b = 0; b < 2; ++b) {
     lay.ry[b] = o; o = al256(o + 8 * (size_t)kp.cap * d2);
     lay.ra[b] = o; o = al256(o + 16 * (size_t)kp.cap);
@@ -221,24 +222,8 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   plan->device = dev;
   plan->max_batch = max_batch;
 
-  // twiddles exp(-2 pi i t / L) in the plan's precision
-  std::vector<double> tw(2 * (size_t)L);
-  for (int t = 0; t < L; ++t) {
-    const double ang = -2.0 * M_PI * (double)t / (double)L;
-    tw[2 * t] = std::cos(ang);
-    tw[2 * t + 1] = std::sin(ang);
-  }
-  std::vector<float> twf;
-  const void* tw_src = tw.data();
-  size_t tw_bytes = tw.size() * sizeof(double);
-  if (P.precision == SFFT_FP32) {
-    twf.assign(tw.begin(), tw.end());
-    tw_src = twf.data();
-    tw_bytes = twf.size() * sizeof(float);
-  }
   const size_t ws_bytes = (size_t)kp.n_slots * kp.ws_slot;
   if ((e = hipMalloc((void**)&plan->d_primes, primes.size() * sizeof(int32_t))) != hipSuccess ||
-      (e = hipMalloc(&plan->d_twL, tw_bytes)) != hipSuccess ||
       (e = hipMalloc((void**)&plan->d_ws, ws_bytes)) != hipSuccess ||
       (e = hipMalloc((void**)&plan->d_queue, 256)) != hipSuccess) {
     sfft_plan_destroy(plan);
@@ -247,7 +232,6 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   }
   if ((e = hipMemcpy(plan->d_primes, primes.data(), primes.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(plan->d_twL, tw_src, tw_bytes, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(plan->d_ws, 0, ws_bytes)) != hipSuccess ||
       (e = hipMemset(plan->d_queue, 0, 256)) != hipSuccess) {
     sfft_plan_destroy(plan);
@@ -260,7 +244,6 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   }
   kp.primes = plan->d_primes;
   kp.n_primes = (int)primes.size();
-  kp.twL = plan->d_twL;
   kp.ws = plan->d_ws;
   kp.queue = plan->d_queue;
   plan->kp = kp;
@@ -272,7 +255,6 @@ sfft_status sfft_plan_destroy(sfft_plan plan) {
   if (!plan) return SFFT_OK;
   (void)hipDeviceSynchronize();
   if (plan->d_primes) (void)hipFree(plan->d_primes);
-  if (plan->d_twL) (void)hipFree(plan->d_twL);
   if (plan->d_ws) (void)hipFree(plan->d_ws);
   if (plan->d_queue) (void)hipFree(plan->d_queue);
   delete plan;

@@ -166,13 +166,21 @@ __device__ __forceinline__ void butterfly(cpx<T>* x, bool inv) {
   }
 }
 
+// Twiddle exp(-2 pi i t / L) from the two LDS tables T1[i] = exp(-2 pi i 64 i / L),
+// T2[j] = exp(-2 pi i j / L): one complex product per lookup.
+template <typename T>
+__device__ __forceinline__ cpx<T> twiddle(const cpx<T>* T1, const cpx<T>* T2, int t) {
+  return cmul(T1[t >> kTwiddleBits], T2[t & ((1 << kTwiddleBits) - 1)]);
+}
+
 template <typename T, int R>
-__device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* __restrict__ twL,
-                              int tw_mul, bool inv) {
+__device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* T1, const cpx<T>* T2,
+                              bool inv) {
   constexpr int MAXV = MaxL<T>::value / kWG;
   constexpr int NQ = MAXV / R;
   cpx<T> v[MAXV];
   const int nitems = L / R;
+  const int tw_mul = L / (Ns * R);
   const int tid = threadIdx.x;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -182,11 +190,16 @@ __device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* __restri
       cpx<T> x[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = buf[j + r * nitems];
+      if (Ns > 1) {
+        // w^k, then its powers by multiplication
+        cpx<T> w1 = twiddle(T1, T2, k * tw_mul);
+        if (inv) w1.y = -w1.y;
+        cpx<T> wr = w1;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cpx<T> w = twL[r * k * tw_mul];
-        if (inv) w.y = -w.y;
-        x[r] = cmul(x[r], w);
+        for (int r = 1; r < R; ++r) {
+          x[r] = cmul(x[r], wr);
+          if (r + 1 < R) wr = cmul(wr, w1);
+        }
       }
       butterfly<T, R>(x, inv);
 #pragma unroll
@@ -207,30 +220,52 @@ __device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* __restri
   __syncthreads();
 }
 
-// Unnormalised power-of-two FFT of L <= MaxL<T> points in LDS, forward
-// (exp(-2 pi i ...)) or inverse (exp(+2 pi i ...)).  twL holds
-// exp(-2 pi i t / Lmax) for t < Lmax.
+// LDS twiddle tables for length L (T1: max(1, L/64) entries, T2: min(L, 64)).
 template <typename T>
-__device__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx<T>* __restrict__ twL, int Lmax,
+__device__ void twiddle_tables(int L, cpx<T>* T1, cpx<T>* T2) {
+  const int n1 = (L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1;
+  const int n2 = L < (1 << kTwiddleBits) ? L : (1 << kTwiddleBits);
+  for (int i = threadIdx.x; i < n1 + n2; i += kWG) {
+    const int t = (i < n1) ? (i << kTwiddleBits) : (i - n1);
+    double c, s;
+    expipi(-2.0 * (double)t / (double)L, &c, &s);
+    const cpx<T> w = cmk<T>((T)c, (T)s);
+    if (i < n1)
+      T1[i] = w;
+    else
+      T2[i - n1] = w;
+  }
+  __syncthreads();
+}
+
+// Unnormalised power-of-two FFT of L <= MaxL<T> points in LDS, forward
+// (exp(-2 pi i ...)) or inverse (exp(+2 pi i ...)), Stockham radix 4 with one
+// radix-2 pass when log2 L is odd.
+template <typename T>
+__device__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx<T>* T1, const cpx<T>* T2,
                         bool inv) {
   int Ns = 1;
   if (log2L & 1) {
-    stockham_pass<T, 2>(buf, L, Ns, twL, Lmax / 2, inv);
+    stockham_pass<T, 2>(buf, L, Ns, T1, T2, inv);
     Ns = 2;
   }
   while (Ns < L) {
-    stockham_pass<T, 4>(buf, L, Ns, twL, Lmax / (Ns * 4), inv);
+    stockham_pass<T, 4>(buf, L, Ns, T1, T2, inv);
     Ns *= 4;
   }
 }
 
 // Bluestein set-up for prime length p and power-of-two L >= 2p - 1:
 // chirp[n] = exp(-i pi (n^2 mod 2p) / p) and bhat = FFT_L(b),
-// b[n] = conj(chirp[n]) for |n| < p (wrapped mod L), 0 elsewhere.
+// b[n] = conj(chirp[n]) for |n| < p (wrapped mod L), 0 elsewhere.  Also
+// fills the LDS twiddle tables that follow the L-point buffer.
 template <typename T>
 __device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
-                                cpx<T>* buf, const cpx<T>* twL, int Lmax) {
+                                cpx<T>* buf) {
   const int tid = threadIdx.x;
+  cpx<T>* T1 = buf + L;
+  cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
+  twiddle_tables<T>(L, T1, T2);
   for (int n = tid; n < p; n += kWG) {
     const int64_t q = ((int64_t)n * n) % (2 * (int64_t)p);
     double c, s;
@@ -249,36 +284,40 @@ __device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* 
     buf[n] = v;
   }
   __syncthreads();
-  fft_lds<T>(buf, L, log2L, twL, Lmax, false);
+  fft_lds<T>(buf, L, log2L, T1, T2, false);
   for (int n = tid; n < L; n += kWG) bhat[n] = buf[n];
   __syncthreads();
 }
 
 // In-place DFT of one prime-length sequence x (global) via Bluestein:
-// X[k] = chirp[k] * IFFT_L(FFT_L(x . chirp) . bhat)[k] / L.
+// X[k] = chirp[k] * IFFT_L(FFT_L(x . chirp) . bhat)[k] / L.  Uses the LDS
+// twiddle tables written by bluestein_setup.
 template <typename T>
 __device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* chirp,
-                              const cpx<T>* bhat, cpx<T>* buf, const cpx<T>* twL, int Lmax) {
+                              const cpx<T>* bhat, cpx<T>* buf) {
   const int tid = threadIdx.x;
+  const cpx<T>* T1 = buf + L;
+  const cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
   for (int n = tid; n < L; n += kWG) buf[n] = (n < p) ? cmul(x[n], chirp[n]) : cmk<T>(0, 0);
   __syncthreads();
-  fft_lds<T>(buf, L, log2L, twL, Lmax, false);
+  fft_lds<T>(buf, L, log2L, T1, T2, false);
   for (int n = tid; n < L; n += kWG) buf[n] = cmul(buf[n], bhat[n]);
   __syncthreads();
-  fft_lds<T>(buf, L, log2L, twL, Lmax, true);
+  fft_lds<T>(buf, L, log2L, T1, T2, true);
   const T invL = (T)1 / (T)L;
   for (int n = tid; n < p; n += kWG) x[n] = cscale(cmul(buf[n], chirp[n]), invL);
   __syncthreads();
 }
 
 // ------------------------------------------------- exponential sums -------
-// (h * r) mod p for 0 <= h, r and h * r < 2^32, exactly.
-__device__ __forceinline__ int mulmod(uint32_t h, uint32_t r, int p, double inv_p) {
+// (h * r) mod p exactly, for h * r < 2^32 and p < 65536: the FP32 quotient
+// estimate is off by at most one, fixed by one step each way.
+__device__ __forceinline__ int mulmod(uint32_t h, uint32_t r, int p, float inv_p) {
   const uint32_t x = h * r;
-  int q = (int)((double)x * inv_p);
+  const int q = (int)((float)x * inv_p);
   int rem = (int)(x - (uint32_t)q * (uint32_t)p);
-  if (rem < 0) rem += p;
-  if (rem >= p) rem -= p;
+  rem += (rem < 0) ? p : 0;
+  rem -= (rem >= p) ? p : 0;
   return rem;
 }
 
@@ -291,64 +330,155 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // integer-reduced index.  As a real product, row 2s / 2s+1 hold Re / Im of set
 // s and K index 2j / 2j+1 hold Re / Im of mode j; it runs as
 // v_mfma_f32_16x16x4_f32 tiles: RT row tiles of 16 rows, NT column tiles of
-// 16 points per wave, two modes per K step.  `afrag` holds A in lane order
-// ([pair][RT][64]); `rr` (LDS) holds r_j; `tw` (LDS) holds omega_p^x.
+// 16 points per wave, two modes per K step.
+//
+// Operands: `afrag` (global) holds A in lane order ([pair][RT][64], readable
+// two pairs past npairs); `rr` (LDS) holds r_j, zero-padded two pairs past
+// npairs; `tw` (LDS) holds omega_p^x; `abuf` (LDS, 2 x (kChunk + 1) pairs)
+// stages A: the four waves share one A stream, copied cooperatively one chunk
+// ahead.  Each chunk buffer also holds the first pair of the next chunk so the
+// A fragments and twiddles of step pr + 1 can be read while the MFMAs of step
+// pr run.
 template <int RT, int NT>
 __device__ void expsum_mfma(const float* __restrict__ afrag, const int* rr,
-                            const cpx<float>* tw, int npairs, int p, int S1,
+                            const cpx<float>* tw, float* abuf, int npairs, int p, int S1,
                             cpx<float>* __restrict__ V, int vstride) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   constexpr int NWAVES = kWG / 64;
   constexpr int NCOL = 16 * NT;
+  constexpr int PAIR = RT * 64;                   // floats per pair
+  constexpr int BUF = (kChunk + 1) * PAIR;        // floats per chunk buffer
+  constexpr int CPY = (BUF + kWG - 1) / kWG;      // floats copied per thread per chunk
   const int ntiles = (p + NCOL - 1) / NCOL;
-  const double inv_p = 1.0 / (double)p;
+  const int passes = (ntiles + NWAVES - 1) / NWAVES;
+  const int nchunks = (npairs + kChunk - 1) / kChunk;
+  const float inv_p = 1.0f / (float)p;
   const int kk = lane >> 4;       // K row of the B fragment
   const int col = lane & 15;      // column (point) of the B fragment
   const int jsel = kk >> 1;       // which mode of the pair
   const int tpart = kk & 1;       // Re / Im of the twiddle
-  const float* twf = reinterpret_cast<const float*>(tw);
-  for (int tile = wave; tile < ntiles; tile += NWAVES) {
+  const float* twf = reinterpret_cast<const float*>(tw) + tpart;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int tile = pass * NWAVES + wave;
+    const bool active = tile < ntiles;
     const int hbase = tile * NCOL;
+    const uint32_t h0 = (uint32_t)(hbase + col);
     floatx4 acc[RT][NT];
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int u = 0; u < NT; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const uint32_t h0 = (uint32_t)(hbase + col);
-    for (int pr = 0; pr < npairs; ++pr) {
-      float a[RT];
+    // chunk 0 into buffer 0
 #pragma unroll
-      for (int t = 0; t < RT; ++t) a[t] = afrag[((size_t)pr * RT + t) * 64 + lane];
-      const uint32_t r = (uint32_t)rr[2 * pr + jsel];
-      int idx = mulmod(h0, r, p, inv_p);
-      const int step = mulmod(16u, r, p, inv_p);
+    for (int q = 0; q < CPY; ++q) {
+      const int e = threadIdx.x + q * kWG;
+      if (e < BUF) abuf[e] = afrag[e];
+    }
+    __syncthreads();
+    float a_cur[RT], b_cur[NT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) a_cur[t] = abuf[t * 64 + lane];
+    {
+      const uint32_t r0 = (uint32_t)rr[jsel];
+      int idx = mulmod(h0, r0, p, inv_p);
+      const int step = mulmod(16u, r0, p, inv_p);
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
-        const float b = twf[2 * idx + tpart];
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b, acc[t][u], 0, 0, 0);
+        b_cur[u] = twf[2 * idx];
         idx += step;
-        if (idx >= p) idx -= p;
+        idx -= (idx >= p) ? p : 0;
       }
+    }
+    for (int c = 0; c < nchunks; ++c) {
+      const float* ab = abuf + (c & 1) * BUF;
+      // next chunk's A, held in registers while this chunk computes
+      float stage[CPY];
+      if (c + 1 < nchunks) {
+        const float* src = afrag + (size_t)(c + 1) * kChunk * PAIR;
+#pragma unroll
+        for (int q = 0; q < CPY; ++q) {
+          const int e = threadIdx.x + q * kWG;
+          stage[q] = (e < BUF) ? src[e] : 0.f;
+        }
+      }
+      const int k1 = min(kChunk, npairs - c * kChunk);
+      if (active) {
+        for (int q = 0; q < k1; ++q) {
+          const int pr = c * kChunk + q;
+          // operands of step pr + 1: A from this chunk buffer, twiddles from LDS
+          float a_nxt[RT], b_nxt[NT];
+#pragma unroll
+          for (int t = 0; t < RT; ++t) a_nxt[t] = ab[(q + 1) * PAIR + t * 64 + lane];
+          {
+            const uint32_t rn = (uint32_t)rr[2 * (pr + 1) + jsel];
+            int idx = mulmod(h0, rn, p, inv_p);
+            const int step = mulmod(16u, rn, p, inv_p);
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+              b_nxt[u] = twf[2 * idx];
+              idx += step;
+              idx -= (idx >= p) ? p : 0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+              acc[t][u] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[t], b_cur[u], acc[t][u], 0, 0, 0);
+#pragma unroll
+          for (int t = 0; t < RT; ++t) a_cur[t] = a_nxt[t];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) b_cur[u] = b_nxt[u];
+        }
+      }
+      if (c + 1 < nchunks) {
+        float* dst = abuf + ((c + 1) & 1) * BUF;
+#pragma unroll
+        for (int q = 0; q < CPY; ++q) {
+          const int e = threadIdx.x + q * kWG;
+          if (e < BUF) dst[e] = stage[q];
+        }
+      }
+      __syncthreads();
     }
     // D layout: lane holds rows 4*(lane/16) + i (i = 0..3) of column lane%16;
     // rows 4*kk, 4*kk+1 are Re, Im of set 2*kk (+ 8 t), rows 4*kk+2, +3 of the next set.
+    if (active) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int s0 = 8 * t + 2 * kk;
+      for (int t = 0; t < RT; ++t) {
+        const int s0 = 8 * t + 2 * kk;
 #pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        const int h = hbase + 16 * u + col;
-        if (h < p) {
-          if (s0 < S1) V[(size_t)s0 * vstride + h] = cmk<float>(acc[t][u][0], acc[t][u][1]);
-          if (s0 + 1 < S1)
-            V[(size_t)(s0 + 1) * vstride + h] = cmk<float>(acc[t][u][2], acc[t][u][3]);
+        for (int u = 0; u < NT; ++u) {
+          const int h = hbase + 16 * u + col;
+          if (h < p) {
+            if (s0 < S1) V[(size_t)s0 * vstride + h] = cmk<float>(acc[t][u][0], acc[t][u][1]);
+            if (s0 + 1 < S1)
+              V[(size_t)(s0 + 1) * vstride + h] = cmk<float>(acc[t][u][2], acc[t][u][3]);
+          }
         }
       }
     }
   }
+}
+
+// Column tiles per wave for a round with prime p: the widest tile (best reuse
+// of each A fragment) that still gives every wave about the same number of
+// columns; a tile pass costs about 4 columns' worth of fixed overhead.
+__host__ __device__ inline int choose_nt(int p) {
+  int best = 8;
+  int best_cost = 1 << 30;
+  for (int nt = 8; nt >= 2; nt >>= 1) {
+    const int tiles = (p + 16 * nt - 1) / (16 * nt);
+    const int passes = (tiles + 3) / 4;
+    const int cost = passes * (16 * nt + 64);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = nt;
+    }
+  }
+  return best;
 }
 
 // Noise of the synthetic black box, added to every sample of the round.
@@ -370,7 +500,7 @@ __device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int S1, ui
 __device__ inline void expsum_valu_f64(const cpx<double>* __restrict__ C, const int* rr,
                                        const cpx<double>* tw, int M, int p, int S1,
                                        cpx<double>* __restrict__ V, int vstride) {
-  const double inv_p = 1.0 / (double)p;
+  const float inv_p = 1.0f / (float)p;
   for (int q = threadIdx.x; q < S1 * p; q += kWG) {
     const int s = q / p, h = q - s * p;
     cpx<double> acc = cmk<double>(0.0, 0.0);

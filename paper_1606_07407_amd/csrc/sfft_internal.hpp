@@ -11,6 +11,9 @@ constexpr int kWG = 256;          // threads per work-group (4 waves of 64)
 constexpr int kMaxD2 = 64;        // largest number of unwrapped coordinates
 constexpr int kMaxSets = 2 * kMaxD2 + 1;
 constexpr int kMaxRT = 8;         // MFMA row tiles: 2 (S+1) real rows <= 128
+constexpr int kChunk = 16;        // sampler: A-fragment pairs staged in LDS per chunk
+constexpr int kTwiddleBits = 6;   // DFT twiddles exp(-2 pi i t / L) = T1[t >> 6] * T2[t & 63]
+constexpr int kTwiddleEntries = 64 + 8192 / 64;  // LDS entries of T1 and T2 for L <= 8192
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -62,7 +65,6 @@ struct KParams {
   int p_max, L_max, log2_Lmax, vstride;
   const int32_t* primes;  // ascending primes usable by the prime rule, up to p_max
   int n_primes;
-  const void* twL;        // complex T [L_max]: exp(-2 pi i t / L_max)
   char* ws;               // slots back to back
   size_t ws_slot;
   WsLayout lay;

@@ -179,7 +179,9 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   const int PR = (st.nR + 1) / 2;
   const int npairs = P0 + PR;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
-  int* rr = reinterpret_cast<int*>(lds + (size_t)kp.p_max * sizeof(cpx<T>));
+  int* rr = reinterpret_cast<int*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
+  float* abuf = reinterpret_cast<float*>(reinterpret_cast<char*>(rr) +
+                                         align16(4 * (size_t)(kp.m_max + 4)));
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
   const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
   for (int x = threadIdx.x; x < p; x += kWG) {
@@ -187,7 +189,7 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     expipi(2.0 * (double)x / (double)p, &c, &s);  // omega_p^x = exp(2 pi i x / p)
     tw[x] = cmk<T>((T)c, (T)s);
   }
-  for (int j = threadIdx.x; j < 2 * npairs; j += kWG) {
+  for (int j = threadIdx.x; j < 2 * npairs + 4; j += kWG) {
     int r = 0;
     if (j < st.M_pl) {
       r = (int)pmod64(ypl[(size_t)j * d2 + m0], p);
@@ -199,8 +201,17 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   __syncthreads();
   if constexpr (sizeof(T) == 4) {
     const float* af = reinterpret_cast<const float*>(slot + kp.lay.afrag);
-    constexpr int NT = (RT == 1) ? 16 : (RT == 2 || RT == 3) ? 8 : (RT == 4) ? 6 : (RT <= 6) ? 4 : 3;
-    expsum_mfma<RT, NT>(af, rr, (const cpx<float>*)tw, npairs, p, kp.S1, (cpx<float>*)V, vstride);
+    // RT * NT accumulator tiles per wave: at most 24 (96 accumulator registers)
+    constexpr int NTMAX = (RT <= 3) ? 8 : (RT <= 6) ? 4 : 2;
+    const int nt = min(choose_nt(p), NTMAX);
+    const cpx<float>* twc = (const cpx<float>*)tw;
+    cpx<float>* Vf = (cpx<float>*)V;
+    if (nt >= 8 && NTMAX >= 8)
+      expsum_mfma<RT, (NTMAX >= 8 ? 8 : NTMAX)>(af, rr, twc, abuf, npairs, p, kp.S1, Vf, vstride);
+    else if (nt >= 4 && NTMAX >= 4)
+      expsum_mfma<RT, (NTMAX >= 4 ? 4 : NTMAX)>(af, rr, twc, abuf, npairs, p, kp.S1, Vf, vstride);
+    else
+      expsum_mfma<RT, 2>(af, rr, twc, abuf, npairs, p, kp.S1, Vf, vstride);
   } else {
     const cpx<double>* cc = reinterpret_cast<const cpx<double>*>(slot + kp.lay.ccomp);
     expsum_valu_f64(cc, rr, (const cpx<double>*)tw, 2 * npairs, p, kp.S1, (cpx<double>*)V,
@@ -230,11 +241,9 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
   cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
   cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
-  const cpx<T>* twL = reinterpret_cast<const cpx<T>*>(kp.twL);
-  bluestein_setup<T>(st.p, st.L, st.log2L, chirp, bhat, buf, twL, kp.L_max);
+  bluestein_setup<T>(st.p, st.L, st.log2L, chirp, bhat, buf);
   for (int s = 0; s < nsets; ++s)
-    bluestein_dft<T>(V + (size_t)s * vstride, st.p, st.L, st.log2L, chirp, bhat, buf, twL,
-                     kp.L_max);
+    bluestein_dft<T>(V + (size_t)s * vstride, st.p, st.L, st.log2L, chirp, bhat, buf);
 }
 
 // ------------------------------------------------ top-k* selection ---------
@@ -820,10 +829,9 @@ __global__ void __launch_bounds__(kWG) dft_kernel(KParams kp, cpx<T>* data, int 
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
   cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
   cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
-  const cpx<T>* twL = reinterpret_cast<const cpx<T>*>(kp.twL);
-  bluestein_setup<T>(p, st.L, st.log2L, chirp, bhat, buf, twL, kp.L_max);
+  bluestein_setup<T>(p, st.L, st.log2L, chirp, bhat, buf);
   for (int q = blockIdx.x; q < count; q += gridDim.x)
-    bluestein_dft<T>(data + (size_t)q * p, p, st.L, st.log2L, chirp, bhat, buf, twL, kp.L_max);
+    bluestein_dft<T>(data + (size_t)q * p, p, st.L, st.log2L, chirp, bhat, buf);
 }
 
 __global__ void zero_queue_kernel(int* q) {
