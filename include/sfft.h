@@ -74,8 +74,10 @@ typedef struct {
 /* A batch of synthetic black-box signals with planted spectra.  All pointers
  * are device pointers.  Signal b is sum_{j in [mode_off[b], mode_off[b+1])}
  * coeffs[j] exp(2 pi i freqs[j] . t) plus complex Gaussian noise of standard
- * deviation sigma[b] per sample (noise from Philox4x64-10, key (seed, b),
- * counter (h, sample set, round, 0); Box-Muller in FP64). */
+ * deviation sigma[b] per sample: Philox4x64-10 with key (seed, b) and counter
+ * (h / 2, sample set, round, 0), output words 0, 1 for even h and 2, 3 for odd
+ * h, Box-Muller on their top 53 bits (in FP64 on the FP64 path, in FP32 from
+ * the exact integer 1 - u1 on the FP32 path). */
 typedef struct {
   int32_t B;                /* number of signals, 1..max_batch                    */
   const int64_t* mode_off;  /* [B + 1], mode_off[0] = 0, non-decreasing           */

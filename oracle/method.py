@@ -65,7 +65,8 @@ READINGS = {
     "R18": "Noise ladder (not in the paper): with K > 1 each axis also gets a K eps shift; "
            "y = y_c + round(wrap(theta_K - 2 pi K eps y_c) / (2 pi K eps)).",
     "R19": "Noise (not in the paper): sigma/sqrt(2) (g1 + i g2) per sample from "
-           "Philox4x64-10, key (seed, signal), counter (h, set, round, 0).",
+           "Philox4x64-10, key (seed, signal), counter (h // 2, set, round, 0), output "
+           "words 0, 1 for even h and 2, 3 for odd h.",
 }
 
 STATUS_OK = 0

@@ -13,8 +13,9 @@ and the key bumped by the Weyl constants (W0, W1) between rounds.
 
 Noise of one sample (Box-Muller in FP64):
     key     = (seed, signal index)
-    counter = (h, sample set, round, 0)
-    u1, u2  = top 53 bits of output words 0 and 1, times 2^-53
+    counter = (floor(h / 2), sample set, round, 0)
+    u1, u2  = top 53 bits of output words 0 and 1 (even h) or 2 and 3 (odd h),
+              times 2^-53
     g       = sqrt(-2 ln(1 - u1)) * (cos 2 pi u2 + i sin 2 pi u2)
     noise   = sigma / sqrt(2) * g        (so E|noise|^2 = sigma^2)
 """
@@ -71,10 +72,13 @@ def sample_noise(seed: int, signal: int, round_i: int, s: int, h: np.ndarray,
     n = h.shape
     z = np.zeros(n, dtype=np.uint64)
     out = philox4x64_10(
-        (h, np.full(n, s, np.uint64), np.full(n, round_i, np.uint64), z),
+        (h >> np.uint64(1), np.full(n, s, np.uint64), np.full(n, round_i, np.uint64), z),
         (np.full(n, np.uint64(seed & 0xFFFFFFFFFFFFFFFF)), np.full(n, signal, np.uint64)))
-    u1 = (out[0] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
-    u2 = (out[1] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    odd = (h & np.uint64(1)).astype(bool)
+    w0 = np.where(odd, out[2], out[0])
+    w1 = np.where(odd, out[3], out[1])
+    u1 = (w0 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u2 = (w1 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
     rad = np.sqrt(-2.0 * np.log1p(-u1))
     g = rad * (np.cos(2.0 * np.pi * u2) + 1j * np.sin(2.0 * np.pi * u2))
     return (sigma / np.sqrt(2.0)) * g

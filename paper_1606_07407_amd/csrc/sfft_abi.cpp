@@ -163,6 +163,8 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
     return fail(SFFT_ERANGE,
                 "largest prime %d needs a %d-point Bluestein DFT; the LDS DFT holds %d points",
                 kp.p_max, L, maxL);
+  if (P.precision == SFFT_FP32 && kp.p_max > 4096)
+    return fail(SFFT_ERANGE, "largest prime %d exceeds 4096 (FP32 sampler index range)", kp.p_max);
   kp.L_max = L;
   kp.log2_Lmax = lg;
   kp.vstride = kp.p_max;
@@ -171,7 +173,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   // LDS: the largest of the per-step carve-ups.
   size_t lds = 0;
   lds = std::max(lds, (size_t)L * cs + (size_t)kTwiddleEntries * cs);     // DFT buffer + twiddles
-  lds = std::max(lds, align16((size_t)kp.p_max * cs) + align16(4 * (size_t)(kp.m_max + 4)) +
+  lds = std::max(lds, align16((size_t)kp.p_max * cs) + 2 * align16(4 * (size_t)(kp.m_max + 4)) +
                           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0));  // sampler
   lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
   lds = std::max(lds, merge_lds(kp.k_max, kp.cap).bytes);                // registry merge

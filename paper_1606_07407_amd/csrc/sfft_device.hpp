@@ -81,20 +81,44 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
   }
 }
 
-// Complex Gaussian noise of one sample: sigma/sqrt(2) * sqrt(-2 ln(1-u1)) e^{2 pi i u2}
-// with u1, u2 the top 53 bits of Philox output words 0 and 1.
-__device__ __forceinline__ cpx<double> sample_noise(uint64_t seed, uint64_t signal,
-                                                    uint64_t round, uint64_t set, uint64_t h,
-                                                    double sigma) {
-  uint64_t c[4] = {h, set, round, 0ull};
+// Complex Gaussian noise of the sample pair (2 hp, 2 hp + 1): one Philox block,
+// key (seed, signal), counter (hp, set, round, 0); words 0, 1 give the even
+// sample, words 2, 3 the odd one.  For words (w0, w1): u1, u2 = top 53 bits
+// times 2^-53, g = sqrt(-2 ln(1 - u1)) e^{2 pi i u2}, noise = sigma/sqrt(2) g.
+// The FP64 path evaluates Box-Muller in FP64; the FP32 path in FP32 from the
+// exact integer 2^53 (1 - u1), which keeps the tail (u1 near 1) finite and
+// accurate to FP32 rounding.
+__device__ __forceinline__ void noise_pair64(uint64_t seed, uint64_t signal, uint64_t round,
+                                             uint64_t set, uint64_t hp, double sigma,
+                                             cpx<double>* n0, cpx<double>* n1) {
+  uint64_t c[4] = {hp, set, round, 0ull};
   philox4x64_10(c, seed, signal);
-  const double u1 = (double)(c[0] >> 11) * 0x1p-53;
-  const double u2 = (double)(c[1] >> 11) * 0x1p-53;
-  const double rad = sqrt(-2.0 * log1p(-u1));
-  const double ang = 2.0 * M_PI * u2;
-  const double gx = rad * cos(ang), gy = rad * sin(ang);
   const double sc = sigma / sqrt(2.0);
-  return cmk<double>(sc * gx, sc * gy);
+  for (int e = 0; e < 2; ++e) {
+    const double u1 = (double)(c[2 * e] >> 11) * 0x1p-53;
+    const double u2 = (double)(c[2 * e + 1] >> 11) * 0x1p-53;
+    const double rad = sqrt(-2.0 * log1p(-u1));
+    const double ang = 2.0 * M_PI * u2;
+    const cpx<double> g = cmk<double>(sc * (rad * cos(ang)), sc * (rad * sin(ang)));
+    if (e == 0) *n0 = g; else *n1 = g;
+  }
+}
+
+__device__ __forceinline__ void noise_pair32(uint64_t seed, uint64_t signal, uint64_t round,
+                                             uint64_t set, uint64_t hp, float sigma,
+                                             cpx<float>* n0, cpx<float>* n1) {
+  uint64_t c[4] = {hp, set, round, 0ull};
+  philox4x64_10(c, seed, signal);
+  const float sc = sigma * 0.70710678118654752440f;
+  for (int e = 0; e < 2; ++e) {
+    const float v = (float)((1ull << 53) - (c[2 * e] >> 11)) * 0x1p-53f;  // 1 - u1 in (0, 1]
+    const float u2 = (float)(c[2 * e + 1] >> 11) * 0x1p-53f;
+    const float rad = sqrtf(-2.0f * logf(v));
+    float sn, cs;
+    sincospif(2.0f * u2, &sn, &cs);
+    const cpx<float> g = cmk<float>(sc * (rad * cs), sc * (rad * sn));
+    if (e == 0) *n0 = g; else *n1 = g;
+  }
 }
 
 // ------------------------------------------------------------ block scans --
@@ -143,9 +167,47 @@ __device__ inline int block_sum(int v, int* part) {
 // item j (k = j mod Ns) reads x_r = buf[j + r L/R], multiplies by
 // w^{r k} with w = exp(-+2 pi i / (Ns R)), applies the R-point DFT and writes
 // buf[(j - k) R + k + r Ns].  All items are read before any is written.
+// 4-point DFT of x[0], x[s], x[2s], x[3s] in place (forward: exp(-2 pi i / 4)).
+template <typename T>
+__device__ __forceinline__ void dft4(cpx<T>* x, int s, bool inv) {
+  const cpx<T> t0 = cadd(x[0], x[2 * s]), t1 = csub(x[0], x[2 * s]);
+  const cpx<T> t2 = cadd(x[s], x[3 * s]), t3 = csub(x[s], x[3 * s]);
+  const cpx<T> mi_t3 = cmk<T>(t3.y, -t3.x);  // -i * t3
+  x[0] = cadd(t0, t2);
+  x[2 * s] = csub(t0, t2);
+  x[s] = inv ? csub(t1, mi_t3) : cadd(t1, mi_t3);
+  x[3 * s] = inv ? cadd(t1, mi_t3) : csub(t1, mi_t3);
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void butterfly(cpx<T>* x, bool inv) {
-  if (R == 2) {
+  if (R == 16) {
+    // n = 4 n1 + n2, k = k1 + 4 k2: DFT4 over n1, twiddle W16^{n2 k1}, DFT4 over n2.
+    for (int n2 = 0; n2 < 4; ++n2) dft4<T>(x + n2, 4, inv);
+    // x[4 k1 + n2] now holds Y[n2][k1]; multiply by W16^{n2 k1}
+    const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;
+    const T h = (T)0.70710678118654752440;
+    const cpx<T> w[10] = {cmk<T>(1, 0),  cmk<T>(c1, -s1), cmk<T>(h, -h),  cmk<T>(s1, -c1),
+                          cmk<T>(0, -1), cmk<T>(-s1, -c1), cmk<T>(-h, -h), cmk<T>(-c1, -s1),
+                          cmk<T>(-1, 0), cmk<T>(-c1, s1)};
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+      for (int n2 = 1; n2 < 4; ++n2) {
+        cpx<T> tw = w[n2 * k1];
+        if (inv) tw.y = -tw.y;
+        x[4 * k1 + n2] = cmul(x[4 * k1 + n2], tw);
+      }
+    for (int k1 = 0; k1 < 4; ++k1) dft4<T>(x + 4 * k1, 1, inv);
+    // x[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 block
+    cpx<T> y[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) y[i] = x[i];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) x[k1 + 4 * k2] = y[4 * k1 + k2];
+  } else if (R == 2) {
     const cpx<T> a = x[0], b = x[1];
     x[0] = cadd(a, b);
     x[1] = csub(a, b);
@@ -191,14 +253,37 @@ __device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* T1, cons
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = buf[j + r * nitems];
       if (Ns > 1) {
-        // w^k, then its powers by multiplication
-        cpx<T> w1 = twiddle(T1, T2, k * tw_mul);
-        if (inv) w1.y = -w1.y;
-        cpx<T> wr = w1;
+        if (R == 16) {
+          // w^r = w^{4a} w^b with w^{4a} from the table (a = 1, 2) or one product,
+          // w^b from at most two products: every factor within a few ulp
+          cpx<T> w1 = twiddle(T1, T2, k * tw_mul);
+          cpx<T> w4 = twiddle(T1, T2, 4 * k * tw_mul);
+          cpx<T> w8 = twiddle(T1, T2, 8 * k * tw_mul);
+          if (inv) {
+            w1.y = -w1.y;
+            w4.y = -w4.y;
+            w8.y = -w8.y;
+          }
+          const cpx<T> w2 = cmul(w1, w1), w3 = cmul(w2, w1), w12 = cmul(w8, w4);
+          const cpx<T> lo[4] = {cmk<T>(1, 0), w1, w2, w3};
+          const cpx<T> hi[4] = {cmk<T>(1, 0), w4, w8, w12};
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          x[r] = cmul(x[r], wr);
-          if (r + 1 < R) wr = cmul(wr, w1);
+          for (int r = 1; r < R; ++r) {
+            const cpx<T> wr = (r & 3) == 0 ? hi[r >> 2]
+                              : (r >> 2) == 0 ? lo[r & 3]
+                                              : cmul(hi[r >> 2], lo[r & 3]);
+            x[r] = cmul(x[r], wr);
+          }
+        } else {
+          // w^k, then its powers by multiplication
+          cpx<T> w1 = twiddle(T1, T2, k * tw_mul);
+          if (inv) w1.y = -w1.y;
+          cpx<T> wr = w1;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            x[r] = cmul(x[r], wr);
+            if (r + 1 < R) wr = cmul(wr, w1);
+          }
         }
       }
       butterfly<T, R>(x, inv);
@@ -244,14 +329,20 @@ __device__ void twiddle_tables(int L, cpx<T>* T1, cpx<T>* T2) {
 template <typename T>
 __device__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx<T>* T1, const cpx<T>* T2,
                         bool inv) {
+  // log2 L = 4 a + b: radix-2 / radix-4 passes for b, then a radix-16 passes
   int Ns = 1;
-  if (log2L & 1) {
+  const int b = log2L & 3;
+  if (b & 1) {
     stockham_pass<T, 2>(buf, L, Ns, T1, T2, inv);
     Ns = 2;
   }
-  while (Ns < L) {
+  if (b & 2) {
     stockham_pass<T, 4>(buf, L, Ns, T1, T2, inv);
     Ns *= 4;
+  }
+  while (Ns < L) {
+    stockham_pass<T, 16>(buf, L, Ns, T1, T2, inv);
+    Ns *= 16;
   }
 }
 
@@ -310,14 +401,27 @@ __device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* 
 }
 
 // ------------------------------------------------- exponential sums -------
-// (h * r) mod p exactly, for h * r < 2^32 and p < 65536: the FP32 quotient
-// estimate is off by at most one, fixed by one step each way.
+// (h * r) mod p exactly, for h, r < 2^16 with h * r < 2^32: the FP32 quotient
+// estimate is off by at most one, fixed branch-free in each direction
+// (unsigned minimum picks the in-range candidate).
 __device__ __forceinline__ int mulmod(uint32_t h, uint32_t r, int p, float inv_p) {
   const uint32_t x = h * r;
-  const int q = (int)((float)x * inv_p);
-  int rem = (int)(x - (uint32_t)q * (uint32_t)p);
-  rem += (rem < 0) ? p : 0;
-  rem -= (rem >= p) ? p : 0;
+  const uint32_t q = (uint32_t)(int)((float)x * inv_p);
+  const uint32_t up = (uint32_t)p;
+  uint32_t rem = x - q * up;
+  rem = min(rem, rem + up);  // rem was negative
+  rem = min(rem, rem - up);  // rem was >= p
+  return (int)rem;
+}
+
+// The same with 24-bit multiplies, for h, r, p < 2^13 (the FP32 sampler keeps
+// p <= 4096 and h < p + 128), so h * r < 2^26 and the quotient is off by at most one.
+__device__ __forceinline__ uint32_t mulmod24(uint32_t h, uint32_t r, uint32_t p, float inv_p) {
+  const uint32_t x = __umul24(h, r);
+  const uint32_t q = (uint32_t)(int)((float)x * inv_p);
+  uint32_t rem = x - __umul24(q, p);
+  rem = min(rem, rem + p);
+  rem = min(rem, rem - p);
   return rem;
 }
 
@@ -334,13 +438,30 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 //
 // Operands: `afrag` (global) holds A in lane order ([pair][RT][64], readable
 // two pairs past npairs); `rr` (LDS) holds r_j, zero-padded two pairs past
-// npairs; `tw` (LDS) holds omega_p^x; `abuf` (LDS, 2 x (kChunk + 1) pairs)
+// npairs, and `rs` the column steps (16 r_j) mod p; `tw` (LDS) holds omega_p^x;
+// `abuf` (LDS, 2 x (kChunk + 1) pairs)
 // stages A: the four waves share one A stream, copied cooperatively one chunk
 // ahead.  Each chunk buffer also holds the first pair of the next chunk so the
 // A fragments and twiddles of step pr + 1 can be read while the MFMAs of step
 // pr run.
+// B fragments of one K step: omega_p^{((h0 + 16 u) r) mod p} (Re or Im part
+// selected by the caller's table offset) for the NT column tiles of a lane;
+// `step` = (16 r) mod p.
+template <int NT>
+__device__ __forceinline__ void twiddle_column(const float* twf, uint32_t h0, uint32_t r,
+                                               uint32_t step, uint32_t p, float inv_p,
+                                               float* b) {
+  uint32_t idx = mulmod24(h0, r, p, inv_p);
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    b[u] = twf[2 * idx];
+    const uint32_t t = idx + step;
+    idx = min(t, t - p);  // t - p wraps above t when t < p
+  }
+}
+
 template <int RT, int NT>
-__device__ void expsum_mfma(const float* __restrict__ afrag, const int* rr,
+__device__ void expsum_mfma(const float* __restrict__ afrag, const int* rr, const int* rs,
                             const cpx<float>* tw, float* abuf, int npairs, int p, int S1,
                             cpx<float>* __restrict__ V, int vstride) {
   const int lane = threadIdx.x & 63;
@@ -379,17 +500,10 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const int* rr,
     float a_cur[RT], b_cur[NT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) a_cur[t] = abuf[t * 64 + lane];
-    {
-      const uint32_t r0 = (uint32_t)rr[jsel];
-      int idx = mulmod(h0, r0, p, inv_p);
-      const int step = mulmod(16u, r0, p, inv_p);
-#pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        b_cur[u] = twf[2 * idx];
-        idx += step;
-        idx -= (idx >= p) ? p : 0;
-      }
-    }
+    const uint32_t up = (uint32_t)p;
+    twiddle_column<NT>(twf, h0, (uint32_t)rr[jsel], (uint32_t)rs[jsel], up, inv_p, b_cur);
+    uint32_t r1 = (uint32_t)rr[2 + jsel];       // residue of step pr + 1
+    uint32_t s1 = (uint32_t)rs[2 + jsel];
     for (int c = 0; c < nchunks; ++c) {
       const float* ab = abuf + (c & 1) * BUF;
       // next chunk's A, held in registers while this chunk computes
@@ -406,31 +520,33 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const int* rr,
       if (active) {
         for (int q = 0; q < k1; ++q) {
           const int pr = c * kChunk + q;
-          // operands of step pr + 1: A from this chunk buffer, twiddles from LDS
+          // operands of step pr + 1 (A from this chunk buffer, twiddles from the
+          // residue loaded one step earlier) and the residue of step pr + 2
           float a_nxt[RT], b_nxt[NT];
+          twiddle_column<NT>(twf, h0, r1, s1, up, inv_p, b_nxt);
 #pragma unroll
           for (int t = 0; t < RT; ++t) a_nxt[t] = ab[(q + 1) * PAIR + t * 64 + lane];
-          {
-            const uint32_t rn = (uint32_t)rr[2 * (pr + 1) + jsel];
-            int idx = mulmod(h0, rn, p, inv_p);
-            const int step = mulmod(16u, rn, p, inv_p);
-#pragma unroll
-            for (int u = 0; u < NT; ++u) {
-              b_nxt[u] = twf[2 * idx];
-              idx += step;
-              idx -= (idx >= p) ? p : 0;
-            }
-          }
+          const uint32_t r2 = (uint32_t)rr[2 * (pr + 2) + jsel];
+          const uint32_t s2 = (uint32_t)rs[2 * (pr + 2) + jsel];
 #pragma unroll
           for (int u = 0; u < NT; ++u)
 #pragma unroll
             for (int t = 0; t < RT; ++t)
               acc[t][u] =
                   __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[t], b_cur[u], acc[t][u], 0, 0, 0);
+          // interleave: LDS reads and index arithmetic between the MFMAs
+#pragma unroll
+          for (int g = 0; g < RT * NT; ++g) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // three VALU
+          }
 #pragma unroll
           for (int t = 0; t < RT; ++t) a_cur[t] = a_nxt[t];
 #pragma unroll
           for (int u = 0; u < NT; ++u) b_cur[u] = b_nxt[u];
+          r1 = r2;
+          s1 = s2;
         }
       }
       if (c + 1 < nchunks) {
@@ -481,18 +597,28 @@ __host__ __device__ inline int choose_nt(int p) {
   return best;
 }
 
-// Noise of the synthetic black box, added to every sample of the round.
+// Noise of the synthetic black box, added to every sample of the round (one
+// Philox block per pair of points).
 template <typename T>
 __device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int S1, uint64_t seed,
                           uint64_t signal, int round, double sigma) {
   if (!(sigma > 0.0)) return;
-  for (int q = threadIdx.x; q < S1 * p; q += kWG) {
-    const int s = q / p, h = q - s * p;
-    const cpx<double> n = sample_noise(seed, signal, (uint64_t)round, (uint64_t)s, (uint64_t)h,
-                                       sigma);
-    cpx<T>& v = V[(size_t)s * vstride + h];
-    v.x = (T)((double)v.x + n.x);
-    v.y = (T)((double)v.y + n.y);
+  const int np2 = (p + 1) / 2;
+  for (int q = threadIdx.x; q < S1 * np2; q += kWG) {
+    const int s = q / np2, hp = q - s * np2;
+    cpx<T>* v = V + (size_t)s * vstride + 2 * hp;
+    if constexpr (sizeof(T) == 4) {
+      cpx<float> n0, n1;
+      noise_pair32(seed, signal, (uint64_t)round, (uint64_t)s, (uint64_t)hp, (float)sigma, &n0,
+                   &n1);
+      v[0] = cadd(v[0], n0);
+      if (2 * hp + 1 < p) v[1] = cadd(v[1], n1);
+    } else {
+      cpx<double> n0, n1;
+      noise_pair64(seed, signal, (uint64_t)round, (uint64_t)s, (uint64_t)hp, sigma, &n0, &n1);
+      v[0] = cadd(v[0], n0);
+      if (2 * hp + 1 < p) v[1] = cadd(v[1], n1);
+    }
   }
 }
 

@@ -180,7 +180,9 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   const int npairs = P0 + PR;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
   int* rr = reinterpret_cast<int*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
-  float* abuf = reinterpret_cast<float*>(reinterpret_cast<char*>(rr) +
+  int* rs = reinterpret_cast<int*>(reinterpret_cast<char*>(rr) +
+                                   align16(4 * (size_t)(kp.m_max + 4)));
+  float* abuf = reinterpret_cast<float*>(reinterpret_cast<char*>(rs) +
                                          align16(4 * (size_t)(kp.m_max + 4)));
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
   const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
@@ -197,6 +199,7 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
       r = (int)pmod64(ry[(size_t)(j - 2 * P0) * d2 + m0], p);
     }
     rr[j] = r;
+    rs[j] = (int)((16 * (int64_t)r) % p);
   }
   __syncthreads();
   if constexpr (sizeof(T) == 4) {
@@ -207,11 +210,11 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     const cpx<float>* twc = (const cpx<float>*)tw;
     cpx<float>* Vf = (cpx<float>*)V;
     if (nt >= 8 && NTMAX >= 8)
-      expsum_mfma<RT, (NTMAX >= 8 ? 8 : NTMAX)>(af, rr, twc, abuf, npairs, p, kp.S1, Vf, vstride);
+      expsum_mfma<RT, (NTMAX >= 8 ? 8 : NTMAX)>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride);
     else if (nt >= 4 && NTMAX >= 4)
-      expsum_mfma<RT, (NTMAX >= 4 ? 4 : NTMAX)>(af, rr, twc, abuf, npairs, p, kp.S1, Vf, vstride);
+      expsum_mfma<RT, (NTMAX >= 4 ? 4 : NTMAX)>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride);
     else
-      expsum_mfma<RT, 2>(af, rr, twc, abuf, npairs, p, kp.S1, Vf, vstride);
+      expsum_mfma<RT, 2>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride);
   } else {
     const cpx<double>* cc = reinterpret_cast<const cpx<double>*>(slot + kp.lay.ccomp);
     expsum_valu_f64(cc, rr, (const cpx<double>*)tw, 2 * npairs, p, kp.S1, (cpx<double>*)V,
@@ -755,7 +758,7 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
 
 // ----------------------------------------------- component: line sampler ----
 template <typename T, int RT>
-__global__ void __launch_bounds__(kWG) sample_kernel(KParams kp, KBatch kb, int round, int p,
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) sample_kernel(KParams kp, KBatch kb, int round, int p,
                                                      int m, const int64_t* res_off,
                                                      const int64_t* res_y, const double* res_c,
                                                      void* Vvoid) {
@@ -811,7 +814,7 @@ __global__ void __launch_bounds__(kWG) sample_kernel(KParams kp, KBatch kb, int 
 
 // ----------------------------------------------------- component: DFT ------
 template <typename T>
-__global__ void __launch_bounds__(kWG) dft_kernel(KParams kp, cpx<T>* data, int count, int p) {
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) dft_kernel(KParams kp, cpx<T>* data, int count, int p) {
   extern __shared__ __align__(16) char lds[];
   __shared__ WgState st;
   char* slot = kp.ws + (size_t)blockIdx.x * kp.ws_slot;
