@@ -31,7 +31,8 @@ from .transforms import dft
 from .philox import sample_noise
 from .primes import ith_prime_at_least
 from .signal import evaluate, sample_points
-from .unwrapping import wrap, y_range
+from .classifier import bf16_round, bucket_features, bucket_label, prob_single
+from .unwrapping import unwrap, wrap, y_range
 
 READINGS = {
     "R1": "Phaseshift listing labels the shifted and unshifted sample vectors the other "
@@ -64,6 +65,9 @@ READINGS = {
            "the coarse decode lies within N^d1/(4K) of the ladder-refined one.",
     "R18": "Noise ladder (not in the paper): with K > 1 each axis also gets a K eps shift; "
            "y = y_c + round(wrap(theta_K - 2 pi K eps y_c) / (2 pi K eps)).",
+    "R21": "Learned classifier (not in the paper): accept iff the network's singleton "
+           "probability on the 8 bucket features exceeds a threshold and the decode is valid; "
+           "the plain ratio test of eq. (42) is the fallback.",
     "R19": "Noise (not in the paper): sigma/sqrt(2) (g1 + i g2) per sample from "
            "Philox4x64-10, key (seed, signal), counter (h // 2, set, round, 0), output "
            "words 0, 1 for even h and 2, 3 for odd h.",
@@ -88,6 +92,10 @@ class Params:
     prime_rule: str = "paper"
     p_min: int = 0
     robust: bool = False
+    classifier: str = "plain"          # "plain" (eq. (42)) or "mlp" (R21)
+    mlp_params: np.ndarray | None = None
+    mlp_threshold: float = 0.5
+    feature_scale: float | None = None  # None: tau_eff
 
     @property
     def d2(self) -> int:
@@ -160,36 +168,55 @@ def _residual(yR, aR, p, m, n, shift):
     return np.exp(2j * np.pi * ph) @ aR
 
 
-def _test_and_decode(F, h, p, m, P: Params, tab):
-    """Collision test (eq. (42)) and phase-ratio decode (eq. (41)) of bucket h."""
+def _plain_test(F, h, p, P: Params) -> bool:
+    """eq. (42): | |F_s[h]| / |F_0[h]| - 1 | < tau for every shifted set (R5, R6)."""
     F0 = complex(F[0][h])
-    absF0 = abs(F0)
-    thr = P.tau_eff + (P.tau_noise * math.sqrt(p) / absF0 if P.tau_noise > 0 else 0.0)
-    ratios = [complex(F[s][h]) / F0 for s in range(1, len(tab) + 1)]
-    for r in ratios:
-        if not abs(abs(r) - 1.0) < thr:
-            return None
+    thr = P.tau_eff + (P.tau_noise * math.sqrt(p) / abs(F0) if P.tau_noise > 0 else 0.0)
+    for s in range(1, len(F)):
+        if not abs(abs(complex(F[s][h]) / F0) - 1.0) < thr:
+            return False
+    return True
+
+
+def _decode(F, h, p, m, P: Params):
+    """Phase-ratio decode of eq. (41) with the ladder (R18); returns (y, valid).
+
+    valid: every coordinate in band (R16) and, in robust mode, the residue and
+    ladder-consistency checks (R17).
+    """
+    F0 = complex(F[0][h])
     NB = P.NB
+    valid = True
     y = np.zeros(P.d2, dtype=np.int64)
     for n in range(1, P.d2 + 1):
-        th = _arg(ratios[n - 1])
+        th = _arg(complex(F[n][h]) / F0)
         yc_real = th * NB / math.pi            # Arg / (2 pi eps) with eps = 1/(2 NB)
         yn = _round_half_away(yc_real)
         if P.ladder_K > 1:                     # R18
             K = P.ladder_K
-            thf = _arg(ratios[P.d2 + n - 1])
+            thf = _arg(complex(F[P.d2 + n][h]) / F0)
             q = (K * yn) % (2 * NB)            # 2 pi K eps yn, reduced exactly
             delta = _wrap_pi(thf - math.pi * q / NB)
             yn = yn + _round_half_away(delta * NB / (math.pi * K))
             if P.robust and abs(yc_real - yn) > NB / (4.0 * K):
-                return None
+                valid = False
         y[n - 1] = yn
     lo, hi = y_range(P.N, P.d1)                # R16: out-of-band decodes are no mode
     if np.any(y < lo) or np.any(y > hi):
-        return None
+        valid = False
     if P.robust and (int(y[m - 1]) % p) != h:  # R17
-        return None
-    return tuple(int(v) for v in y), F0 / p
+        valid = False
+    return y, valid
+
+
+def _coefficient(F0h, p: int) -> complex:
+    """a = F_0[h] / p (eq. (41))."""
+    return complex(F0h) / p
+
+
+def _features(F, h, y, m, P: Params) -> np.ndarray:
+    scale = P.tau_eff if P.feature_scale is None else P.feature_scale
+    return bucket_features(F, h, y, m, P.d2, P.ladder_K, P.NB, scale)
 
 
 def round_samples(freqs, coeffs, P: Params, p: int, m: int, i: int, yR, aR,
@@ -216,7 +243,8 @@ def round_samples(freqs, coeffs, P: Params, p: int, m: int, i: int, yR, aR,
 
 
 def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
-                    signal: int = 0, keep_spectra: bool = False) -> Result:
+                    signal: int = 0, keep_spectra: bool = False, collect: list | None = None
+                    ) -> Result:
     """Recover the spectrum of the planted signal sum_j coeffs[j] e^{2 pi i freqs[j] . t}.
 
     The signal is only evaluated as a black box at the sampling points; the
@@ -226,6 +254,7 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
     freqs = np.asarray(freqs, dtype=np.int64)
     coeffs = np.asarray(coeffs, dtype=np.complex128)
     d, d1, d2, N = P.d, P.d1, P.d2, P.N
+    y_planted = unwrap(freqs, d1, N) if collect is not None else None
     tab = shift_table(d2, P.ladder_K)
     R: dict = {}
     trace, spectra, registry = [], [], []
@@ -247,9 +276,18 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
         cand = sorted(int(x) for x in order if abs(F0[x]) / p >= P.eta)  # R8
         accepted = []
         for hb in cand:
-            out = _test_and_decode(F, hb, p, m, P, tab)
-            if out is not None:
-                accepted.append(out)
+            y, valid = _decode(F, hb, p, m, P)
+            if P.classifier == "mlp" or collect is not None:
+                x = bf16_round(_features(F, hb, y, m, P))
+            if P.classifier == "mlp":
+                ok = valid and prob_single(P.mlp_params, x[None, :])[0] > P.mlp_threshold
+            else:
+                ok = valid and _plain_test(F, hb, p, P)
+            if collect is not None:
+                collect.append((i, hb, x, bucket_label(hb, p, m, y_planted, coeffs, R, P.eta),
+                                int(ok)))
+            if ok:
+                accepted.append((tuple(int(v) for v in y), _coefficient(F0[hb], p)))
         for y, a in accepted:                                            # R10
             R[y] = R.get(y, 0.0) + a
         R = {y: a for y, a in R.items() if abs(a) >= P.eta}              # R8

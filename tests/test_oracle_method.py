@@ -194,12 +194,7 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         monkeypatch.setattr(mps_mod, "sample_points",
                             lambda d, d1, N, p, m, n, shift: orig(d, d1, N, p, m, m, shift))
     elif mutation == "coef_scale":
-        orig_td = mps_mod._test_and_decode
-
-        def td(F, h, p, m, P, tab):
-            out = orig_td(F, h, p, m, P, tab)
-            return None if out is None else (out[0], out[1] * p / (p - 1))
-        monkeypatch.setattr(mps_mod, "_test_and_decode", td)
+        monkeypatch.setattr(mps_mod, "_coefficient", lambda F0h, p: complex(F0h) / (p - 1))
     elif mutation == "arg_sign":
         monkeypatch.setattr(mps_mod, "_arg", lambda z: -math.atan2(z.imag, z.real))
     assert not _pins_hold()
