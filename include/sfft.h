@@ -47,7 +47,21 @@ typedef enum {
 
 enum { SFFT_PRIME_PAPER = 0, SFFT_PRIME_SMOOTH = 1 };
 enum { SFFT_FP64 = 0, SFFT_FP32 = 1 };
-enum { SFFT_CLS_PLAIN = 0 };
+enum { SFFT_CLS_PLAIN = 0, SFFT_CLS_MLP = 1 };
+
+/* Learned bucket classifier (not in the paper): an 8-64-64-2 ReLU network with
+ * BF16 parameters, evaluated with FP32 accumulation.  Parameter blob: the
+ * SFFT_MLP_PARAMS BF16 values W1 [64][8], b1 [64], W2 [64][64], b2 [64],
+ * W3 [2][64], b3 [2], row-major, back to back.  Output 1 is "the bucket holds
+ * exactly one mode".  Features of a candidate bucket h, with r_s =
+ * F_s[h] / F_0[h], y the decoded unwrapped frequency and z = r_s exp(-i pi K y_n
+ * / N^d1) for a set shifted by K eps along axis n: the coarse and fine sets of
+ * the projection axis m and of the axis n* != m whose fine |r| is furthest from
+ * 1 (ties to the smaller n; n* = m when d2 = 1; fine = coarse without a
+ * ladder), each as asinh((Re z - 1) / s), asinh(Im z / s), s = feature_scale;
+ * inputs are rounded to BF16 before the network. */
+#define SFFT_MLP_PARAMS 4866
+#define SFFT_MLP_FEATURES 8
 
 /* Method parameters (the inputs c, k, N, d, d1, d2, eps of the MultiPhaseshift
  * listing, plus the readings the paper leaves open). */
@@ -68,7 +82,12 @@ typedef struct {
                          exponential sums and DFTs, FP64 decode and registry        */
   int32_t robust;     /* 0: paper's test.  1: also residue y_m = h (mod p) and
                          ladder-consistency checks                                  */
-  int32_t classifier; /* SFFT_CLS_PLAIN (the ratio-magnitude test of eq. (42))      */
+  int32_t classifier; /* SFFT_CLS_PLAIN: the ratio-magnitude test of eq. (42).
+                         SFFT_CLS_MLP: accept iff the network's probability of one
+                         mode exceeds mlp_threshold (the decode checks still apply) */
+  const void* mlp_weights; /* device, SFFT_MLP_PARAMS BF16 values; NULL with PLAIN      */
+  double mlp_threshold;    /* acceptance threshold on the probability, (0, 1)          */
+  double feature_scale;    /* s of the features; <= 0 means s = tau                    */
 } sfft_params;
 
 /* A batch of synthetic black-box signals with planted spectra.  All pointers
@@ -99,6 +118,15 @@ typedef struct {
   int32_t* rounds;   /* [B] rounds run (optional)                                   */
   int64_t* samples;  /* [B] signal samples taken (optional)                         */
   int32_t* trace;    /* [B][max_rounds][SFFT_TRACE_W] per-round record (optional)   */
+  /* Bucket-feature export (optional; all four NULL to disable).  Every candidate
+   * bucket of every round appends one record at an atomically claimed index
+   * (order across signals is not deterministic); records beyond feat_cap are
+   * counted but dropped.  *feat_count is zeroed by the call. */
+  float* feat;        /* [feat_cap][SFFT_MLP_FEATURES] features (before BF16 rounding)  */
+  uint8_t* label;     /* [feat_cap] 1 iff the residual holds exactly one mode in h  */
+  int32_t* feat_meta; /* [feat_cap][4] signal, round, bucket h, accepted (0/1)      */
+  int64_t* feat_count;/* [1] records produced                                       */
+  int64_t feat_cap;
 } sfft_outputs;
 
 /* Create a plan: validates `params` (SFFT_EINVAL / SFFT_ERANGE), derives the
@@ -139,6 +167,28 @@ sfft_status sfft_sample_lines(sfft_plan plan, const sfft_signal_batch* batch, in
  * `count` sequences of length p stored back to back in `data` (complex of the
  * plan's precision, device), in place.  Any p in [2, plan's largest prime]. */
 sfft_status sfft_dft(sfft_plan plan, void* data, int32_t count, int32_t p, void* stream);
+
+/* Learned classifier kernels.  `w` points to SFFT_MLP_PARAMS BF16 values
+ * (device); x holds n feature rows of SFFT_MLP_FEATURES floats (device), which
+ * are rounded to BF16 on input; y holds n labels in {0, 1}.
+ *
+ * sfft_mlp_forward: prob[i] = probability of one mode for row i (device, n).
+ * sfft_mlp_grad: mean softmax cross-entropy over the rows and its gradient
+ *   with respect to the parameters (device: grad [SFFT_MLP_PARAMS], loss [1],
+ *   both overwritten); the forward and backward passes of training.
+ * sfft_mlp_train: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master
+ *   parameters initialised from `w`, `epochs` passes of ceil(n / batch) steps
+ *   over minibatches drawn with replacement (counter-based hash of seed, step,
+ *   row); `w` is overwritten with the BF16 rounding of the trained masters;
+ *   loss_hist (device, [epochs], optional) receives the mean minibatch loss of
+ *   each epoch.  Allocates and frees its optimiser state (about 80 KB) and
+ *   synchronises `stream` before returning. */
+sfft_status sfft_mlp_forward(const void* w, const float* x, int64_t n, float* prob, void* stream);
+sfft_status sfft_mlp_grad(const void* w, const float* x, const uint8_t* y, int64_t n, float* grad,
+                          float* loss, void* stream);
+sfft_status sfft_mlp_train(void* w, const float* x, const uint8_t* y, int64_t n, int32_t epochs,
+                           int32_t batch, double lr, uint64_t seed, float* loss_hist,
+                           void* stream);
 
 /* Largest prime a round of this plan can use, and the number of sample sets
  * per round (S+1). */

@@ -278,14 +278,15 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
         for hb in cand:
             y, valid = _decode(F, hb, p, m, P)
             if P.classifier == "mlp" or collect is not None:
-                x = bf16_round(_features(F, hb, y, m, P))
+                feats = _features(F, hb, y, m, P)
             if P.classifier == "mlp":
+                x = bf16_round(feats)
                 ok = valid and prob_single(P.mlp_params, x[None, :])[0] > P.mlp_threshold
             else:
                 ok = valid and _plain_test(F, hb, p, P)
             if collect is not None:
-                collect.append((i, hb, x, bucket_label(hb, p, m, y_planted, coeffs, R, P.eta),
-                                int(ok)))
+                collect.append((i, hb, feats, bucket_label(hb, p, m, y_planted, coeffs, R, P.eta),
+                                int(ok), abs(F0[hb]) / p))
             if ok:
                 accepted.append((tuple(int(v) for v in y), _coefficient(F0[hb], p)))
         for y, a in accepted:                                            # R10

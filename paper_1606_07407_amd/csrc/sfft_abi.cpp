@@ -87,7 +87,14 @@ static sfft_status validate_params(const sfft_params* p) {
   if (p->precision != SFFT_FP64 && p->precision != SFFT_FP32)
     return fail(SFFT_EINVAL, "unknown precision");
   if (p->robust != 0 && p->robust != 1) return fail(SFFT_EINVAL, "robust must be 0 or 1");
-  if (p->classifier != SFFT_CLS_PLAIN) return fail(SFFT_EINVAL, "unknown classifier");
+  if (p->classifier != SFFT_CLS_PLAIN && p->classifier != SFFT_CLS_MLP)
+    return fail(SFFT_EINVAL, "unknown classifier");
+  if (p->classifier == SFFT_CLS_MLP) {
+    if (!p->mlp_weights) return fail(SFFT_EINVAL, "the learned classifier needs mlp_weights");
+    if (!(p->mlp_threshold > 0.0 && p->mlp_threshold < 1.0))
+      return fail(SFFT_EINVAL, "mlp_threshold must be in (0, 1)");
+  }
+  if (!std::isfinite(p->feature_scale)) return fail(SFFT_EINVAL, "feature_scale must be finite");
   return SFFT_OK;
 }
 
@@ -133,6 +140,10 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.tau = (P.tau > 0.0) ? P.tau : 1.0 / (2.0 * (double)kp.NB);
   kp.tau_noise = P.tau_noise;
   kp.eta = P.eta;
+  kp.classifier = P.classifier;
+  kp.mlp_w = (const uint16_t*)P.mlp_weights;
+  kp.mlp_thr = P.mlp_threshold;
+  kp.feat_scale = (P.feature_scale > 0.0) ? P.feature_scale : kp.tau;
 
   // Largest prime any round can use: the max_rounds-th rule prime >= max(ceil(c k_max), p_min).
   const double xd = std::max(std::ceil(P.c * (double)P.k_max), (double)P.p_min);
@@ -177,7 +188,8 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
                           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0));  // sampler
   lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
   lds = std::max(lds, merge_lds(kp.k_max, kp.cap).bytes);                // registry merge
-  lds = std::max(lds, 4 * (size_t)kp.k_max);                             // decode / output
+  lds = std::max(lds, decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max);  // decode / export
+  lds = std::max(lds, 4 * (size_t)kp.k_max);                             // output
   lds = align16(lds);
   if (lds > 160 * 1024 - 4096)
     return fail(SFFT_ERANGE, "plan needs %zu bytes of LDS per work-group", lds);
@@ -204,6 +216,8 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   lay.acc_a = o;  o = al256(o + 16 * (size_t)kp.k_max);
   lay.acc_ok = o; o = al256(o + 4 * (size_t)kp.k_max);
   lay.run = o;    o = al256(o + 4 * (size_t)kp.k_max);
+  lay.pl_sorted = o; o = al256(o + 4 * (size_t)kp.k_max);
+  lay.feat_tmp = o;  o = al256(o + 4 * 8 * (size_t)kp.k_max);
   lay.bytes = o;
   kp.lay = lay;
   kp.ws_slot = lay.bytes;
@@ -308,7 +322,17 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
   ko.rounds = out->rounds;
   ko.samples = out->samples;
   ko.trace = out->trace;
-  int e = launch_zero_queue(plan->kp, stream);
+  const int nexp = (out->feat != nullptr) + (out->label != nullptr) + (out->feat_meta != nullptr) +
+                   (out->feat_count != nullptr);
+  if (nexp != 0 && nexp != 4)
+    return fail(SFFT_EINVAL, "feature export needs feat, label, feat_meta and feat_count");
+  if (nexp == 4 && out->feat_cap < 0) return fail(SFFT_EINVAL, "feat_cap must be >= 0");
+  ko.feat = out->feat;
+  ko.label = out->label;
+  ko.meta = out->feat_meta;
+  ko.count = out->feat_count;
+  ko.cap = nexp ? out->feat_cap : 0;
+  int e = launch_zero_queue(plan->kp, out->feat_count, stream);
   if (e) return hip_fail((hipError_t)e, "queue reset launch");
   const int grid = std::min(batch->B, plan->kp.n_slots);
   e = launch_recover(plan->kp, to_kbatch(batch), ko, grid, stream);
@@ -344,6 +368,61 @@ sfft_status sfft_dft(sfft_plan plan, void* data, int32_t count, int32_t p, void*
     return fail(SFFT_EINVAL, "p = %d outside 2..%d", p, plan->kp.p_max);
   const int e = launch_dft(plan->kp, data, count, p, stream);
   if (e) return hip_fail((hipError_t)e, "dft launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_mlp_forward(const void* w, const float* x, int64_t n, float* prob, void* stream) {
+  g_err[0] = 0;
+  if (!w || !x || !prob) return fail(SFFT_EINVAL, "NULL argument");
+  if (n < 1) return fail(SFFT_EINVAL, "n must be >= 1");
+  const int e = launch_mlp_forward(w, x, n, prob, stream);
+  if (e) return hip_fail((hipError_t)e, "mlp forward launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_mlp_grad(const void* w, const float* x, const uint8_t* y, int64_t n, float* grad,
+                          float* loss, void* stream) {
+  g_err[0] = 0;
+  if (!w || !x || !y || !grad || !loss) return fail(SFFT_EINVAL, "NULL argument");
+  if (n < 1) return fail(SFFT_EINVAL, "n must be >= 1");
+  const int e = launch_mlp_grad(w, x, y, n, n, 0, 0, grad, loss, true, stream);
+  if (e) return hip_fail((hipError_t)e, "mlp grad launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_mlp_train(void* w, const float* x, const uint8_t* y, int64_t n, int32_t epochs,
+                           int32_t batch, double lr, uint64_t seed, float* loss_hist,
+                           void* stream) {
+  g_err[0] = 0;
+  if (!w || !x || !y) return fail(SFFT_EINVAL, "NULL argument");
+  if (n < 1 || epochs < 1 || batch < 1) return fail(SFFT_EINVAL, "n, epochs, batch must be >= 1");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(SFFT_EINVAL, "lr must be > 0");
+  const int P = kMlpParamCount;
+  float* st = nullptr;  // master, m, v, grad, loss
+  hipError_t he = hipMalloc((void**)&st, sizeof(float) * (4 * (size_t)P + 64));
+  if (he != hipSuccess) return fail(SFFT_ENOMEM, "optimiser state: %s", hipGetErrorString(he));
+  float *master = st, *m = st + P, *v = st + 2 * P, *g = st + 3 * P, *loss = st + 4 * P;
+  const uint64_t hseed = seed ? seed : 0x5DEECE66Dull;  // 0 would mean "rows in order"
+  const int64_t steps = (n + batch - 1) / batch;
+  int e = launch_mlp_init(w, master, m, v, stream);
+  if (!e && loss_hist) e = launch_fill(loss_hist, epochs, 0.f, stream);
+  double b1t = 1.0, b2t = 1.0;
+  uint64_t t = 0;
+  for (int ep = 0; ep < epochs && !e; ++ep) {
+    for (int64_t s = 0; s < steps && !e; ++s) {
+      ++t;
+      b1t *= 0.9;
+      b2t *= 0.999;
+      e = launch_mlp_grad(w, x, y, n, batch, hseed, t, g, loss, true, stream);
+      if (!e) e = launch_mlp_adam(master, m, v, g, w, (float)lr, (float)(1.0 - b1t),
+                                  (float)(1.0 - b2t), stream);
+      if (!e && loss_hist) e = launch_mlp_accum(loss, loss_hist + ep, 1.f / (float)steps, stream);
+    }
+  }
+  hipError_t se = hipStreamSynchronize((hipStream_t)stream);
+  (void)hipFree(st);
+  if (e) return hip_fail((hipError_t)e, "mlp train launch");
+  if (se != hipSuccess) return hip_fail(se, "mlp train");
   return SFFT_OK;
 }
 

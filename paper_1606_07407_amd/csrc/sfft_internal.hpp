@@ -36,6 +36,13 @@ __host__ __device__ inline MergeLds merge_lds(int k_max, int cap) {
   return m;
 }
 
+// LDS carve-up of the decode step: accept flags [k_max] | classifier parameters
+// (FP32) | residual-mode counts per bucket [p_max] (feature export only).
+__host__ __device__ inline size_t decode_lds_w(int k_max) { return align16(4 * (size_t)k_max); }
+__host__ __device__ inline size_t decode_lds_cnt(int k_max) {
+  return decode_lds_w(k_max) + align16(4 * (size_t)4866);
+}
+
 // Byte offsets of one work-group slot's workspace (each 256-byte aligned).
 struct WsLayout {
   size_t ypl;      // int64  [k_max][d2]        planted modes, unwrapped
@@ -52,6 +59,8 @@ struct WsLayout {
   size_t acc_a;    // double2[k_max]            decoded coefficients
   size_t acc_ok;   // int32  [k_max]            accept flags, then ranks
   size_t run;      // int32  [k_max]            merge bookkeeping
+  size_t pl_sorted;// int32  [k_max]            planted modes in lexicographic order (export)
+  size_t feat_tmp; // float  [k_max][8]         candidate features (export)
   size_t bytes;    // size of one slot
 };
 
@@ -69,6 +78,9 @@ struct KParams {
   size_t ws_slot;
   WsLayout lay;
   int* queue;             // work-queue counter (zeroed before each launch)
+  int classifier;         // 0 plain ratio test, 1 learned classifier
+  const uint16_t* mlp_w;  // BF16 parameters of the learned classifier
+  double mlp_thr, feat_scale;
   int n_slots;
   int lds_bytes;
 };
@@ -91,10 +103,25 @@ struct KOut {
   int32_t* rounds;
   int64_t* samples;
   int32_t* trace;
+  float* feat;            // bucket-feature export (NULL: off)
+  uint8_t* label;
+  int32_t* meta;
+  int64_t* count;
+  int64_t cap;
 };
 
 // Launchers (defined in the .hip file).  Return a hipError_t as int.
-int launch_zero_queue(const KParams& kp, void* stream);
+int launch_zero_queue(const KParams& kp, int64_t* count, void* stream);
+int launch_mlp_forward(const void* w, const float* x, int64_t n, float* prob, void* stream);
+int launch_mlp_grad(const void* w, const float* x, const uint8_t* y, int64_t n, int64_t rows,
+                    uint64_t seed, uint64_t step, float* grad, float* loss, bool zero,
+                    void* stream);
+int launch_mlp_init(const void* w, float* master, float* m, float* v, void* stream);
+int launch_mlp_adam(float* master, float* m, float* v, const float* g, void* w, float lr,
+                    float bc1, float bc2, void* stream);
+int launch_mlp_accum(const float* src, float* dst, float scale, void* stream);
+int launch_fill(float* a, int n, float v, void* stream);
+constexpr int kMlpParamCount = 4866;
 int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream);
 int launch_sample_lines(const KParams& kp, const KBatch& kb, int round, int p, int m,
                         const int64_t* res_off, const int64_t* res_y, const double* res_c,

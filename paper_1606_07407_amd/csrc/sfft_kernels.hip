@@ -12,6 +12,7 @@
 
 #include "sfft_device.hpp"
 #include "sfft_internal.hpp"
+#include "sfft_mlp.hpp"
 
 namespace sfft {
 
@@ -332,15 +333,74 @@ __device__ void select_round(const KParams& kp, char* slot, WgState& st, char* l
 }
 
 // ------------------------------------------- collision test and decode ------
-// eq. (42): | |F_s[h]| / |F_0[h]| - 1 | < tau (+ tau_noise sqrt(p) / |F_0[h]|)
-// for every shifted set; eq. (41): y_n = Arg(F_n / F_0) / (2 pi eps), refined
-// by the K eps ladder; a = F_0[h] / p.  FP64 throughout.
+// LDS carve-up of the decode step: accept flags [k_max] | classifier
+// parameters (FP32) | residual-mode counts per bucket [p_max] (export only).
+
+// Ratio F_s[h] / F_0[h] in FP64.
 template <typename T>
-__device__ void decode_round(const KParams& kp, char* slot, WgState& st, const cpx<T>* V,
-                             int vstride, int* acc_list, int* sh_part) {
+__device__ __forceinline__ void ratio(const cpx<T>* V, int vstride, int s, int h, double f0x,
+                                      double f0y, double den, double* rx, double* ry) {
+  const double fx = (double)V[(size_t)s * vstride + h].x;
+  const double fy = (double)V[(size_t)s * vstride + h].y;
+  *rx = (fx * f0x + fy * f0y) / den;
+  *ry = (fy * f0x - fx * f0y) / den;
+}
+
+// The 8 classifier features of bucket h (see include/sfft.h): ratios of the
+// coarse and fine sets of axis m and of the most collision-suspicious other
+// axis, with the decoded phase removed, as asinh of their deviation from 1.
+template <typename T>
+__device__ void bucket_features(const KParams& kp, const cpx<T>* V, int vstride, int h,
+                                const int64_t* y, int m0, double f0x, double f0y, float* f) {
+  const double den = f0x * f0x + f0y * f0y;
+  const bool lad = kp.ladder_K > 1;
+  const int d2 = kp.d2;
+  auto set_of = [&](int n0, bool fine) { return (fine && lad) ? d2 + n0 + 1 : n0 + 1; };
+  int nstar = m0;
+  double best = -1.0;
+  for (int n0 = 0; n0 < d2; ++n0) {
+    if (n0 == m0) continue;
+    double rx, ry;
+    ratio<T>(V, vstride, set_of(n0, true), h, f0x, f0y, den, &rx, &ry);
+    const double dv = fabs(hypot(rx, ry) - 1.0);
+    if (dv > best) {
+      best = dv;
+      nstar = n0;
+    }
+  }
+  const double sc = kp.feat_scale;
+  const int ax[4] = {m0, m0, nstar, nstar};
+  for (int q = 0; q < 4; ++q) {
+    const bool fine = (q & 1) != 0;
+    const int64_t K = (fine && lad) ? kp.ladder_K : 1;
+    double rx, ry;
+    ratio<T>(V, vstride, set_of(ax[q], fine), h, f0x, f0y, den, &rx, &ry);
+    const int64_t qq = pmod64(K * y[ax[q]], 2 * kp.NB);
+    double c, sn;
+    expipi(-(double)qq / (double)kp.NB, &c, &sn);
+    const double zx = rx * c - ry * sn, zy = rx * sn + ry * c;
+    f[2 * q] = (float)asinh((zx - 1.0) / sc);
+    f[2 * q + 1] = (float)asinh(zy / sc);
+  }
+}
+
+// Decode every candidate (eq. (41), ladder refinement; band, residue and
+// ladder-consistency checks), then accept it by the ratio-magnitude test of
+// eq. (42) (| |F_s[h]| / |F_0[h]| - 1 | < tau (+ tau_noise sqrt(p) / |F_0[h]|)
+// for every shifted set) or by the learned classifier; a = F_0[h] / p.  FP64.
+template <typename T>
+__device__ void decode_round(const KParams& kp, const KOut& ko, char* slot, WgState& st,
+                             const cpx<T>* V, int vstride, char* lds, int* sh_part) {
+  int* acc_list = reinterpret_cast<int*>(lds);
+  float* Wl = reinterpret_cast<float*>(lds + decode_lds_w(kp.k_max));
   const int* cand = reinterpret_cast<const int*>(slot + kp.lay.cand);
   int64_t* acc_y = reinterpret_cast<int64_t*>(slot + kp.lay.acc_y);
   double2* acc_a = reinterpret_cast<double2*>(slot + kp.lay.acc_a);
+  int* acc_ok = reinterpret_cast<int*>(slot + kp.lay.acc_ok);
+  float* ftmp = reinterpret_cast<float*>(slot + kp.lay.feat_tmp);
+  const bool use_mlp = kp.classifier == 1;
+  const bool exporting = ko.feat != nullptr;
+  if (use_mlp) mlp_load(kp.mlp_w, Wl);
   const int p = st.p, d2 = kp.d2, S = kp.S;
   const int64_t NB = kp.NB;
   const double NBd = (double)NB;
@@ -357,50 +417,176 @@ __device__ void decode_round(const KParams& kp, char* slot, WgState& st, const c
   for (int c = threadIdx.x; c < st.ncand; c += kWG) {
     const int h = cand[c];
     const double f0x = (double)V[h].x, f0y = (double)V[h].y;
-    const double absF0 = hypot(f0x, f0y);
-    double thr = kp.tau;
-    if (kp.tau_noise > 0.0) thr += kp.tau_noise * sqrt((double)p) / absF0;
     const double den = f0x * f0x + f0y * f0y;
-    bool ok = true;
-    for (int s = 1; s <= S && ok; ++s) {
-      const double fx = (double)V[(size_t)s * vstride + h].x;
-      const double fy = (double)V[(size_t)s * vstride + h].y;
-      const double rx = (fx * f0x + fy * f0y) / den, ry = (fy * f0x - fx * f0y) / den;
-      const double mag = hypot(rx, ry);
-      if (!(fabs(mag - 1.0) < thr)) ok = false;
-    }
     int64_t* y = acc_y + (size_t)c * d2;
-    for (int n = 0; n < d2 && ok; ++n) {
-      const double fx = (double)V[(size_t)(n + 1) * vstride + h].x;
-      const double fy = (double)V[(size_t)(n + 1) * vstride + h].y;
-      const double rx = (fx * f0x + fy * f0y) / den, ry = (fy * f0x - fx * f0y) / den;
+    bool valid = true;
+    for (int n = 0; n < d2; ++n) {
+      double rx, ry;
+      ratio<T>(V, vstride, n + 1, h, f0x, f0y, den, &rx, &ry);
       double th = atan2(ry, rx);
       if (th >= M_PI) th = -M_PI;
       const double yc_real = th * NBd / M_PI;
       int64_t yn = llround(yc_real);
       if (kp.ladder_K > 1) {
         const int64_t K = kp.ladder_K;
-        const double gx = (double)V[(size_t)(d2 + n + 1) * vstride + h].x;
-        const double gy = (double)V[(size_t)(d2 + n + 1) * vstride + h].y;
-        const double sx = (gx * f0x + gy * f0y) / den, sy = (gy * f0x - gx * f0y) / den;
+        double sx, sy;
+        ratio<T>(V, vstride, d2 + n + 1, h, f0x, f0y, den, &sx, &sy);
         double thf = atan2(sy, sx);
         if (thf >= M_PI) thf = -M_PI;
         const int64_t q = pmod64(K * yn, 2 * NB);
         double delta = thf - M_PI * (double)q / NBd;
         delta = delta - 2.0 * M_PI * floor((delta + M_PI) / (2.0 * M_PI));
         yn = yn + llround(delta * NBd / (M_PI * (double)K));
-        if (kp.robust && fabs(yc_real - (double)yn) > NBd / (4.0 * (double)K)) ok = false;
+        if (kp.robust && fabs(yc_real - (double)yn) > NBd / (4.0 * (double)K)) valid = false;
       }
-      if (yn < lo || yn > hi) ok = false;
+      if (yn < lo || yn > hi) valid = false;
       y[n] = yn;
     }
-    if (ok && kp.robust && pmod64(y[st.m0], p) != h) ok = false;
+    if (kp.robust && pmod64(y[st.m0], p) != h) valid = false;
+    bool ok;
+    float f[kMlpIn];
+    if (use_mlp || exporting) bucket_features<T>(kp, V, vstride, h, y, st.m0, f0x, f0y, f);
+    if (use_mlp) {
+      float xb[kMlpIn];
+      for (int i = 0; i < kMlpIn; ++i) xb[i] = bf16_round(f[i]);
+      ok = valid && (double)mlp_prob(Wl, xb) > kp.mlp_thr;
+    } else {
+      const double absF0 = sqrt(den);
+      double thr = kp.tau;
+      if (kp.tau_noise > 0.0) thr += kp.tau_noise * sqrt((double)p) / absF0;
+      ok = valid;
+      for (int s = 1; s <= S && ok; ++s) {
+        double rx, ry;
+        ratio<T>(V, vstride, s, h, f0x, f0y, den, &rx, &ry);
+        if (!(fabs(hypot(rx, ry) - 1.0) < thr)) ok = false;
+      }
+    }
+    if (exporting) {
+      for (int i = 0; i < kMlpIn; ++i) ftmp[(size_t)c * kMlpIn + i] = f[i];
+    }
     acc_list[c] = ok ? 1 : 0;
+    acc_ok[c] = ok ? 1 : 0;
     acc_a[c] = make_double2(f0x / (double)p, f0y / (double)p);
   }
   __syncthreads();
+}
+
+// Number accepted and their ranks (ascending h) in acc_list.
+__device__ inline void decode_finish(const KParams& kp, WgState& st, char* lds, int* sh_part) {
+  int* acc_list = reinterpret_cast<int*>(lds);
   const int n = block_exscan(acc_list, st.ncand, sh_part);
   if (threadIdx.x == 0) st.nacc = n;
+  __syncthreads();
+}
+
+// lower_bound of row y among n rows (lexicographic order); rows given directly
+// or through an index permutation.
+__device__ inline int lower_bound_rows(const int64_t* rows, const int* perm, int n, int w,
+                                       const int64_t* y) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int r = perm ? perm[mid] : mid;
+    if (lexcmp(rows + (size_t)r * w, y, w) < 0)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Export: planted modes sorted lexicographically once per signal (bitonic
+// sort of indices in LDS), for the residual-mode counts of the labels.
+__device__ void export_sort_planted(const KParams& kp, char* slot, WgState& st, char* lds) {
+  const MergeLds ml = merge_lds(kp.k_max, kp.cap);
+  int* ids = reinterpret_cast<int*>(lds + ml.ids);
+  int64_t* key0 = reinterpret_cast<int64_t*>(lds + ml.key0);
+  const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
+  int* out = reinterpret_cast<int*>(slot + kp.lay.pl_sorted);
+  const int n = st.M_pl, d2 = kp.d2;
+  int N2 = 1;
+  while (N2 < n) N2 <<= 1;
+  for (int q = threadIdx.x; q < N2; q += kWG) {
+    ids[q] = q < n ? q : 0x7fffffff;
+    key0[q] = q < n ? ypl[(size_t)q * d2] : INT64_MAX;
+  }
+  __syncthreads();
+  for (int size = 2; size <= N2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < N2 / 2; t += kWG) {
+        const int lo_i = 2 * t - (t & (stride - 1));
+        const int hi_i = lo_i + stride;
+        const bool asc = ((lo_i & size) == 0);
+        const int a = ids[lo_i], b = ids[hi_i];
+        int cmp;
+        if (key0[lo_i] != key0[hi_i]) {
+          cmp = key0[lo_i] < key0[hi_i] ? -1 : 1;
+        } else if (a == 0x7fffffff || b == 0x7fffffff) {
+          cmp = (a == b) ? 0 : (a < b ? -1 : 1);
+        } else {
+          cmp = lexcmp(ypl + (size_t)a * d2, ypl + (size_t)b * d2, d2);
+          if (cmp == 0) cmp = (a < b) ? -1 : (a > b ? 1 : 0);
+        }
+        if ((cmp > 0) == asc) {
+          ids[lo_i] = b;
+          ids[hi_i] = a;
+          const int64_t k0 = key0[lo_i];
+          key0[lo_i] = key0[hi_i];
+          key0[hi_i] = k0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = threadIdx.x; q < n; q += kWG) out[q] = ids[q];
+  __syncthreads();
+}
+
+// Export: label of each candidate = exactly one residual mode (planted minus
+// the registry, |coefficient| >= eta) in its bucket; then one record per
+// candidate (features, label, signal, round, bucket, accepted).
+__device__ void export_round(const KParams& kp, const KBatch& kb, const KOut& ko, char* slot,
+                             WgState& st, char* lds) {
+  int* cnt = reinterpret_cast<int*>(lds + decode_lds_cnt(kp.k_max));
+  const int p = st.p, d2 = kp.d2, m0 = st.m0;
+  const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
+  const int* psort = reinterpret_cast<const int*>(slot + kp.lay.pl_sorted);
+  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
+  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[st.cur]);
+  const int* cand = reinterpret_cast<const int*>(slot + kp.lay.cand);
+  const int* acc_ok = reinterpret_cast<const int*>(slot + kp.lay.acc_ok);
+  const float* ftmp = reinterpret_cast<const float*>(slot + kp.lay.feat_tmp);
+  for (int h = threadIdx.x; h < p; h += kWG) cnt[h] = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < st.M_pl; j += kWG) {
+    const int64_t* yj = ypl + (size_t)j * d2;
+    const int pos = lower_bound_rows(ry, nullptr, st.nR, d2, yj);
+    bool present = true;
+    if (pos < st.nR && lexcmp(ry + (size_t)pos * d2, yj, d2) == 0) {
+      const double rx = kb.coeffs[2 * (st.off + j)] - ra[pos].x;
+      const double ryy = kb.coeffs[2 * (st.off + j) + 1] - ra[pos].y;
+      present = hypot(rx, ryy) >= kp.eta;
+    }
+    if (present) atomicAdd(&cnt[(int)pmod64(yj[m0], p)], 1);
+  }
+  for (int e = threadIdx.x; e < st.nR; e += kWG) {
+    const int64_t* ye = ry + (size_t)e * d2;
+    const int pos = lower_bound_rows(ypl, psort, st.M_pl, d2, ye);
+    const bool planted = pos < st.M_pl && lexcmp(ypl + (size_t)psort[pos] * d2, ye, d2) == 0;
+    if (!planted) atomicAdd(&cnt[(int)pmod64(ye[m0], p)], 1);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < st.ncand; c += kWG) {
+    const unsigned long long slot_i = atomicAdd((unsigned long long*)ko.count, 1ull);
+    if ((int64_t)slot_i < ko.cap) {
+      for (int i = 0; i < kMlpIn; ++i) ko.feat[slot_i * kMlpIn + i] = ftmp[(size_t)c * kMlpIn + i];
+      ko.label[slot_i] = cnt[cand[c]] == 1 ? 1 : 0;
+      ko.meta[slot_i * 4 + 0] = st.sig;
+      ko.meta[slot_i * 4 + 1] = st.i;
+      ko.meta[slot_i * 4 + 2] = cand[c];
+      ko.meta[slot_i * 4 + 3] = acc_ok[c];
+    }
+  }
   __syncthreads();
 }
 
@@ -703,6 +889,7 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
                     reinterpret_cast<float*>(slot + kp.lay.afrag), 0, 2 * P0);
       __syncthreads();
     }
+    if (ko.feat) export_sort_planted(kp, slot, st, lds);
     while (st.nR < st.k && st.i <= kp.max_rounds) {
       if (threadIdx.x == 0) {
         st.kstar = st.k - st.nR;
@@ -730,8 +917,9 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
       sample_round<T, RT>(kp, kb, slot, st, P0, lds, V, vstride);
       dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
       select_round<T>(kp, slot, st, lds, V, sh_part);
-      int* acc_list = reinterpret_cast<int*>(lds);
-      decode_round<T>(kp, slot, st, V, vstride, acc_list, sh_part);
+      decode_round<T>(kp, ko, slot, st, V, vstride, lds, sh_part);
+      if (ko.feat) export_round(kp, kb, ko, slot, st, lds);
+      decode_finish(kp, st, lds, sh_part);
       merge_round<T>(kp, slot, st, lds, sh_part);
       if (threadIdx.x == 0) {
         st.samples += (int64_t)kp.S1 * st.p;
@@ -837,13 +1025,17 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) d
     bluestein_dft<T>(data + (size_t)q * p, p, st.L, st.log2L, chirp, bhat, buf);
 }
 
-__global__ void zero_queue_kernel(int* q) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
+__global__ void zero_queue_kernel(int* q, int64_t* count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *q = 0;
+    if (count) *count = 0;
+  }
 }
 
 // ------------------------------------------------------------ launchers -----
-int launch_zero_queue(const KParams& kp, void* stream) {
-  hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, kp.queue);
+int launch_zero_queue(const KParams& kp, int64_t* count, void* stream) {
+  hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, kp.queue,
+                     count);
   return (int)hipGetLastError();
 }
 

@@ -23,8 +23,10 @@ SFFT_OK, SFFT_NOT_CONVERGED = 0, 1
 SFFT_EINVAL, SFFT_ERANGE, SFFT_ENOMEM, SFFT_EDEVICE = -1, -2, -3, -4
 SFFT_PRIME_PAPER, SFFT_PRIME_SMOOTH = 0, 1
 SFFT_FP64, SFFT_FP32 = 0, 1
-SFFT_CLS_PLAIN = 0
+SFFT_CLS_PLAIN, SFFT_CLS_MLP = 0, 1
 SFFT_TRACE_W = 8
+SFFT_MLP_PARAMS = 4866
+SFFT_MLP_FEATURES = 8
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ERANGE", -3: "ENOMEM",
                 -4: "EDEVICE"}
@@ -38,6 +40,8 @@ class sfft_params(ctypes.Structure):
         ("tau_noise", ctypes.c_double), ("eta", ctypes.c_double),
         ("max_rounds", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("robust", ctypes.c_int32), ("classifier", ctypes.c_int32),
+        ("mlp_weights", ctypes.c_void_p), ("mlp_threshold", ctypes.c_double),
+        ("feature_scale", ctypes.c_double),
     ]
 
 
@@ -53,7 +57,9 @@ class sfft_outputs(ctypes.Structure):
     _fields_ = [
         ("freqs", ctypes.c_void_p), ("coeffs", ctypes.c_void_p), ("k_found", ctypes.c_void_p),
         ("status", ctypes.c_void_p), ("rounds", ctypes.c_void_p), ("samples", ctypes.c_void_p),
-        ("trace", ctypes.c_void_p),
+        ("trace", ctypes.c_void_p), ("feat", ctypes.c_void_p), ("label", ctypes.c_void_p),
+        ("feat_meta", ctypes.c_void_p), ("feat_count", ctypes.c_void_p),
+        ("feat_cap", ctypes.c_int64),
     ]
 
 
@@ -94,6 +100,13 @@ def lib() -> ctypes.CDLL:
         L.sfft_last_error.restype = ctypes.c_char_p
         L.sfft_version.argtypes = []
         L.sfft_version.restype = i32
+        L.sfft_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.sfft_mlp_forward.restype = i32
+        L.sfft_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.sfft_mlp_grad.restype = i32
+        L.sfft_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double,
+                                     ctypes.c_uint64, vp, vp]
+        L.sfft_mlp_train.restype = i32
         _lib = L
     return _lib
 
@@ -136,11 +149,15 @@ class Params:
     precision: int = SFFT_FP32
     robust: int = 0
     classifier: int = SFFT_CLS_PLAIN
+    mlp_weights: object = None      # device tensor of SFFT_MLP_PARAMS bfloat16 values
+    mlp_threshold: float = 0.5
+    feature_scale: float = 0.0
 
     def to_c(self) -> sfft_params:
         return sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
                            self.p_min, self.ladder_K, self.tau, self.tau_noise, self.eta,
-                           self.max_rounds, self.precision, self.robust, self.classifier)
+                           self.max_rounds, self.precision, self.robust, self.classifier,
+                           _ptr(self.mlp_weights), self.mlp_threshold, self.feature_scale)
 
 
 class Plan:
@@ -233,10 +250,19 @@ class DeviceBatch:
                                  self.seed & 0xFFFFFFFFFFFFFFFF)
 
 
-def alloc_outputs(plan: Plan, B: int, trace: bool = True, device="cuda") -> dict:
+def alloc_outputs(plan: Plan, B: int, trace: bool = True, device="cuda",
+                  export_cap: int = 0) -> dict:
     torch = _torch()
     P = plan.params
-    out = dict(
+    if export_cap > 0:
+        exp = dict(
+            feat=torch.zeros((export_cap, SFFT_MLP_FEATURES), dtype=torch.float32, device=device),
+            label=torch.zeros(export_cap, dtype=torch.uint8, device=device),
+            feat_meta=torch.zeros((export_cap, 4), dtype=torch.int32, device=device),
+            feat_count=torch.zeros(1, dtype=torch.int64, device=device))
+    else:
+        exp = dict(feat=None, label=None, feat_meta=None, feat_count=None)
+    out = dict(**exp,
         freqs=torch.zeros((B, P.k_max, P.d), dtype=torch.int64, device=device),
         coeffs=torch.zeros((B, P.k_max, 2), dtype=torch.float64, device=device),
         k_found=torch.zeros(B, dtype=torch.int32, device=device),
@@ -252,9 +278,11 @@ def alloc_outputs(plan: Plan, B: int, trace: bool = True, device="cuda") -> dict
 def sfft_recover(plan: Plan, batch: DeviceBatch, out: dict | None = None, stream=None) -> dict:
     if out is None:
         out = alloc_outputs(plan, batch.B)
+    cap = int(out["feat"].shape[0]) if out.get("feat") is not None else 0
     o = sfft_outputs(_ptr(out["freqs"]), _ptr(out["coeffs"]), _ptr(out["k_found"]),
                      _ptr(out["status"]), _ptr(out.get("rounds")), _ptr(out.get("samples")),
-                     _ptr(out.get("trace")))
+                     _ptr(out.get("trace")), _ptr(out.get("feat")), _ptr(out.get("label")),
+                     _ptr(out.get("feat_meta")), _ptr(out.get("feat_count")), cap)
     b = batch.to_c()
     _check(lib().sfft_recover(plan.handle, ctypes.byref(b), ctypes.byref(o), _stream(stream)),
            "sfft_recover")
@@ -281,6 +309,37 @@ def sfft_dft(plan: Plan, data, stream=None):
     count, p = int(data.shape[0]), int(data.shape[1])
     _check(lib().sfft_dft(plan.handle, _ptr(data), count, p, _stream(stream)), "sfft_dft")
     return data
+
+
+def sfft_mlp_forward(w, x, prob=None, stream=None):
+    """Probability of one mode for each feature row (x: float32 [n, 8] device)."""
+    torch = _torch()
+    n = int(x.shape[0])
+    if prob is None:
+        prob = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(lib().sfft_mlp_forward(_ptr(w), _ptr(x), n, _ptr(prob), _stream(stream)),
+           "sfft_mlp_forward")
+    return prob
+
+
+def sfft_mlp_grad(w, x, y, stream=None):
+    """(loss tensor [1], gradient tensor [SFFT_MLP_PARAMS]) of the mean cross-entropy."""
+    torch = _torch()
+    grad = torch.empty(SFFT_MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(lib().sfft_mlp_grad(_ptr(w), _ptr(x), _ptr(y), int(x.shape[0]), _ptr(grad),
+                               _ptr(loss), _stream(stream)), "sfft_mlp_grad")
+    return loss, grad
+
+
+def sfft_mlp_train(w, x, y, epochs: int, batch: int, lr: float, seed: int = 1, stream=None):
+    """Train in place (w: bfloat16 [SFFT_MLP_PARAMS] device); returns per-epoch losses."""
+    torch = _torch()
+    hist = torch.zeros(epochs, dtype=torch.float32, device=x.device)
+    _check(lib().sfft_mlp_train(_ptr(w), _ptr(x), _ptr(y), int(x.shape[0]), int(epochs),
+                                int(batch), float(lr), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                _ptr(hist), _stream(stream)), "sfft_mlp_train")
+    return hist
 
 
 def outputs_to_host(out: dict) -> dict:

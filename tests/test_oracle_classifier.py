@@ -69,7 +69,7 @@ def test_labels_count_residual_modes():
     y = oracle.unwrap(w, 1, 256)
     tr = {t["i"]: t for t in r.trace}
     # round 1: the registry is empty, so the label is "exactly one planted y_m = h mod p"
-    for (i, h, x, lab, acc) in col:
+    for (i, h, x, lab, acc, _) in col:
         if i != 1:
             continue
         p, m = tr[1]["p"], tr[1]["m"]
