@@ -83,6 +83,24 @@ def cpu_baseline(cfg, pb, n_sig: int) -> dict:
                       f"{dt:.1f} s, {n_ok}/{n_sig} exact"}
 
 
+def time_recover(sfft, plan, db, B, steps, warmup):
+    import torch
+    out = sfft.alloc_outputs(plan, B)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        sfft.sfft_recover(plan, db, out, stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        sfft.sfft_recover(plan, db, out, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return out, wall / steps, ev0.elapsed_time(ev1) / steps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c3b")
     ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--classifier", default="both", choices=["both", "plain", "mlp"])
+    ap.add_argument("--train-rows", type=int, default=1_000_000)
     ap.add_argument("--cpu-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -100,6 +120,7 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_1606_07407_amd import classifier as cls
     from paper_1606_07407_amd import sfft
 
     cfg = workloads.config(args.config)
@@ -111,41 +132,50 @@ def main():
     pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], ks, cfg["mag"], sig)
     k_max = int(np.max(pb.k))
     torch.cuda.set_device(0)
-    params = sfft.Params(d=cfg["d"], N=cfg["N"], k_max=k_max, d1=cfg["d1"], c=cfg["c"],
-                         p_min=cfg["p_min"], ladder_K=cfg["ladder_K"], tau=cfg["tau"] or 0.0,
-                         eta=cfg["eta"],
-                         precision=sfft.SFFT_FP32 if cfg["precision"] == "fp32" else sfft.SFFT_FP64,
-                         robust=int(cfg["robust"]))
-    plan = sfft.sfft_plan_create(params, max_batch=B)
     db = sfft.DeviceBatch.from_planted(pb)
-    out = sfft.alloc_outputs(plan, B)
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        sfft.sfft_recover(plan, db, out, stream)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        sfft.sfft_recover(plan, db, out, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1) / args.steps
-    h = sfft.outputs_to_host(out)
-    ok = exact_support(pb, h)
-    n_ok = int(ok.sum())
-    step_s = wall / args.steps
-    flops = algorithmic_flops(h["trace"], pb.k, plan.num_sets)
-    achieved = flops / (gpu_ms * 1e-3) / 1e12
+    base = dict(d=cfg["d"], N=cfg["N"], k_max=k_max, d1=cfg["d1"], c=cfg["c"],
+                p_min=cfg["p_min"], ladder_K=cfg["ladder_K"], tau=cfg["tau"] or 0.0,
+                eta=cfg["eta"],
+                precision=sfft.SFFT_FP32 if cfg["precision"] == "fp32" else sfft.SFFT_FP64,
+                robust=int(cfg["robust"]))
+    kinds = ["plain", "mlp"] if args.classifier == "both" else [args.classifier]
+    results, train_info = {}, None
+    for kind in kinds:
+        extra = {}
+        if kind == "mlp":
+            t0 = time.perf_counter()
+            x, y, sid = cls.export_features(args.train_rows)
+            w, hist = cls.train(x, y)
+            train_info = {"rows": int(x.shape[0]), "epochs": int(len(hist)),
+                          "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+                          "train_accuracy": cls.accuracy(w, x, y),
+                          "setup_s": time.perf_counter() - t0,
+                          "data": "buckets exported by the plain path on d=6 N=4096 k=2000 "
+                                  "signals, sigma~U[0,1e-2]"}
+            del x, y, sid
+            extra = dict(classifier=sfft.SFFT_CLS_MLP, mlp_weights=w, mlp_threshold=0.5)
+        plan = sfft.sfft_plan_create(sfft.Params(**base, **extra), max_batch=B)
+        out, step_s, gpu_ms = time_recover(sfft, plan, db, B, args.steps, args.warmup)
+        h = sfft.outputs_to_host(out)
+        ok = exact_support(pb, h)
+        flops = algorithmic_flops(h["trace"], pb.k, plan.num_sets)
+        results[kind] = dict(value=int(ok.sum()) / step_s, success_rate=float(ok.mean()),
+                             ms_per_step=step_s * 1e3, kernel_ms=gpu_ms,
+                             mean_rounds=float(np.mean(h["rounds"])),
+                             mean_samples=float(np.mean(h["samples"])), flops=flops)
+        plan.close()
+    # headline: the classifier with the highest exact-support success, then throughput
+    best = max(kinds, key=lambda k: (results[k]["success_rate"], results[k]["value"]))
+    r = results[best]
+    achieved = r["flops"] / (r["kernel_ms"] * 1e-3) / 1e12
     line = {
         "metric": METRIC,
-        "value": n_ok / step_s,
+        "value": r["value"],
         "unit": "recoveries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": step_s * 1e3,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -156,12 +186,15 @@ def main():
                         f"sigma={cfg['sigma']} |a|~U{list(cfg['mag'])}",
             "batch": B, "d": cfg["d"], "N": cfg["N"], "k": cfg["k"], "d1": cfg["d1"],
             "c": cfg["c"], "ladder_K": cfg["ladder_K"], "tau": cfg["tau"], "eta": cfg["eta"],
-            "p_min": cfg["p_min"], "classifier": "plain",
+            "p_min": cfg["p_min"], "classifier": best,
             "parallelism": "one GPU, one work-group per signal",
         },
-        "success_rate": n_ok / B,
-        "mean_rounds": float(np.mean(h["rounds"])),
-        "mean_samples": float(np.mean(h["samples"])),
+        "success_rate": r["success_rate"],
+        "mean_rounds": r["mean_rounds"],
+        "mean_samples": r["mean_samples"],
+        "learned_vs_plain": {k: {kk: v for kk, v in results[k].items() if kk != "flops"}
+                             for k in kinds},
+        "classifier_training": train_info,
         "roofline": {
             "bound": "mfma",
             "achieved": achieved,
@@ -169,14 +202,13 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_MFMA,
             "traffic": None,
-            "kernel": "recover_kernel (persistent, whole recovery)",
-            "kernel_ms": gpu_ms,
-            "algorithmic_flops_per_launch": flops,
+            "kernel": f"recover_kernel (persistent, whole recovery, {best} classifier)",
+            "kernel_ms": r["kernel_ms"],
+            "algorithmic_flops_per_launch": r["flops"],
         },
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, pb, min(args.cpu_sample, B))
-    plan.close()
     print(json.dumps(line), flush=True)
 
 

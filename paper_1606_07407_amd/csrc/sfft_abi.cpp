@@ -145,7 +145,12 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.mlp_thr = P.mlp_threshold;
   kp.feat_scale = (P.feature_scale > 0.0) ? P.feature_scale : kp.tau;
 
-  // Largest prime any round can use: the max_rounds-th rule prime >= max(ceil(c k_max), p_min).
+  // Largest prime a round can use: the max_rounds-th rule prime >= max(ceil(c k_max), p_min),
+  // clamped to what the in-LDS DFT holds (Bluestein length 2p - 1 <= maxL).  A round that
+  // would need a larger prime (k* still near k_max after many rounds) ends its signal with
+  // SFFT_ERANGE; the first round must fit.
+  const int maxL = (P.precision == SFFT_FP32) ? 8192 : 4096;
+  const int64_t p_lim = (maxL + 1) / 2;
   const double xd = std::max(std::ceil(P.c * (double)P.k_max), (double)P.p_min);
   if (xd > 40000.0) return fail(SFFT_ERANGE, "c * k_max = %.0f is beyond the prime range", xd);
   const int64_t x = (int64_t)xd;
@@ -153,8 +158,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   const bool smooth = (P.prime_rule == SFFT_PRIME_SMOOTH);
   int found = 0;
   int64_t pmax = 0;
-  for (int64_t q = 2; found < P.max_rounds; ++q) {
-    if (q > 46000) return fail(SFFT_ERANGE, "prime schedule exceeds 46000");
+  for (int64_t q = 2; found < P.max_rounds && q <= p_lim; ++q) {
     if (is_prime_host(q) && (!smooth || smooth7(q - 1))) {
       primes.push_back((int32_t)q);
       if (q >= x) {
@@ -163,19 +167,16 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
       }
     }
   }
+  if (found == 0)
+    return fail(SFFT_ERANGE,
+                "the first round needs a prime >= %lld; the in-LDS DFT holds primes up to %lld",
+                (long long)x, (long long)p_lim);
   kp.p_max = (int)pmax;
   int L = 1, lg = 0;
   while (L < 2 * kp.p_max - 1) {
     L <<= 1;
     ++lg;
   }
-  const int maxL = (P.precision == SFFT_FP32) ? 8192 : 4096;
-  if (L > maxL)
-    return fail(SFFT_ERANGE,
-                "largest prime %d needs a %d-point Bluestein DFT; the LDS DFT holds %d points",
-                kp.p_max, L, maxL);
-  if (P.precision == SFFT_FP32 && kp.p_max > 4096)
-    return fail(SFFT_ERANGE, "largest prime %d exceeds 4096 (FP32 sampler index range)", kp.p_max);
   kp.L_max = L;
   kp.log2_Lmax = lg;
   kp.vstride = kp.p_max;

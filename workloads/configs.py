@@ -32,7 +32,7 @@ CONFIGS = {
                 seed=3100, d1=1, c=3.0, ladder_K=1024, tau=1e-3, eta=1e-3,
                 precision="fp32", p_min=101, robust=True),
     "c4": dict(d=6, N=4096, k=2000, B=512, mag=(1.0, 2.0), sigma=(0.0, 1e-2),
-               seed=4000, d1=1, c=3.0, ladder_K=64, tau=1e-3, eta=1e-3,
+               seed=4000, d1=1, c=2.0, ladder_K=64, tau=1e-3, eta=1e-3,
                precision="fp32", p_min=101, robust=True),
     "c5": dict(d=20, N=65536, k=4096, B=64, mag=(1.0, 4.0), sigma=1e-2,
                seed=5000, d1=1, c=3.0, ladder_K=256, tau=3e-3, eta=1e-3,
