@@ -117,7 +117,8 @@ typedef struct {
   int32_t* status;   /* [B] SFFT_OK or SFFT_NOT_CONVERGED (or SFFT_ERANGE)          */
   int32_t* rounds;   /* [B] rounds run (optional)                                   */
   int64_t* samples;  /* [B] signal samples taken (optional)                         */
-  int32_t* trace;    /* [B][max_rounds][SFFT_TRACE_W] per-round record (optional)   */
+  int32_t* trace;    /* [B][max_rounds][SFFT_TRACE_W] per-round record (optional);
+                      * rows after the last round run are zeroed                   */
   /* Bucket-feature export (optional; all four NULL to disable).  Every candidate
    * bucket of every round appends one record at an atomically claimed index
    * (order across signals is not deterministic); records beyond feat_cap are

@@ -220,24 +220,26 @@ def _features(F, h, y, m, P: Params) -> np.ndarray:
 
 
 def round_samples(freqs, coeffs, P: Params, p: int, m: int, i: int, yR, aR,
-                  sigma: float = 0.0, seed: int = 0, signal: int = 0) -> np.ndarray:
+                  sigma: float = 0.0, seed: int = 0, signal: int = 0,
+                  hs=None) -> np.ndarray:
     """The S+1 sample sets of round i: v_s[h] = f(t_h) + noise - g(t~_h), complex [S+1, p].
 
     t_h = (h/p) U e_m + eps_s U e_n (eqs. (36), (41)); g is the registry
     {(yR[e], aR[e])} evaluated on the unwrapped line (Section 5.0).  Set 0 is
-    unshifted and is sampled once per round (R15).
+    unshifted and is sampled once per round (R15).  hs: only these points h
+    (columns of the result, in the given order); default all p.
     """
     d, d1, N = P.d, P.d1, P.N
     tab = shift_table(P.d2, P.ladder_K)
-    h = np.arange(p)
+    h = np.arange(p) if hs is None else np.asarray(hs, dtype=np.int64)
     V = []
     for s, (n, K) in enumerate([(1, 0)] + tab):
         shift = P.eps * K
-        t = sample_points(d, d1, N, p, m, n, shift)
+        t = sample_points(d, d1, N, p, m, n, shift)[h]
         v = evaluate(freqs, coeffs, t)
         v = v + sample_noise(seed, signal, i, s, h, sigma)
         if len(aR):                                        # adaptive subtraction of g
-            v = v - _residual(np.asarray(yR), np.asarray(aR), p, m, n, shift)
+            v = v - _residual(np.asarray(yR), np.asarray(aR), p, m, n, shift)[h]
         V.append(v)
     return np.array(V)
 

@@ -149,7 +149,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   // clamped to what the in-LDS DFT holds (Bluestein length 2p - 1 <= maxL).  A round that
   // would need a larger prime (k* still near k_max after many rounds) ends its signal with
   // SFFT_ERANGE; the first round must fit.
-  const int maxL = (P.precision == SFFT_FP32) ? 8192 : 4096;
+  const int maxL = (P.precision == SFFT_FP32) ? 16384 : 8192;
   const int64_t p_lim = (maxL + 1) / 2;
   const double xd = std::max(std::ceil(P.c * (double)P.k_max), (double)P.p_min);
   if (xd > 40000.0) return fail(SFFT_ERANGE, "c * k_max = %.0f is beyond the prime range", xd);
@@ -182,15 +182,18 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.vstride = kp.p_max;
   const size_t cs = (P.precision == SFFT_FP32) ? 8 : 16;  // complex element size
 
-  // LDS: the largest of the per-step carve-ups.
+  // LDS: the largest of the per-step carve-ups.  The merge/sort arrays stay in
+  // LDS unless they would be the largest; then they live in the slot.
   size_t lds = 0;
   lds = std::max(lds, (size_t)L * cs + (size_t)kTwiddleEntries * cs);     // DFT buffer + twiddles
-  lds = std::max(lds, align16((size_t)kp.p_max * cs) + 2 * align16(4 * (size_t)(kp.m_max + 4)) +
+  lds = std::max(lds, align16((size_t)kp.p_max * cs) + 2 * align16(2 * (size_t)(kp.m_max + 4)) +
                           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0));  // sampler
   lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
-  lds = std::max(lds, merge_lds(kp.k_max, kp.cap).bytes);                // registry merge
   lds = std::max(lds, decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max);  // decode / export
   lds = std::max(lds, 4 * (size_t)kp.k_max);                             // output
+  const size_t merge_bytes = merge_lds(kp.k_max, kp.cap).bytes;
+  kp.merge_global = merge_bytes > lds ? 1 : 0;
+  if (!kp.merge_global) lds = merge_bytes > lds ? merge_bytes : lds;
   lds = align16(lds);
   if (lds > 160 * 1024 - 4096)
     return fail(SFFT_ERANGE, "plan needs %zu bytes of LDS per work-group", lds);
@@ -219,6 +222,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   lay.run = o;    o = al256(o + 4 * (size_t)kp.k_max);
   lay.pl_sorted = o; o = al256(o + 4 * (size_t)kp.k_max);
   lay.feat_tmp = o;  o = al256(o + 4 * 8 * (size_t)kp.k_max);
+  lay.merge = o;     o = al256(o + (kp.merge_global ? merge_bytes : 0));
   lay.bytes = o;
   kp.lay = lay;
   kp.ws_slot = lay.bytes;

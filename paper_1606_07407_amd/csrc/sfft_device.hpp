@@ -45,11 +45,11 @@ template <typename T>
 struct MaxL;
 template <>
 struct MaxL<float> {
-  static constexpr int value = 8192;
+  static constexpr int value = 16384;
 };
 template <>
 struct MaxL<double> {
-  static constexpr int value = 4096;
+  static constexpr int value = 8192;
 };
 
 // exp(i pi x) in FP64 for a dyadic/rational x given as q / den, q exact.
@@ -235,10 +235,11 @@ __device__ __forceinline__ cpx<T> twiddle(const cpx<T>* T1, const cpx<T>* T2, in
   return cmul(T1[t >> kTwiddleBits], T2[t & ((1 << kTwiddleBits) - 1)]);
 }
 
-template <typename T, int R>
+// One in-place pass: every thread holds its up to MAXV items in registers
+// between the read and the write phase, so L <= MAXV * kWG.
+template <typename T, int R, int MAXV>
 __device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* T1, const cpx<T>* T2,
                               bool inv) {
-  constexpr int MAXV = MaxL<T>::value / kWG;
   constexpr int NQ = MAXV / R;
   cpx<T> v[MAXV];
   const int nitems = L / R;
@@ -323,27 +324,47 @@ __device__ void twiddle_tables(int L, cpx<T>* T1, cpx<T>* T2) {
   __syncthreads();
 }
 
-// Unnormalised power-of-two FFT of L <= MaxL<T> points in LDS, forward
-// (exp(-2 pi i ...)) or inverse (exp(+2 pi i ...)), Stockham radix 4 with one
-// radix-2 pass when log2 L is odd.
-template <typename T>
-__device__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx<T>* T1, const cpx<T>* T2,
-                        bool inv) {
-  // log2 L = 4 a + b: radix-2 / radix-4 passes for b, then a radix-16 passes
+// Unnormalised power-of-two FFT of L points in LDS, forward (exp(-2 pi i ...))
+// or inverse (exp(+2 pi i ...)), Stockham: log2 L = 4 a + b, radix-2 / radix-4
+// passes for b, then a radix-16 passes.  MAXV = L / kWG items per thread.
+template <typename T, int MAXV>
+__device__ __forceinline__ void fft_lds_v(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
+                                          const cpx<T>* T2, bool inv) {
   int Ns = 1;
   const int b = log2L & 3;
   if (b & 1) {
-    stockham_pass<T, 2>(buf, L, Ns, T1, T2, inv);
+    stockham_pass<T, 2, MAXV>(buf, L, Ns, T1, T2, inv);
     Ns = 2;
   }
   if (b & 2) {
-    stockham_pass<T, 4>(buf, L, Ns, T1, T2, inv);
+    stockham_pass<T, 4, MAXV>(buf, L, Ns, T1, T2, inv);
     Ns *= 4;
   }
   while (Ns < L) {
-    stockham_pass<T, 16>(buf, L, Ns, T1, T2, inv);
+    stockham_pass<T, 16, MAXV>(buf, L, Ns, T1, T2, inv);
     Ns *= 16;
   }
+}
+
+// The largest lengths, kept out of line: their register-held pass needs twice
+// the registers, and inlining it would raise the register pressure (and the
+// spills) of every caller for all lengths.
+template <typename T>
+__device__ __noinline__ void fft_lds_large(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
+                                           const cpx<T>* T2, bool inv) {
+  fft_lds_v<T, MaxL<T>::value / kWG>(buf, L, log2L, T1, T2, inv);
+}
+
+// L <= MaxL<T>.  Lengths up to half the maximum take the inlined variant with
+// half the per-thread registers.
+template <typename T>
+__device__ __forceinline__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
+                                        const cpx<T>* T2, bool inv) {
+  constexpr int HALF = MaxL<T>::value / 2 / kWG;
+  if (L <= HALF * kWG)
+    fft_lds_v<T, HALF>(buf, L, log2L, T1, T2, inv);
+  else
+    fft_lds_large<T>(buf, L, log2L, T1, T2, inv);
 }
 
 // Bluestein set-up for prime length p and power-of-two L >= 2p - 1:
@@ -414,8 +435,9 @@ __device__ __forceinline__ int mulmod(uint32_t h, uint32_t r, int p, float inv_p
   return (int)rem;
 }
 
-// The same with 24-bit multiplies, for h, r, p < 2^13 (the FP32 sampler keeps
-// p <= 4096 and h < p + 128), so h * r < 2^26 and the quotient is off by at most one.
+// The same with 24-bit multiplies, for p <= 2^13 and h < p + 128 (what the FP32
+// sampler uses): h * r < 2^27, and the FP32 quotient estimate (relative error
+// about 2^-23 on a quotient below 2^14) is off by at most one.
 __device__ __forceinline__ uint32_t mulmod24(uint32_t h, uint32_t r, uint32_t p, float inv_p) {
   const uint32_t x = __umul24(h, r);
   const uint32_t q = (uint32_t)(int)((float)x * inv_p);
@@ -461,7 +483,8 @@ __device__ __forceinline__ void twiddle_column(const float* twf, uint32_t h0, ui
 }
 
 template <int RT, int NT>
-__device__ void expsum_mfma(const float* __restrict__ afrag, const int* rr, const int* rs,
+__device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
+                            const uint16_t* rs,
                             const cpx<float>* tw, float* abuf, int npairs, int p, int S1,
                             cpx<float>* __restrict__ V, int vstride) {
   const int lane = threadIdx.x & 63;
@@ -623,7 +646,7 @@ __device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int S1, ui
 }
 
 // FP64 line sampler on the vector units: one thread per (set, point).
-__device__ inline void expsum_valu_f64(const cpx<double>* __restrict__ C, const int* rr,
+__device__ inline void expsum_valu_f64(const cpx<double>* __restrict__ C, const uint16_t* rr,
                                        const cpx<double>* tw, int M, int p, int S1,
                                        cpx<double>* __restrict__ V, int vstride) {
   const float inv_p = 1.0f / (float)p;

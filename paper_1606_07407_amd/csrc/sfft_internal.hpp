@@ -13,7 +13,7 @@ constexpr int kMaxSets = 2 * kMaxD2 + 1;
 constexpr int kMaxRT = 8;         // MFMA row tiles: 2 (S+1) real rows <= 128
 constexpr int kChunk = 16;        // sampler: A-fragment pairs staged in LDS per chunk
 constexpr int kTwiddleBits = 6;   // DFT twiddles exp(-2 pi i t / L) = T1[t >> 6] * T2[t & 63]
-constexpr int kTwiddleEntries = 64 + 8192 / 64;  // LDS entries of T1 and T2 for L <= 8192
+constexpr int kTwiddleEntries = 64 + 16384 / 64;  // LDS entries of T1 and T2 for L <= 16384
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -61,6 +61,7 @@ struct WsLayout {
   size_t run;      // int32  [k_max]            merge bookkeeping
   size_t pl_sorted;// int32  [k_max]            planted modes in lexicographic order (export)
   size_t feat_tmp; // float  [k_max][8]         candidate features (export)
+  size_t merge;    // MergeLds carve-up when it does not stay in LDS (merge_global)
   size_t bytes;    // size of one slot
 };
 
@@ -83,6 +84,7 @@ struct KParams {
   double mlp_thr, feat_scale;
   int n_slots;
   int lds_bytes;
+  int merge_global;       // 1: the merge/sort arrays live in the slot, not in LDS
 };
 
 struct KBatch {

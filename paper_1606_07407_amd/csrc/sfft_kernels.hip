@@ -180,11 +180,12 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   const int PR = (st.nR + 1) / 2;
   const int npairs = P0 + PR;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
-  int* rr = reinterpret_cast<int*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
-  int* rs = reinterpret_cast<int*>(reinterpret_cast<char*>(rr) +
-                                   align16(4 * (size_t)(kp.m_max + 4)));
+  // residues and column steps fit 16 bits (p <= 8192)
+  uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
+  uint16_t* rs = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(rr) +
+                                             align16(2 * (size_t)(kp.m_max + 4)));
   float* abuf = reinterpret_cast<float*>(reinterpret_cast<char*>(rs) +
-                                         align16(4 * (size_t)(kp.m_max + 4)));
+                                         align16(2 * (size_t)(kp.m_max + 4)));
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
   const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
   for (int x = threadIdx.x; x < p; x += kWG) {
@@ -199,8 +200,8 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     } else if (j >= 2 * P0 && j - 2 * P0 < st.nR) {
       r = (int)pmod64(ry[(size_t)(j - 2 * P0) * d2 + m0], p);
     }
-    rr[j] = r;
-    rs[j] = (int)((16 * (int64_t)r) % p);
+    rr[j] = (uint16_t)r;
+    rs[j] = (uint16_t)((16 * r) % p);
   }
   __syncthreads();
   if constexpr (sizeof(T) == 4) {
@@ -495,12 +496,20 @@ __device__ inline int lower_bound_rows(const int64_t* rows, const int* perm, int
   return lo;
 }
 
+// The merge and sort arrays: in LDS, or in the signal's workspace slot when
+// they would be the largest LDS consumer of the plan (large k_max).  Offset 0
+// (the accept-flag scan) always stays in LDS.
+__device__ __forceinline__ char* merge_base(const KParams& kp, char* slot, char* lds) {
+  return kp.merge_global ? slot + kp.lay.merge : lds;
+}
+
 // Export: planted modes sorted lexicographically once per signal (bitonic
 // sort of indices in LDS), for the residual-mode counts of the labels.
 __device__ void export_sort_planted(const KParams& kp, char* slot, WgState& st, char* lds) {
   const MergeLds ml = merge_lds(kp.k_max, kp.cap);
-  int* ids = reinterpret_cast<int*>(lds + ml.ids);
-  int64_t* key0 = reinterpret_cast<int64_t*>(lds + ml.key0);
+  char* mb = merge_base(kp, slot, lds);
+  int* ids = reinterpret_cast<int*>(mb + ml.ids);
+  int64_t* key0 = reinterpret_cast<int64_t*>(mb + ml.key0);
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
   int* out = reinterpret_cast<int*>(slot + kp.lay.pl_sorted);
   const int n = st.M_pl, d2 = kp.d2;
@@ -600,14 +609,15 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
   const int d2 = kp.d2, S = kp.S;
   const int nC = st.ncand;
   const MergeLds ml = merge_lds(kp.k_max, kp.cap);
-  int* accpos = reinterpret_cast<int*>(lds + ml.accpos);      // exscan of accept flags
-  int* ids = reinterpret_cast<int*>(lds + ml.ids);            // candidate index, sorted
-  int64_t* key0 = reinterpret_cast<int64_t*>(lds + ml.key0);  // first coordinate of y
-  int* runflag = reinterpret_cast<int*>(lds + ml.runflag);    // 1 matched run, 2 new run
-  int* runpos = reinterpret_cast<int*>(lds + ml.runpos);      // lower_bound in R
-  int* cnt = reinterpret_cast<int*>(lds + ml.cnt);            // new runs per position
-  int* matchrun = reinterpret_cast<int*>(lds + ml.matchrun);  // run updating entry e
-  int* keep = reinterpret_cast<int*>(lds + ml.keep);          // ranks, then prune flags
+  char* mb = merge_base(kp, slot, lds);
+  int* accpos = reinterpret_cast<int*>(lds + ml.accpos);     // exscan of accept flags (LDS)
+  int* ids = reinterpret_cast<int*>(mb + ml.ids);            // candidate index, sorted
+  int64_t* key0 = reinterpret_cast<int64_t*>(mb + ml.key0);  // first coordinate of y
+  int* runflag = reinterpret_cast<int*>(mb + ml.runflag);    // 1 matched run, 2 new run
+  int* runpos = reinterpret_cast<int*>(mb + ml.runpos);      // lower_bound in R
+  int* cnt = reinterpret_cast<int*>(mb + ml.cnt);            // new runs per position
+  int* matchrun = reinterpret_cast<int*>(mb + ml.matchrun);  // run updating entry e
+  int* keep = reinterpret_cast<int*>(mb + ml.keep);          // ranks, then prune flags
   const int64_t* acc_y = reinterpret_cast<const int64_t*>(slot + kp.lay.acc_y);
   const double2* acc_a = reinterpret_cast<const double2*>(slot + kp.lay.acc_a);
   const int nA = st.nacc;
@@ -833,6 +843,10 @@ __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgSt
     for (int i = 0; i < d; ++i) fo[(size_t)e * d + i] = 0;
     co[2 * e] = 0.0;
     co[2 * e + 1] = 0.0;
+  }
+  if (ko.trace) {
+    int32_t* tr = ko.trace + (size_t)st.sig * kp.max_rounds * 8;
+    for (int e = (st.i - 1) * 8 + threadIdx.x; e < kp.max_rounds * 8; e += kWG) tr[e] = 0;
   }
   if (threadIdx.x == 0) {
     ko.k_found[st.sig] = nR;

@@ -69,7 +69,8 @@ BAD = [
     (dict(d=200, d1=1), -2),                         # d2 beyond 64
     (dict(d=6, d1=6, N=1024), -2),                   # N^d1 = 2^60 > 2^40
     (dict(k_max=20000, c=5.0), -2),                  # primes beyond the DFT size
-    (dict(k_max=900, c=5.0), -2),                    # first round needs p >= 4500 > 4096
+    (dict(k_max=1700, c=5.0), -2),                   # first round needs p >= 8500 > 8192
+    (dict(k_max=900, c=5.0, precision=0), -2),       # FP64: p >= 4500 > 4096
     (dict(d=40, d1=1, ladder_K=4), -2),              # 2 (S+1) rows beyond 8 MFMA tiles
 ]
 

@@ -60,22 +60,23 @@ def _oracle_params(cfg, k):
 # ------------------------------------------------------------ sampler -------
 
 SAMPLER_CASES = [
-    # name, config overrides, k, p, m, residual count
-    ("c1_fp64", "c1", {}, 8, 41, 2, 3),
-    ("e4_fp64", "e4", {}, 100, 503, 3, 20),
-    ("c2_fp32", "c2", {}, 256, 1283, 2, 40),
-    ("c3_fp32_ladder_noise", "c3b", {}, 200, 601, 4, 50),
-    ("c3_fp32_full_p", "c3b", {}, 1000, 3001, 2, 0),
+    # name, config overrides, k, p, m, residual count, signals
+    ("c1_fp64", "c1", {}, 8, 41, 2, 3, 2),
+    ("e4_fp64", "e4", {}, 100, 503, 3, 20, 2),
+    ("c2_fp32", "c2", {}, 256, 1283, 2, 40, 2),
+    ("c3_fp32_ladder_noise", "c3b", {}, 200, 601, 4, 50, 2),
+    ("c3_fp32_full_p", "c3b", {}, 1000, 3001, 2, 0, 2),
+    # the large workload's first round: k = 4096, 41 sets, p = 8161, 6 row tiles
+    ("c5_fp32_full_p", "c5", {}, 4096, 8161, 7, 64, 1),
 ]
 
 
-@pytest.mark.parametrize("name,cname,over,k,p,m,nres", SAMPLER_CASES)
-def test_sampler_matches_oracle(name, cname, over, k, p, m, nres):
+@pytest.mark.parametrize("name,cname,over,k,p,m,nres,B", SAMPLER_CASES)
+def test_sampler_matches_oracle(name, cname, over, k, p, m, nres, B):
     import torch
     sfft = _sfft()
     cfg = workloads.config(cname, **over)
     _say(f"[sampler] {name} k={k} p={p} m={m} nres={nres}")
-    B = 2
     pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], k, cfg["mag"],
                                  cfg["sigma"])
     plan = sfft.sfft_plan_create(_params(cfg, k), max_batch=B)
@@ -105,12 +106,19 @@ def test_sampler_matches_oracle(name, cname, over, k, p, m, nres):
                                t_y if nres else None, t_a if nres else None)
     torch.cuda.synchronize()
     V = V.cpu().numpy()
+    # every point up to p = 4096; beyond that the first and last 64 points and
+    # 512 drawn ones (the oracle evaluates each point separately)
+    hs = None
+    if p > 4096:
+        hs = np.unique(np.concatenate([np.arange(64), np.arange(p - 64, p),
+                                       rng.choice(p, size=512, replace=False)]))
     for b in range(B):
         w, a = pb.signal(b)
         lo, hi = res_off[b], res_off[b + 1]
         ref = oracle.round_samples(w, a, P, p, m, round_i, RY[lo:hi], RA[lo:hi],
-                                   sigma=float(pb.sigma[b]), seed=pb.seed, signal=b)
-        err = np.abs(V[b] - ref).max()
+                                   sigma=float(pb.sigma[b]), seed=pb.seed, signal=b, hs=hs)
+        got = V[b] if hs is None else V[b][:, hs]
+        err = np.abs(got - ref).max()
         M = len(a) + (hi - lo)
         amax = max(np.abs(a).max(), np.abs(RA[lo:hi]).max() if hi > lo else 0.0)
         tol = (1e-11 if cfg["precision"] == "fp64" else 8 * U32) * M * amax
@@ -127,12 +135,15 @@ def test_sampler_matches_oracle(name, cname, over, k, p, m, nres):
 def test_dft_matches_numpy(prec):
     import torch
     sfft = _sfft()
-    params = sfft.Params(d=2, N=64, k_max=400 if prec == "fp32" else 200, c=5.0,
+    # largest plans of each precision: Bluestein lengths up to 16384 (FP32) / 8192 (FP64),
+    # both register variants of the in-LDS FFT
+    params = sfft.Params(d=2, N=64, k_max=1600 if prec == "fp32" else 800, c=5.0,
                          precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64)
     plan = sfft.sfft_plan_create(params, max_batch=4)
     pmax = plan.max_prime
+    assert pmax > (4096 if prec == "fp32" else 2048)
     rng = np.random.default_rng(11)
-    for p in sorted({2, 3, 5, 13, 41, 127, 1283, pmax}):
+    for p in sorted(q for q in {2, 3, 5, 13, 41, 127, 1283, 2053, 4093, 4099, pmax} if q <= pmax):
         _say(f"[dft] {prec} p={p}")
         x = rng.normal(size=(5, p)) + 1j * rng.normal(size=(5, p))
         dt = torch.complex64 if prec == "fp32" else torch.complex128
@@ -153,9 +164,9 @@ def test_dft_matches_numpy(prec):
 
 # ------------------------------------------------------------ recover -------
 
-def _compare(cfg, pb, h, rel_tol, check_trace=True):
+def _compare(cfg, pb, h, rel_tol, check_trace=True, signals=None):
     res = []
-    for b in range(pb.B):
+    for b in (range(pb.B) if signals is None else signals):
         w, a = pb.signal(b)
         P = _oracle_params(cfg, pb.k[b])
         ref = oracle.multiphaseshift(w, a, P, sigma=float(pb.sigma[b]), seed=pb.seed, signal=b)
@@ -224,4 +235,102 @@ def test_recover_deterministic_and_reusable():
     torch.cuda.synchronize()
     for key in ("freqs", "coeffs", "k_found", "status", "trace"):
         assert np.array_equal(o1[key], o2[key]), key
+    plan.close()
+
+
+def test_full_size_headline_batch():
+    """The bench's launch: 512 signals, d = 10, N = 65536, k = 1000, sigma = 1e-3.
+    Every signal's support equals its planted set (a property at any size);
+    sampled signals are checked against the oracle in full."""
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config("c3b")
+    B = cfg["B"]
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], cfg["k"], cfg["mag"],
+                                 cfg["sigma"])
+    _say(f"[full] c3b B={B} k={cfg['k']}")
+    plan = sfft.sfft_plan_create(_params(cfg, cfg["k"]), max_batch=B)
+    out = sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb))
+    torch.cuda.synchronize()
+    h = sfft.outputs_to_host(out)
+    for b in range(B):
+        w, a = pb.signal(b)
+        o = np.lexsort(w.T[::-1])
+        kf = int(h["k_found"][b])
+        assert int(h["status"][b]) == 0 and kf == cfg["k"], b
+        assert np.array_equal(h["freqs"][b, :kf], w[o]), b
+        # noise sigma = 1e-3 on p >= 3001 samples: the coefficient estimate is
+        # within a few sigma / sqrt(p) of the planted value
+        assert np.abs(h["coeffs"][b, :kf] - a[o]).max() < 1e-3, b
+    rel = _compare(cfg, pb, h, 1e-5, signals=(0, 257, B - 1))
+    _say(f"    all {B} exact; sampled oracle parity max rel {rel:.2e}")
+    plan.close()
+
+
+def test_graph_capture_replays():
+    """sfft_recover captured in a HIP graph: every replay equals the eager run."""
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config("c3a")
+    B = 64
+    ks = workloads.planted.uneven_k(cfg["seed"], B, 64, 400)
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], ks, cfg["mag"],
+                                 cfg["sigma"])
+    plan = sfft.sfft_plan_create(_params(cfg, int(pb.k.max())), max_batch=B)
+    db = sfft.DeviceBatch.from_planted(pb)
+    eager = sfft.outputs_to_host(sfft.sfft_recover(plan, db))
+    torch.cuda.synchronize()
+    out = sfft.alloc_outputs(plan, B)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sfft.sfft_recover(plan, db, out)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for t in out.values():
+            if isinstance(t, torch.Tensor):
+                t.fill_(7)  # eager work between replays; the replay must overwrite it
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = sfft.outputs_to_host(out)
+        for key in ("freqs", "coeffs", "k_found", "status", "rounds", "samples", "trace"):
+            assert np.array_equal(got[key], eager[key]), (rep, key)
+    _say(f"[graph] 3 replays equal the eager run (B={B})")
+    del g
+    plan.close()
+
+
+def test_large_workload_exact_support():
+    """The large workload in the bench's launch: 64 signals, d = 20, N = 65536,
+    k = 4096, sigma = 1e-2, Bluestein length 16384.  Every support equals the
+    planted set; coefficients within the noise bound of the planted values."""
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config("c5")
+    B = cfg["B"]
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], cfg["k"], cfg["mag"],
+                                 cfg["sigma"])
+    _say(f"[large] c5 B={B} k={cfg['k']}")
+    plan = sfft.sfft_plan_create(_params(cfg, cfg["k"]), max_batch=B)
+    out = sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb))
+    torch.cuda.synchronize()
+    h = sfft.outputs_to_host(out)
+    bad = []
+    worst = 0.0
+    for b in range(B):
+        w, a = pb.signal(b)
+        o = np.lexsort(w.T[::-1])
+        kf = int(h["k_found"][b])
+        if not (int(h["status"][b]) == 0 and kf == cfg["k"]
+                and np.array_equal(h["freqs"][b, :kf], w[o])):
+            bad.append(b)
+            continue
+        worst = max(worst, float(np.abs(h["coeffs"][b, :kf] - a[o]).max()))
+    _say(f"    rounds {np.mean(h['rounds']):.2f}, failed {bad}, max |a - planted| {worst:.2e}")
+    assert not bad
+    # sigma / sqrt(p_min) with a wide margin: the estimate averages >= 1009 samples
+    assert worst < 10 * cfg["sigma"] / np.sqrt(cfg["p_min"]) * 3
     plan.close()

@@ -188,7 +188,7 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         orig = sig_mod.unwrap_matrix
         monkeypatch.setattr(sig_mod, "unwrap_matrix", lambda d, d1, N: orig(d, d1, N) * N)
     elif mutation == "no_residual":
-        monkeypatch.setattr(mps_mod, "_residual", lambda yR, aR, p, m, n, shift: 0.0)
+        monkeypatch.setattr(mps_mod, "_residual", lambda yR, aR, p, m, n, shift: np.zeros(p, complex))
     elif mutation == "shift_axis":
         orig = sig_mod.sample_points
         monkeypatch.setattr(mps_mod, "sample_points",
@@ -198,3 +198,15 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
     elif mutation == "arg_sign":
         monkeypatch.setattr(mps_mod, "_arg", lambda z: -math.atan2(z.imag, z.real))
     assert not _pins_hold()
+
+
+def test_round_samples_point_subset():
+    """Sampling only some points h gives exactly those columns of the full sets."""
+    w, a = workloads.planted_signal(31, 0, 3, 256, 20, (1.0, 2.0))
+    P = oracle.Params(d=3, N=256, k=20, ladder_K=8)
+    yR = oracle.unwrap(w[:3], 1, 256)
+    aR = a[:3] * 0.5
+    full = oracle.round_samples(w, a, P, 61, 2, 2, yR, aR, sigma=0.1, seed=5, signal=1)
+    hs = np.array([60, 0, 17, 17, 33])
+    part = oracle.round_samples(w, a, P, 61, 2, 2, yR, aR, sigma=0.1, seed=5, signal=1, hs=hs)
+    assert np.array_equal(part, full[:, hs])

@@ -11,7 +11,7 @@ measured single-GPU configurations:
   c3a     d=10, N=65536, k~U{64..1024}, |a|~U[1,2], sigma=1e-3, B=512
   c3b     d=10, N=65536, k=1000, |a|~U[1,2], sigma=1e-3, B=512   (headline)
   c4      d=6,  N=4096,  k=2000, |a|~U[1,2], sigma~U[0,1e-2]  (classifier data)
-  c5      d=20, N=65536, k=4096, |a|~U[1,4], sigma=1e-2, B=64
+  c5      d=20, N=65536, k=4096, |a|~U[1,4], sigma=1e-2, B=64  (p ~ 2k)
   e4      d=20, N=20, d1=4, k=100 (the worked example of Section 4.1)
 """
 from __future__ import annotations
@@ -34,8 +34,10 @@ CONFIGS = {
     "c4": dict(d=6, N=4096, k=2000, B=512, mag=(1.0, 2.0), sigma=(0.0, 1e-2),
                seed=4000, d1=1, c=2.0, ladder_K=64, tau=1e-3, eta=1e-3,
                precision="fp32", p_min=101, robust=True),
+    # c = 1.99: the first prime (8161) keeps the Bluestein length 2p - 1 within
+    # the 16384-point in-LDS FFT
     "c5": dict(d=20, N=65536, k=4096, B=64, mag=(1.0, 4.0), sigma=1e-2,
-               seed=5000, d1=1, c=3.0, ladder_K=256, tau=3e-3, eta=1e-3,
+               seed=5000, d1=1, c=1.99, ladder_K=256, tau=3e-3, eta=1e-3,
                precision="fp32", p_min=1009, robust=True),
     "e4": dict(d=20, N=20, k=100, B=1, mag=(1.0, 1.0), sigma=0.0, seed=6000,
                d1=4, c=5.0, ladder_K=1, tau=1e-6, eta=1e-8, precision="fp64",
