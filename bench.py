@@ -27,21 +27,24 @@ import workloads  # noqa: E402
 
 METRIC = "signal recoveries/sec at exact support, d=10 k=1000; learned vs plain"
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X FP32 vector
 
 
 def algorithmic_flops(trace: np.ndarray, k: np.ndarray, S1: int) -> float:
     """8 flops per exponential-sum term + 5 p log2 p per DFT, summed over rounds and signals.
 
-    Terms of round i: S1 * p_i * (planted modes + registry size entering the round).
+    Terms of round i: sets * p_i * (planted modes + registry size entering the round),
+    sets = S1 for a decoding round and 1 for a verification round.
     """
     total = 0.0
     for b in range(trace.shape[0]):
         nR = 0
         for row in trace[b]:
-            i, kstar, p = int(row[0]), int(row[1]), int(row[2])
+            i, p, verify = int(row[0]), int(row[2]), int(row[7])
             if i == 0:
                 break
-            total += 8.0 * S1 * p * (int(k[b]) + nR) + S1 * 5.0 * p * math.log2(p)
+            sets = 1 if verify else S1
+            total += 8.0 * sets * p * (int(k[b]) + nR) + sets * 5.0 * p * math.log2(p)
             nR = int(row[6])
     return total
 
@@ -71,7 +74,8 @@ def cpu_baseline(cfg, pb, n_sig: int) -> dict:
         w, a = pb.signal(b)
         P = oracle.Params(d=cfg["d"], N=cfg["N"], k=int(pb.k[b]), d1=cfg["d1"], c=cfg["c"],
                           ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
-                          p_min=cfg["p_min"], robust=cfg["robust"])
+                          p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
+                          verify_eta=cfg["verify_eta"])
         r = oracle.multiphaseshift(w, a, P, sigma=float(pb.sigma[b]), seed=pb.seed, signal=b)
         o = np.lexsort(w.T[::-1])
         n_ok += int(r.status == 0 and r.freqs.shape == w.shape and np.array_equal(r.freqs, w[o]))
@@ -101,6 +105,59 @@ def time_recover(sfft, plan, db, B, steps, warmup):
     return out, wall / steps, ev0.elapsed_time(ev1) / steps
 
 
+def components(sfft, plan, pb, db, S1, p, m, steps):
+    """The sampler and the DFT entry points on their own at the first round's shape
+    (all planted modes, no registry): HIP events on the launch stream."""
+    import torch
+    B = pb.B
+    stream = torch.cuda.current_stream()
+    V = torch.zeros((B, S1, p), dtype=torch.complex64, device="cuda")
+    X = V.view(B * S1, p)
+    sfft.sfft_sample_lines(plan, db, 1, p, m, V=V, stream=stream)
+    sfft.sfft_dft(plan, X, stream=stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(steps):
+        sfft.sfft_sample_lines(plan, db, 1, p, m, V=V, stream=stream)
+    ev[1].record(stream)
+    for _ in range(steps):
+        sfft.sfft_dft(plan, X, stream=stream)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    ts = ev[0].elapsed_time(ev[1]) / steps
+    td = ev[1].elapsed_time(ev[2]) / steps
+    terms = float(S1) * p * float(np.sum(pb.k))
+    L = 1 << math.ceil(math.log2(2 * p - 1))
+    n_dft = B * S1
+    alg = n_dft * 5.0 * p * math.log2(p)
+    # executed: two L-point FFTs, the filter and both chirp products per sequence
+    exe = n_dft * (2 * 5.0 * L * math.log2(L) + 6.0 * L + 12.0 * p)
+    return {
+        "shape": f"{B} signals x {S1} sets x {p} points, {int(pb.k[0])} modes, round 1",
+        "sampler": {"kernel": "sample_kernel", "ms": ts, "terms": terms,
+                    "tflops": 8.0 * terms / (ts * 1e-3) / 1e12,
+                    "frac_mfma_fp32": 8.0 * terms / (ts * 1e-3) / 1e12 / PEAK_FP32_MFMA},
+        "dft": {"kernel": "dft_kernel", "ms": td, "bluestein_L": L,
+                "algorithmic_tflops": alg / (td * 1e-3) / 1e12,
+                "executed_tflops": exe / (td * 1e-3) / 1e12,
+                "frac_valu_fp32": exe / (td * 1e-3) / 1e12 / PEAK_FP32_VALU,
+                "hbm_gbs": n_dft * p * 16.0 / (td * 1e-3) / 1e9},
+    }
+
+
+def calibration_copy(mib: int, reps: int = 3):
+    """A plain device copy of known size, for scaling the HBM traffic counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +169,9 @@ def main():
     ap.add_argument("--train-rows", type=int, default=1_000_000)
     ap.add_argument("--cpu-sample", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-components", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain copy of this size (traffic-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); signals are "
@@ -137,9 +197,10 @@ def main():
                 p_min=cfg["p_min"], ladder_K=cfg["ladder_K"], tau=cfg["tau"] or 0.0,
                 eta=cfg["eta"],
                 precision=sfft.SFFT_FP32 if cfg["precision"] == "fp32" else sfft.SFFT_FP64,
-                robust=int(cfg["robust"]))
+                robust=int(cfg["robust"]), verify=int(cfg["verify"]),
+                verify_eta=cfg["verify_eta"] or 0.0)
     kinds = ["plain", "mlp"] if args.classifier == "both" else [args.classifier]
-    results, train_info = {}, None
+    results, train_info, comp = {}, None, None
     for kind in kinds:
         extra = {}
         if kind == "mlp":
@@ -163,7 +224,13 @@ def main():
                              ms_per_step=step_s * 1e3, kernel_ms=gpu_ms,
                              mean_rounds=float(np.mean(h["rounds"])),
                              mean_samples=float(np.mean(h["samples"])), flops=flops)
+        if kind == kinds[0] and not args.no_components:
+            tr0 = h["trace"][0, 0]
+            comp = components(sfft, plan, pb, db, plan.num_sets, int(tr0[2]), int(tr0[3]),
+                              args.steps)
         plan.close()
+    if args.calib_copy_mib > 0:
+        calibration_copy(args.calib_copy_mib)
     # headline: the classifier with the highest exact-support success, then throughput
     best = max(kinds, key=lambda k: (results[k]["success_rate"], results[k]["value"]))
     r = results[best]
@@ -186,7 +253,8 @@ def main():
                         f"sigma={cfg['sigma']} |a|~U{list(cfg['mag'])}",
             "batch": B, "d": cfg["d"], "N": cfg["N"], "k": cfg["k"], "d1": cfg["d1"],
             "c": cfg["c"], "ladder_K": cfg["ladder_K"], "tau": cfg["tau"], "eta": cfg["eta"],
-            "p_min": cfg["p_min"], "classifier": best,
+            "p_min": cfg["p_min"], "verify": cfg["verify"], "verify_eta": cfg["verify_eta"],
+            "classifier": best,
             "parallelism": "one GPU, one work-group per signal",
         },
         "success_rate": r["success_rate"],
@@ -207,6 +275,8 @@ def main():
             "algorithmic_flops_per_launch": r["flops"],
         },
     }
+    if comp is not None:
+        line["components"] = comp
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, pb, min(args.cpu_sample, B))
     print(json.dumps(line), flush=True)

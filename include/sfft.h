@@ -39,6 +39,8 @@ typedef struct sfft_plan_s* sfft_plan;
 typedef enum {
   SFFT_OK = 0,
   SFFT_NOT_CONVERGED = 1, /* per-signal: max_rounds reached with |R| < k          */
+  SFFT_RESIDUAL_NONZERO = 2, /* per-signal: |R| = k but the last verification round
+                                still found residual energy (verify = 1)          */
   SFFT_EINVAL = -1,       /* invalid argument (see sfft_last_error())             */
   SFFT_ERANGE = -2,       /* sizes beyond what the plan or the device supports    */
   SFFT_ENOMEM = -3,       /* device allocation failed                             */
@@ -88,6 +90,13 @@ typedef struct {
   const void* mlp_weights; /* device, SFFT_MLP_PARAMS BF16 values; NULL with PLAIN      */
   double mlp_threshold;    /* acceptance threshold on the probability, (0, 1)          */
   double feature_scale;    /* s of the features; <= 0 means s = tau                    */
+  int32_t verify;          /* 1: verification round when |R| reaches k (not in the
+                              paper): the residual is sampled once on the tilted line
+                              t_h = (h/p) U v, v_n = q^(n-1) mod p, q = 1 + (i mod
+                              (p-1)), p the round-i prime for k* = 1, and transformed;
+                              buckets with |F[h]|/p >= verify_eta send the loop on with
+                              k* = their count.  0: stop at |R| = k (the listing)     */
+  double verify_eta;       /* residual-energy floor of the verification; <= 0: eta     */
 } sfft_params;
 
 /* A batch of synthetic black-box signals with planted spectra.  All pointers
@@ -107,14 +116,17 @@ typedef struct {
   uint64_t seed;            /* noise key material                                 */
 } sfft_signal_batch;
 
-#define SFFT_TRACE_W 8 /* per round: i, k*, p, m, candidates, accepted, |R|, 0 */
+#define SFFT_TRACE_W 8 /* per round: i, k*, p, m, candidates, accepted, |R|, verify;
+                          a verification row has k* = 0, m = 0, candidates = buckets
+                          with residual energy, verify = 1 */
 
 /* Outputs of sfft_recover (device pointers; the optional ones may be NULL). */
 typedef struct {
   int64_t* freqs;    /* [B][k_max][d] recovered w, lexicographic order, zero-padded */
   double* coeffs;    /* [B][k_max][2] recovered a (re, im), same order              */
-  int32_t* k_found;  /* [B] number of modes written (|R| at the end)                */
-  int32_t* status;   /* [B] SFFT_OK or SFFT_NOT_CONVERGED (or SFFT_ERANGE)          */
+  int32_t* k_found;  /* [B] number of modes written: min(|R| at the end, k_max)    */
+  int32_t* status;   /* [B] SFFT_OK, SFFT_NOT_CONVERGED, SFFT_RESIDUAL_NONZERO
+                      * (or SFFT_ERANGE)                                          */
   int32_t* rounds;   /* [B] rounds run (optional)                                   */
   int64_t* samples;  /* [B] signal samples taken (optional)                         */
   int32_t* trace;    /* [B][max_rounds][SFFT_TRACE_W] per-round record (optional);

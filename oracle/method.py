@@ -32,7 +32,7 @@ from .philox import sample_noise
 from .primes import ith_prime_at_least
 from .signal import evaluate, sample_points
 from .classifier import bf16_round, bucket_features, bucket_label, prob_single
-from .unwrapping import unwrap, wrap, y_range
+from .unwrapping import unwrap, unwrap_matrix, wrap, y_range
 
 READINGS = {
     "R1": "Phaseshift listing labels the shifted and unshifted sample vectors the other "
@@ -68,6 +68,15 @@ READINGS = {
     "R21": "Learned classifier (not in the paper): accept iff the network's singleton "
            "probability on the 8 bucket features exceeds a threshold and the decode is valid; "
            "the plain ratio test of eq. (42) is the fallback.",
+    "R14": "Verification (not in the paper, which stops at |R| = k): when |R| reaches k, "
+           "round i samples the residual once along the tilted line t_h = (h/p) U v, "
+           "v_n = q^(n-1) mod p, q = 1 + (i mod (p-1)), p the round's prime for k* = 1 "
+           "(every unwrapped coordinate enters the bucket index, so residual modes rarely "
+           "share a bucket), and transforms it; if some bucket has |F[h]|/p >= verify_eta "
+           "the next round runs with k* = min(that count, k, k + max(16, ceil(k/8)) - |R|), "
+           "so the registry never exceeds k + max(16, ceil(k/8)) entries; when that is 0, or "
+           "the round cap ends the loop before a clean check, or |R| > k at the end, the "
+           "status is RESIDUAL_NONZERO.",
     "R19": "Noise (not in the paper): sigma/sqrt(2) (g1 + i g2) per sample from "
            "Philox4x64-10, key (seed, signal), counter (h // 2, set, round, 0), output "
            "words 0, 1 for even h and 2, 3 for odd h.",
@@ -75,6 +84,7 @@ READINGS = {
 
 STATUS_OK = 0
 STATUS_NOT_CONVERGED = 1
+STATUS_RESIDUAL_NONZERO = 2
 
 
 @dataclass
@@ -96,6 +106,8 @@ class Params:
     mlp_params: np.ndarray | None = None
     mlp_threshold: float = 0.5
     feature_scale: float | None = None  # None: tau_eff
+    verify: bool = False               # R14
+    verify_eta: float | None = None    # None: eta
 
     @property
     def d2(self) -> int:
@@ -166,6 +178,21 @@ def _residual(yR, aR, p, m, n, shift):
     ph = np.outer(h / p, yR[:, m - 1].astype(np.float64))
     ph = ph + shift * yR[:, n - 1].astype(np.float64)[None, :]
     return np.exp(2j * np.pi * ph) @ aR
+
+
+def verify_samples(freqs, coeffs, P: Params, p: int, q: int, i: int, yR, aR,
+                   sigma: float = 0.0, seed: int = 0, signal: int = 0) -> np.ndarray:
+    """R14: residual samples f(t_h) + noise - g(t_h) on the tilted line
+    t_h = (h/p) U v, v_n = q^(n-1) mod p, h = 0..p-1 (noise of set 0, round i)."""
+    v = np.array([pow(int(q), n, int(p)) for n in range(P.d2)], dtype=np.int64)
+    direction = unwrap_matrix(P.d, P.d1, P.N).astype(np.float64) @ v.astype(np.float64)
+    h = np.arange(p)
+    t = (h.astype(np.float64) / p)[:, None] * direction[None, :]
+    out = evaluate(freqs, coeffs, t) + sample_noise(seed, signal, i, 0, h, sigma)
+    if len(aR):
+        ph = np.outer(h.astype(np.float64) / p, (np.asarray(yR) @ v).astype(np.float64))
+        out = out - np.exp(2j * np.pi * ph) @ np.asarray(aR)
+    return out
 
 
 def _plain_test(F, h, p, P: Params) -> bool:
@@ -262,10 +289,38 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
     trace, spectra, registry = [], [], []
     samples = 0
     i = 1
-    while len(R) < P.k and i <= P.max_rounds:              # R13
-        kstar = P.k - len(R)
-        p = ith_prime_at_least(max(math.ceil(P.c * kstar), P.p_min), i,
-                               smooth=(P.prime_rule == "smooth"))
+    k_next = 0          # k* of the round after a verification that found residual energy
+    verified = False
+    smooth = P.prime_rule == "smooth"
+    while i <= P.max_rounds:                               # R13
+        if len(R) >= P.k and k_next == 0:
+            if not P.verify or verified:
+                break
+            # R14: is the residual empty?  One tilted line, prime for k* = 1.
+            p = ith_prime_at_least(max(math.ceil(P.c), P.p_min), i, smooth=smooth)
+            q = 1 + (i % (p - 1))
+            yR = np.array(list(R.keys()), dtype=np.int64).reshape(-1, d2)
+            aR = np.array(list(R.values()), dtype=np.complex128)
+            F0 = dft(verify_samples(freqs, coeffs, P, p, q, i, yR, aR, sigma=sigma,
+                                    seed=seed, signal=signal))
+            samples += p
+            veta = P.eta if P.verify_eta is None else P.verify_eta
+            n_res = int(np.count_nonzero(np.abs(F0) / p >= veta))
+            trace.append(dict(i=i, kstar=0, p=p, m=0, n_cand=n_res, n_acc=0, n_R=len(R),
+                              verify=1))
+            i += 1
+            if n_res == 0:
+                verified = True
+                continue
+            # the registry may grow past k by at most `extra` entries while it is repaired
+            extra = max(16, math.ceil(P.k / 8))
+            k_next = min(n_res, P.k, P.k + extra - len(R))
+            if k_next <= 0:
+                break
+            continue
+        kstar = P.k - len(R) if len(R) < P.k else k_next
+        k_next = 0
+        p = ith_prime_at_least(max(math.ceil(P.c * kstar), P.p_min), i, smooth=smooth)
         m = (i % d2) + 1
         snapshot = (np.array(list(R.keys()), dtype=np.int64).reshape(-1, d2),
                     np.array(list(R.values()), dtype=np.complex128))
@@ -295,12 +350,17 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
             R[y] = R.get(y, 0.0) + a
         R = {y: a for y, a in R.items() if abs(a) >= P.eta}              # R8
         trace.append(dict(i=i, kstar=kstar, p=p, m=m, n_cand=len(cand),
-                          n_acc=len(accepted), n_R=len(R)))
+                          n_acc=len(accepted), n_R=len(R), verify=0))
         if keep_spectra:
             spectra.append(np.array(F))
             registry.append(snapshot)
         i += 1
-    status = STATUS_OK if len(R) >= P.k else STATUS_NOT_CONVERGED
+    if len(R) < P.k:
+        status = STATUS_NOT_CONVERGED
+    elif len(R) > P.k or (P.verify and not verified):
+        status = STATUS_RESIDUAL_NONZERO
+    else:
+        status = STATUS_OK
     if R:
         ys = np.array(list(R.keys()), dtype=np.int64).reshape(-1, d2)
         a = np.array(list(R.values()), dtype=np.complex128)

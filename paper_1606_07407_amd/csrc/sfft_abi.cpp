@@ -95,6 +95,8 @@ static sfft_status validate_params(const sfft_params* p) {
       return fail(SFFT_EINVAL, "mlp_threshold must be in (0, 1)");
   }
   if (!std::isfinite(p->feature_scale)) return fail(SFFT_EINVAL, "feature_scale must be finite");
+  if (p->verify != 0 && p->verify != 1) return fail(SFFT_EINVAL, "verify must be 0 or 1");
+  if (!std::isfinite(p->verify_eta)) return fail(SFFT_EINVAL, "verify_eta must be finite");
   return SFFT_OK;
 }
 
@@ -127,7 +129,8 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.NB = 1;
   for (int r = 0; r < P.d1; ++r) kp.NB *= P.N;
   kp.k_max = P.k_max;
-  kp.cap = P.k_max;
+  // registry capacity: k_max, plus the repair slack of the verification round
+  kp.cap = P.k_max + (P.verify ? std::max(16, (P.k_max + 7) / 8) : 0);
   kp.pairs_max = (kp.k_max + 1) / 2 + (kp.cap + 1) / 2;
   kp.m_max = 2 * kp.pairs_max;
   kp.max_rounds = P.max_rounds;
@@ -144,6 +147,8 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.mlp_w = (const uint16_t*)P.mlp_weights;
   kp.mlp_thr = P.mlp_threshold;
   kp.feat_scale = (P.feature_scale > 0.0) ? P.feature_scale : kp.tau;
+  kp.verify = P.verify;
+  kp.verify_eta = (P.verify_eta > 0.0) ? P.verify_eta : P.eta;
 
   // Largest prime a round can use: the max_rounds-th rule prime >= max(ceil(c k_max), p_min),
   // clamped to what the in-LDS DFT holds (Bluestein length 2p - 1 <= maxL).  A round that
@@ -191,6 +196,8 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
   lds = std::max(lds, decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max);  // decode / export
   lds = std::max(lds, 4 * (size_t)kp.k_max);                             // output
+  lds = std::max(lds, align16((size_t)kp.p_max * cs) + align16(2 * (size_t)(kp.m_max + 4)) +
+                          (size_t)kp.m_max * cs + (size_t)kWG * 16);     // verification
   const size_t merge_bytes = merge_lds(kp.k_max, kp.cap).bytes;
   kp.merge_global = merge_bytes > lds ? 1 : 0;
   if (!kp.merge_global) lds = merge_bytes > lds ? merge_bytes : lds;

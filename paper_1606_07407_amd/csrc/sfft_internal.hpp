@@ -85,6 +85,8 @@ struct KParams {
   int n_slots;
   int lds_bytes;
   int merge_global;       // 1: the merge/sort arrays live in the slot, not in LDS
+  int verify;             // verification round when |R| reaches k
+  double verify_eta;
 };
 
 struct KBatch {

@@ -107,6 +107,7 @@ __device__ __forceinline__ int lexcmp(const int64_t* a, const int64_t* b, int n)
 // Shared per-work-group scalars.
 struct WgState {
   int sig, k, M_pl, nR, cur, i, p, m0, kstar, ncand, nacc, status, L, log2L, nU, flag;
+  int kv, verified;  // k* after a verification that found residual energy; clean check
   int64_t off, samples;
   double sigma;
   uint64_t prefix;
@@ -224,6 +225,82 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   }
   __syncthreads();
   add_noise<T>(V, vstride, p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
+  __syncthreads();
+}
+
+// Verification samples (the check at |R| = k): the residual, planted modes
+// minus registry, on the tilted line t_h = (h/p) U v, v_n = q^(n-1) mod p, so
+// the bucket of a mode is (y . v) mod p, exact in integers:
+//   V[h] = sum_j C[j][0] omega_p^{(h r_j) mod p} - sum_e a_e omega_p^{(h r_e) mod p},
+// then noise (set 0 of round st.i) and the DFT of that one sequence.  Writes
+// the number of buckets with |F[h]| >= verify_eta p to st.ncand.
+template <typename T>
+__device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, WgState& st,
+                            char* lds, cpx<T>* V, int* sh_part) {
+  const int p = st.p, d2 = kp.d2;
+  const int M = st.M_pl + st.nR;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
+  uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
+  cpx<T>* coef = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(rr) +
+                                           align16(2 * (size_t)(kp.m_max + 4)));
+  cpx<T>* part = coef + kp.m_max;
+  const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
+  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
+  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[st.cur]);
+  const cpx<T>* cc = ws_cpx<T>(slot, kp.lay.ccomp);
+  const int64_t q = 1 + (st.i % (p - 1));
+  for (int x = threadIdx.x; x < p; x += kWG) {
+    double c, sn;
+    expipi(2.0 * (double)x / (double)p, &c, &sn);
+    tw[x] = cmk<T>((T)c, (T)sn);
+  }
+  for (int j = threadIdx.x; j < M; j += kWG) {
+    const int64_t* y = (j < st.M_pl) ? ypl + (size_t)j * d2 : ry + (size_t)(j - st.M_pl) * d2;
+    int64_t r = 0, v = 1;
+    for (int n = 0; n < d2; ++n) {
+      r = (r + v * pmod64(y[n], p)) % p;
+      v = (v * q) % p;
+    }
+    rr[j] = (uint16_t)r;
+    if (j < st.M_pl) {
+      coef[j] = cc[(size_t)j * kp.S1];
+    } else {
+      const double2 a = ra[j - st.M_pl];
+      coef[j] = cmk<T>((T)-a.x, (T)-a.y);
+    }
+  }
+  __syncthreads();
+  // G threads per point when p is small; partial sums reduced through LDS
+  const int G = (p < kWG) ? kWG / p : 1;
+  const float inv_p = 1.0f / (float)p;
+  for (int t = threadIdx.x; t < G * p; t += kWG) {
+    const int h = t % p, g = t / p;
+    cpx<T> acc = cmk<T>(0, 0);
+    for (int j = g; j < M; j += G)
+      acc = cadd(acc, cmul(coef[j], tw[mulmod((uint32_t)h, (uint32_t)rr[j], p, inv_p)]));
+    if (G == 1)
+      V[h] = acc;
+    else
+      part[g * p + h] = acc;
+  }
+  __syncthreads();
+  if (G > 1) {
+    for (int h = threadIdx.x; h < p; h += kWG) {
+      cpx<T> acc = part[h];
+      for (int g = 1; g < G; ++g) acc = cadd(acc, part[g * p + h]);
+      V[h] = acc;
+    }
+    __syncthreads();
+  }
+  add_noise<T>(V, kp.vstride, p, 1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
+  __syncthreads();
+  dft_round<T>(kp, slot, st, lds, V, kp.vstride, 1);
+  const double thr = kp.verify_eta * (double)p;
+  int cnt = 0;
+  for (int h = threadIdx.x; h < p; h += kWG)
+    cnt += (hypot((double)V[h].x, (double)V[h].y) >= thr) ? 1 : 0;
+  const int tot = block_sum(cnt, sh_part);
+  if (threadIdx.x == 0) st.ncand = tot;
   __syncthreads();
 }
 
@@ -849,7 +926,7 @@ __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgSt
     for (int e = (st.i - 1) * 8 + threadIdx.x; e < kp.max_rounds * 8; e += kWG) tr[e] = 0;
   }
   if (threadIdx.x == 0) {
-    ko.k_found[st.sig] = nR;
+    ko.k_found[st.sig] = nOut;
     ko.status[st.sig] = st.status;
     if (ko.rounds) ko.rounds[st.sig] = st.i - 1;
     if (ko.samples) ko.samples[st.sig] = st.samples;
@@ -904,10 +981,17 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
       __syncthreads();
     }
     if (ko.feat) export_sort_planted(kp, slot, st, lds);
-    while (st.nR < st.k && st.i <= kp.max_rounds) {
+    if (threadIdx.x == 0) {
+      st.kv = 0;
+      st.verified = 0;
+    }
+    __syncthreads();
+    while (st.i <= kp.max_rounds) {
+      const bool at_k = st.nR >= st.k && st.kv == 0;
+      if (at_k && (!kp.verify || st.verified)) break;
       if (threadIdx.x == 0) {
-        st.kstar = st.k - st.nR;
-        st.p = prime_for_round(kp, st.kstar, st.i);
+        st.kstar = at_k ? 0 : (st.nR < st.k ? st.k - st.nR : st.kv);
+        st.p = prime_for_round(kp, at_k ? 1 : st.kstar, st.i);
         st.m0 = st.i % kp.d2;
         if (st.p < 2 || st.p > kp.p_max) {
           st.flag = 1;
@@ -926,6 +1010,38 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
         if (threadIdx.x == 0) st.status = -2;  // SFFT_ERANGE
         __syncthreads();
         break;
+      }
+      if (at_k) {
+        verify_round<T>(kp, kb, slot, st, lds, V, sh_part);
+        if (threadIdx.x == 0) {
+          st.samples += st.p;
+          if (ko.trace) {
+            int32_t* tr = ko.trace + ((size_t)st.sig * kp.max_rounds + (st.i - 1)) * 8;
+            tr[0] = st.i;
+            tr[1] = 0;
+            tr[2] = st.p;
+            tr[3] = 0;
+            tr[4] = st.ncand;
+            tr[5] = 0;
+            tr[6] = st.nR;
+            tr[7] = 1;
+          }
+          st.i += 1;
+          if (st.ncand == 0) {
+            st.verified = 1;
+          } else {
+            // the registry grows past k by at most max(16, ceil(k/8)) while repaired
+            const int room = st.k + max(16, (st.k + 7) / 8) - st.nR;
+            st.kv = min(min(st.ncand, st.k), room);
+            if (st.kv <= 0) {
+              st.kv = 0;
+              st.flag = 2;  // no room: stop with RESIDUAL_NONZERO
+            }
+          }
+        }
+        __syncthreads();
+        if (st.flag) break;
+        continue;
       }
       registry_operands<T>(kp, slot, st, P0);
       sample_round<T, RT>(kp, kb, slot, st, P0, lds, V, vstride);
@@ -948,11 +1064,13 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
           tr[6] = st.nR;
           tr[7] = 0;
         }
+        st.kv = 0;
         st.i += 1;
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0 && st.status == 0) st.status = (st.nR >= st.k) ? 0 : 1;
+    if (threadIdx.x == 0 && st.status == 0)
+      st.status = (st.nR < st.k) ? 1 : (st.nR > st.k || (kp.verify && !st.verified)) ? 2 : 0;
     __syncthreads();
     write_output(kp, ko, slot, st, lds);
   }

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsfft.so")
 
-SFFT_OK, SFFT_NOT_CONVERGED = 0, 1
+SFFT_OK, SFFT_NOT_CONVERGED, SFFT_RESIDUAL_NONZERO = 0, 1, 2
 SFFT_EINVAL, SFFT_ERANGE, SFFT_ENOMEM, SFFT_EDEVICE = -1, -2, -3, -4
 SFFT_PRIME_PAPER, SFFT_PRIME_SMOOTH = 0, 1
 SFFT_FP64, SFFT_FP32 = 0, 1
@@ -42,6 +42,8 @@ class sfft_params(ctypes.Structure):
         ("robust", ctypes.c_int32), ("classifier", ctypes.c_int32),
         ("mlp_weights", ctypes.c_void_p), ("mlp_threshold", ctypes.c_double),
         ("feature_scale", ctypes.c_double),
+        ("verify", ctypes.c_int32),
+        ("verify_eta", ctypes.c_double),
     ]
 
 
@@ -152,12 +154,15 @@ class Params:
     mlp_weights: object = None      # device tensor of SFFT_MLP_PARAMS bfloat16 values
     mlp_threshold: float = 0.5
     feature_scale: float = 0.0
+    verify: int = 0
+    verify_eta: float = 0.0
 
     def to_c(self) -> sfft_params:
         return sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
                            self.p_min, self.ladder_K, self.tau, self.tau_noise, self.eta,
                            self.max_rounds, self.precision, self.robust, self.classifier,
-                           _ptr(self.mlp_weights), self.mlp_threshold, self.feature_scale)
+                           _ptr(self.mlp_weights), self.mlp_threshold, self.feature_scale,
+                           self.verify, self.verify_eta)
 
 
 class Plan:

@@ -49,7 +49,8 @@ def _plan(cfg, k_max, B, **over):
     sfft = _sfft()
     kw = dict(d=cfg["d"], N=cfg["N"], k_max=k_max, d1=cfg["d1"], c=cfg["c"],
               p_min=cfg["p_min"], ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
-              precision=sfft.SFFT_FP32, robust=int(cfg["robust"]))
+              precision=sfft.SFFT_FP32, robust=int(cfg["robust"]), verify=int(cfg["verify"]),
+              verify_eta=cfg["verify_eta"] or 0.0)
     kw.update(over)
     return sfft.sfft_plan_create(sfft.Params(**kw), max_batch=B)
 
@@ -57,7 +58,7 @@ def _plan(cfg, k_max, B, **over):
 def _oracle_params(cfg, k, **over):
     kw = dict(d=cfg["d"], N=cfg["N"], k=int(k), d1=cfg["d1"], c=cfg["c"],
               ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"], p_min=cfg["p_min"],
-              robust=cfg["robust"])
+              robust=cfg["robust"], verify=cfg["verify"], verify_eta=cfg["verify_eta"])
     kw.update(over)
     return oracle.Params(**kw)
 
@@ -182,7 +183,7 @@ def test_train_then_learned_recovery():
         assert np.array_equal(out["freqs"][b, :kf], ref.freqs)
         tr = out["trace"][b, :ref.rounds]
         want = np.array([[t["i"], t["kstar"], t["p"], t["m"], t["n_cand"], t["n_acc"],
-                          t["n_R"], 0] for t in ref.trace])
+                          t["n_R"], t["verify"]] for t in ref.trace])
         assert np.array_equal(tr, want)
     plan.close()
 

@@ -47,13 +47,15 @@ def _params(cfg, k_max, precision=None):
                        p_min=cfg["p_min"], ladder_K=cfg["ladder_K"],
                        tau=(cfg["tau"] or 0.0), eta=cfg["eta"], max_rounds=cfg.get("max_rounds", 64),
                        precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64,
-                       robust=int(cfg["robust"]))
+                       robust=int(cfg["robust"]), verify=int(cfg["verify"]),
+                       verify_eta=cfg["verify_eta"] or 0.0)
 
 
 def _oracle_params(cfg, k):
     return oracle.Params(d=cfg["d"], N=cfg["N"], k=int(k), d1=cfg["d1"], c=cfg["c"],
                          ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
-                         p_min=cfg["p_min"], robust=cfg["robust"],
+                         p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
+                         verify_eta=cfg["verify_eta"],
                          max_rounds=cfg.get("max_rounds", 64))
 
 
@@ -184,7 +186,7 @@ def _compare(cfg, pb, h, rel_tol, check_trace=True, signals=None):
         if check_trace:
             tr = h["trace"][b, :ref.rounds]
             want = np.array([[t["i"], t["kstar"], t["p"], t["m"], t["n_cand"], t["n_acc"],
-                              t["n_R"], 0] for t in ref.trace])
+                              t["n_R"], t["verify"]] for t in ref.trace])
             assert np.array_equal(tr, want), (b, tr, want)
     return max(res) if res else 0.0
 

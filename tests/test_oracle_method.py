@@ -210,3 +210,43 @@ def test_round_samples_point_subset():
     hs = np.array([60, 0, 17, 17, 33])
     part = oracle.round_samples(w, a, P, 61, 2, 2, yR, aR, sigma=0.1, seed=5, signal=1, hs=hs)
     assert np.array_equal(part, full[:, hs])
+
+
+def test_verification_line_closed_form():
+    """R14 samples: their DFT is p times the residual's bucket sums, bucket of a
+    mode = (y . v) mod p with v_n = q^(n-1) mod p (eq. (3) on the tilted line)."""
+    w, a = workloads.planted_signal(41, 0, 4, 64, 40, (1.0, 2.0))
+    P = oracle.Params(d=4, N=64, k=40, d1=2)
+    y = oracle.unwrap(w, 2, 64)
+    yR = np.vstack([y[:5], y[:1] + np.array([1, 0])])      # 5 exact entries + 1 wrong one
+    aR = np.concatenate([a[:5] * 0.75, [0.3 + 0.1j]])
+    p, q = 101, 7
+    F = np.fft.fft(oracle.method.verify_samples(w, a, P, p, q, 3, yR, aR))
+    v = np.array([1, q], dtype=np.int64)
+    want = np.zeros(p, complex)
+    np.add.at(want, (y @ v) % p, a)
+    np.add.at(want, (yR @ v) % p, -aR)
+    assert np.abs(F / p - want).max() < 1e-9
+
+
+def test_verification_catches_false_accepts():
+    """R14 as the judge: with the ratio test switched off (tau = 10 accepts every
+    in-band decode) and c = 1.5, the plain loop ends at |R| = k with wrong entries
+    and status OK; with verification every OK result is the planted spectrum."""
+    silent_wrong = exact_verified = 0
+    for seed in range(8):
+        w, a = workloads.planted_signal(800 + seed, 0, 3, 64, 30, (1.0, 2.0))
+        o = np.lexsort(w.T[::-1])
+        for verify in (False, True):
+            P = oracle.Params(d=3, N=64, k=30, c=1.5, tau=10.0, verify=verify,
+                              verify_eta=1e-2)
+            r = oracle.multiphaseshift(w, a, P)
+            exact = r.freqs.shape == w.shape and np.array_equal(r.freqs, w[o])
+            if verify:
+                assert exact or r.status != oracle.method.STATUS_OK, seed
+                exact_verified += int(exact)
+                if exact:   # the run ends with one clean verification row
+                    assert r.trace[-1]["verify"] == 1 and r.trace[-1]["n_cand"] == 0
+            else:
+                silent_wrong += int(r.status == oracle.method.STATUS_OK and not exact)
+    assert silent_wrong >= 4 and exact_verified >= 6

@@ -27,18 +27,22 @@ CONFIGS = {
                p_min=0, robust=False),
     "c3a": dict(d=10, N=65536, k=(64, 1024), B=512, mag=(1.0, 2.0), sigma=1e-3,
                 seed=3000, d1=1, c=3.0, ladder_K=1024, tau=1e-3, eta=1e-3,
-                precision="fp32", p_min=101, robust=True),
+                precision="fp32", p_min=101, robust=True, verify=True,
+                verify_eta=1e-2),
     "c3b": dict(d=10, N=65536, k=1000, B=512, mag=(1.0, 2.0), sigma=1e-3,
                 seed=3100, d1=1, c=3.0, ladder_K=1024, tau=1e-3, eta=1e-3,
-                precision="fp32", p_min=101, robust=True),
+                precision="fp32", p_min=101, robust=True, verify=True,
+                verify_eta=1e-2),
     "c4": dict(d=6, N=4096, k=2000, B=512, mag=(1.0, 2.0), sigma=(0.0, 1e-2),
                seed=4000, d1=1, c=2.0, ladder_K=64, tau=1e-3, eta=1e-3,
-               precision="fp32", p_min=101, robust=True),
+               precision="fp32", p_min=101, robust=True, verify=True,
+                verify_eta=1e-2),
     # c = 1.99: the first prime (8161) keeps the Bluestein length 2p - 1 within
     # the 16384-point in-LDS FFT
     "c5": dict(d=20, N=65536, k=4096, B=64, mag=(1.0, 4.0), sigma=1e-2,
                seed=5000, d1=1, c=1.99, ladder_K=256, tau=3e-3, eta=1e-3,
-               precision="fp32", p_min=1009, robust=True),
+               precision="fp32", p_min=1009, robust=True, verify=True,
+               verify_eta=1e-2),
     "e4": dict(d=20, N=20, k=100, B=1, mag=(1.0, 1.0), sigma=0.0, seed=6000,
                d1=4, c=5.0, ladder_K=1, tau=1e-6, eta=1e-8, precision="fp64",
                p_min=0, robust=False),
@@ -47,7 +51,8 @@ CONFIGS = {
 
 def config(name: str, **over):
     """A copy of the named recipe with fields overridden by keyword."""
-    cfg = copy.deepcopy(CONFIGS[name])
+    cfg = dict(verify=False, verify_eta=None)
+    cfg.update(copy.deepcopy(CONFIGS[name]))
     cfg.update(over)
     cfg["name"] = name
     return cfg
