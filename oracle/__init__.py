@@ -16,7 +16,10 @@ Parity pins (tests under tests/test_oracle_*.py): closed forms of eqs. (3)
 and (41), a brute-force O(p^2) DFT, exhaustive unwrap/wrap bijections, the
 k = 1 special case, brute-force d-dimensional DFTs on tiny full grids, exact
 recovery of planted spectra, the d = 1 reduction to Phaseshift, per-round
-isolation statistics, and the Philox known-answer vector.
+isolation statistics, the Philox known-answer vector, the closed form of the
+verification line (R14) and the false-accept experiment it is there for; the
+learned classifier (classifier.py) is pinned by finite differences, a
+hand-computed network and the feature definitions.
 """
 from .primes import is_prime, ith_prime_at_least, primes_upto
 from .unwrapping import unwrap_matrix, unwrap, wrap, y_range
