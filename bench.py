@@ -87,6 +87,35 @@ def cpu_baseline(cfg, pb, n_sig: int) -> dict:
                       f"{dt:.1f} s, {n_ok}/{n_sig} exact"}
 
 
+def sources_sha256() -> str:
+    """Hash of the device sources and the ABI header (identifies the profiled build)."""
+    import hashlib
+    h = hashlib.sha256()
+    files = [os.path.join(ROOT, "include", "sfft.h")]
+    csrc = os.path.join(ROOT, "paper_1606_07407_amd", "csrc")
+    files += sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
+                    if f.endswith((".hip", ".hpp", ".cpp")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per recover_kernel launch from the committed counter summary, or None
+    when that summary was taken on other sources than the current ones."""
+    path = os.path.join(ROOT, "profiles", f"recover_kernel_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-record:"):
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("sources_sha256") != sources_sha256():
+                return None
+            return float(kv["read_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
 def time_recover(sfft, plan, db, B, steps, warmup):
     import torch
     out = sfft.alloc_outputs(plan, B)
@@ -269,7 +298,8 @@ def main():
             "peak": PEAK_FP32_MFMA,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_MFMA,
-            "traffic": None,
+            "traffic": profiled_traffic(args.config) if best == "plain" else None,
+            "traffic_unit": "bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
             "kernel": f"recover_kernel (persistent, whole recovery, {best} classifier)",
             "kernel_ms": r["kernel_ms"],
             "algorithmic_flops_per_launch": r["flops"],
