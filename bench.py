@@ -30,11 +30,14 @@ PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X FP32 vector
 
 
-def algorithmic_flops(trace: np.ndarray, k: np.ndarray, S1: int) -> float:
-    """8 flops per exponential-sum term + 5 p log2 p per DFT, summed over rounds and signals.
+def algorithmic_flops(trace: np.ndarray, k: np.ndarray, S1: int, residual: int = 0) -> float:
+    """Work of the method as run, summed over rounds and signals: 8 flops per
+    (sample, mode) term of the exponential sums, 5 p log2 p per length-p DFT, and
+    8 flops per (registry entry, set) of the spectrum-domain subtraction.
 
-    Terms of round i: sets * p_i * (planted modes + registry size entering the round),
-    sets = S1 for a decoding round and 1 for a verification round.
+    Round i with p_i and |R_i| entering: sets = S1 (1 for a verification round);
+    planted terms sets p_i k; registry terms sets p_i |R_i| when the residual is
+    subtracted from the samples (residual = 1), else sets |R_i| subtraction terms.
     """
     total = 0.0
     for b in range(trace.shape[0]):
@@ -44,7 +47,11 @@ def algorithmic_flops(trace: np.ndarray, k: np.ndarray, S1: int) -> float:
             if i == 0:
                 break
             sets = 1 if verify else S1
-            total += 8.0 * sets * p * (int(k[b]) + nR) + sets * 5.0 * p * math.log2(p)
+            total += 8.0 * sets * p * int(k[b]) + sets * 5.0 * p * math.log2(p)
+            if verify or residual == 1:
+                total += 8.0 * sets * p * nR
+            else:
+                total += 8.0 * sets * nR
             nR = int(row[6])
     return total
 
@@ -227,7 +234,7 @@ def main():
                 eta=cfg["eta"],
                 precision=sfft.SFFT_FP32 if cfg["precision"] == "fp32" else sfft.SFFT_FP64,
                 robust=int(cfg["robust"]), verify=int(cfg["verify"]),
-                verify_eta=cfg["verify_eta"] or 0.0)
+                verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]))
     kinds = ["plain", "mlp"] if args.classifier == "both" else [args.classifier]
     results, train_info, comp = {}, None, None
     for kind in kinds:
@@ -248,7 +255,7 @@ def main():
         out, step_s, gpu_ms = time_recover(sfft, plan, db, B, args.steps, args.warmup)
         h = sfft.outputs_to_host(out)
         ok = exact_support(pb, h)
-        flops = algorithmic_flops(h["trace"], pb.k, plan.num_sets)
+        flops = algorithmic_flops(h["trace"], pb.k, plan.num_sets, int(cfg["residual"]))
         results[kind] = dict(value=int(ok.sum()) / step_s, success_rate=float(ok.mean()),
                              ms_per_step=step_s * 1e3, kernel_ms=gpu_ms,
                              mean_rounds=float(np.mean(h["rounds"])),
@@ -257,6 +264,19 @@ def main():
             tr0 = h["trace"][0, 0]
             comp = components(sfft, plan, pb, db, plan.num_sets, int(tr0[2]), int(tr0[3]),
                               args.steps)
+        plan.close()
+    # the listing's residual step (registry subtracted from the samples on the matrix
+    # cores), same launch, plain classifier
+    if not args.no_components:
+        plan = sfft.sfft_plan_create(sfft.Params(**dict(base, residual=1)), max_batch=B)
+        out, step_s, gpu_ms = time_recover(sfft, plan, db, B, args.steps, args.warmup)
+        h = sfft.outputs_to_host(out)
+        ok = exact_support(pb, h)
+        results["plain_residual_from_samples"] = dict(
+            value=int(ok.sum()) / step_s, success_rate=float(ok.mean()), ms_per_step=step_s * 1e3,
+            kernel_ms=gpu_ms, mean_rounds=float(np.mean(h["rounds"])),
+            mean_samples=float(np.mean(h["samples"])),
+            flops=algorithmic_flops(h["trace"], pb.k, plan.num_sets, 1))
         plan.close()
     if args.calib_copy_mib > 0:
         calibration_copy(args.calib_copy_mib)
@@ -290,7 +310,7 @@ def main():
         "mean_rounds": r["mean_rounds"],
         "mean_samples": r["mean_samples"],
         "learned_vs_plain": {k: {kk: v for kk, v in results[k].items() if kk != "flops"}
-                             for k in kinds},
+                             for k in results},
         "classifier_training": train_info,
         "roofline": {
             "bound": "mfma",

@@ -50,6 +50,7 @@ typedef enum {
 enum { SFFT_PRIME_PAPER = 0, SFFT_PRIME_SMOOTH = 1 };
 enum { SFFT_FP64 = 0, SFFT_FP32 = 1 };
 enum { SFFT_CLS_PLAIN = 0, SFFT_CLS_MLP = 1 };
+enum { SFFT_RESIDUAL_SPECTRUM = 0, SFFT_RESIDUAL_SAMPLES = 1 };
 
 /* Learned bucket classifier (not in the paper): an 8-64-64-2 ReLU network with
  * BF16 parameters, evaluated with FP32 accumulation.  Parameter blob: the
@@ -97,6 +98,14 @@ typedef struct {
                               buckets with |F[h]|/p >= verify_eta send the loop on with
                               k* = their count.  0: stop at |R| = k (the listing)     */
   double verify_eta;       /* residual-energy floor of the verification; <= 0: eta     */
+  int32_t residual;        /* where the modes found so far are subtracted (Section 5.0):
+                              SFFT_RESIDUAL_SAMPLES: g(t) as an exponential sum over the
+                              samples of every set, on the matrix cores with the planted
+                              sum (the listing's step); SFFT_RESIDUAL_SPECTRUM: the
+                              closed form of its DFT (eq. (41)), p sum a E_s over the
+                              entries of each bucket, subtracted from the spectra in
+                              FP64 -- the same spectra with O(|R| (S+1)) instead of
+                              O(p |R| (S+1)) work                                      */
 } sfft_params;
 
 /* A batch of synthetic black-box signals with planted spectra.  All pointers

@@ -97,6 +97,8 @@ static sfft_status validate_params(const sfft_params* p) {
   if (!std::isfinite(p->feature_scale)) return fail(SFFT_EINVAL, "feature_scale must be finite");
   if (p->verify != 0 && p->verify != 1) return fail(SFFT_EINVAL, "verify must be 0 or 1");
   if (!std::isfinite(p->verify_eta)) return fail(SFFT_EINVAL, "verify_eta must be finite");
+  if (p->residual != SFFT_RESIDUAL_SPECTRUM && p->residual != SFFT_RESIDUAL_SAMPLES)
+    return fail(SFFT_EINVAL, "unknown residual mode");
   return SFFT_OK;
 }
 
@@ -148,6 +150,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.mlp_thr = P.mlp_threshold;
   kp.feat_scale = (P.feature_scale > 0.0) ? P.feature_scale : kp.tau;
   kp.verify = P.verify;
+  kp.residual = P.residual;
   kp.verify_eta = (P.verify_eta > 0.0) ? P.verify_eta : P.eta;
 
   // Largest prime a round can use: the max_rounds-th rule prime >= max(ceil(c k_max), p_min),
@@ -195,6 +198,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
                           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0));  // sampler
   lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
   lds = std::max(lds, decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max);  // decode / export
+  lds = std::max(lds, 4 * ((size_t)kp.p_max + 1 + 2 * (size_t)kp.cap));  // registry subtraction
   lds = std::max(lds, 4 * (size_t)kp.k_max);                             // output
   lds = std::max(lds, align16((size_t)kp.p_max * cs) + align16(2 * (size_t)(kp.m_max + 4)) +
                           (size_t)kp.m_max * cs + (size_t)kWG * 16);     // verification
@@ -215,10 +219,11 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   // slack: the sampler copies whole chunks of A fragments past npairs
   lay.afrag = o; o = al256(o + (P.precision == SFFT_FP32 ? 4 * (size_t)(kp.pairs_max + kChunk + 2) * kp.RT * 64 : 0));
   for (int b = 0; b < 2; ++b) {
-    lay.ry[b] = o; o = al256(o + 8 * (size_t)kp.cap * d2);
-    lay.ra[b] = o; o = al256(o + 16 * (size_t)kp.cap);
-    lay.rE[b] = o; o = al256(o + 16 * (size_t)kp.cap * S);
+    lay.sy[b] = o;  o = al256(o + 8 * (size_t)kp.cap * d2);
+    lay.sa[b] = o;  o = al256(o + 16 * (size_t)kp.cap);
+    lay.ord[b] = o; o = al256(o + 4 * (size_t)kp.cap);
   }
+  lay.dirty = o;  o = al256(o + 4 * (size_t)(kp.cap + 1));
   lay.V = o;      o = al256(o + cs * (size_t)S1 * kp.vstride);
   lay.chirp = o;  o = al256(o + cs * (size_t)kp.p_max);
   lay.bhat = o;   o = al256(o + cs * (size_t)L);

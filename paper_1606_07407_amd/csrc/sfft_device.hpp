@@ -482,7 +482,7 @@ __device__ __forceinline__ void twiddle_column(const float* twf, uint32_t h0, ui
   }
 }
 
-template <int RT, int NT>
+template <int RT, int NT, bool BLK = (RT * NT <= 12)>
 __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
                             const uint16_t* rs,
                             const cpx<float>* tw, float* abuf, int npairs, int p, int S1,
@@ -508,11 +508,17 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
     const bool active = tile < ntiles;
     const int hbase = tile * NCOL;
     const uint32_t h0 = (uint32_t)(hbase + col);
-    floatx4 acc[RT][NT];
+    // BLK: the MFMAs of one chunk (32 modes) accumulate from zero and the chunk
+    // sum is then added to `tot`, so the FP32 rounding of a long sum grows with
+    // the chunk sums instead of the running total (used where the registers allow)
+    floatx4 acc[RT][NT], tot[RT][NT];
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int u = 0; u < NT; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int u = 0; u < NT; ++u) {
+        acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+        tot[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
     // chunk 0 into buffer 0
 #pragma unroll
     for (int q = 0; q < CPY; ++q) {
@@ -541,6 +547,12 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
       }
       const int k1 = min(kChunk, npairs - c * kChunk);
       if (active) {
+        if constexpr (BLK) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
         for (int q = 0; q < k1; ++q) {
           const int pr = c * kChunk + q;
           // operands of step pr + 1 (A from this chunk buffer, twiddles from the
@@ -571,6 +583,12 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
           r1 = r2;
           s1 = s2;
         }
+        if constexpr (BLK) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) tot[t][u] += acc[t][u];
+        }
       }
       if (c + 1 < nchunks) {
         float* dst = abuf + ((c + 1) & 1) * BUF;
@@ -591,10 +609,10 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
           const int h = hbase + 16 * u + col;
+          const floatx4 r = BLK ? tot[t][u] : acc[t][u];
           if (h < p) {
-            if (s0 < S1) V[(size_t)s0 * vstride + h] = cmk<float>(acc[t][u][0], acc[t][u][1]);
-            if (s0 + 1 < S1)
-              V[(size_t)(s0 + 1) * vstride + h] = cmk<float>(acc[t][u][2], acc[t][u][3]);
+            if (s0 < S1) V[(size_t)s0 * vstride + h] = cmk<float>(r[0], r[1]);
+            if (s0 + 1 < S1) V[(size_t)(s0 + 1) * vstride + h] = cmk<float>(r[2], r[3]);
           }
         }
       }
@@ -606,9 +624,11 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
 // of each A fragment) that still gives every wave about the same number of
 // columns; a tile pass costs about 4 columns' worth of fixed overhead.
 __host__ __device__ inline int choose_nt(int p) {
+  // below 640 points the chunk-blocked accumulation (at most 4 column tiles)
+  // keeps the FP32 error of the long planted sum small relative to F / p
   int best = 8;
   int best_cost = 1 << 30;
-  for (int nt = 8; nt >= 2; nt >>= 1) {
+  for (int nt = (p < 640 ? 4 : 8); nt >= 2; nt >>= 1) {
     const int tiles = (p + 16 * nt - 1) / (16 * nt);
     const int passes = (tiles + 3) / 4;
     const int cost = passes * (16 * nt + 64);

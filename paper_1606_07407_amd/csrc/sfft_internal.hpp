@@ -48,9 +48,10 @@ struct WsLayout {
   size_t ypl;      // int64  [k_max][d2]        planted modes, unwrapped
   size_t ccomp;    // cplx T [m_max][S1]        per-mode coefficient rows
   size_t afrag;    // float  [pairs_max][RT][64] MFMA A fragments (FP32 path)
-  size_t ry[2];    // int64  [cap][d2]          registry keys (two buffers)
-  size_t ra[2];    // double2[cap]              registry coefficients
-  size_t rE[2];    // double2[cap][S]           registry shift phases
+  size_t sy[2];    // int64  [cap][d2]          registry keys by slot (two banks)
+  size_t sa[2];    // double2[cap]              registry coefficients by slot
+  size_t ord[2];   // int32  [cap]              slots in lexicographic order of y
+  size_t dirty;    // int32  [cap]              slots whose exponential-sum rows are stale
   size_t V;        // cplx T [S1][vstride]      samples, then spectra
   size_t chirp;    // cplx T [p_max]            Bluestein chirp
   size_t bhat;     // cplx T [L_max]            DFT of the chirp filter
@@ -87,6 +88,7 @@ struct KParams {
   int merge_global;       // 1: the merge/sort arrays live in the slot, not in LDS
   int verify;             // verification round when |R| reaches k
   double verify_eta;
+  int residual;           // 0: registry subtracted from the spectra, 1: from the samples
 };
 
 struct KBatch {

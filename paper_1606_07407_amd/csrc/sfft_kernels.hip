@@ -108,6 +108,7 @@ __device__ __forceinline__ int lexcmp(const int64_t* a, const int64_t* b, int n)
 struct WgState {
   int sig, k, M_pl, nR, cur, i, p, m0, kstar, ncand, nacc, status, L, log2L, nU, flag;
   int kv, verified;  // k* after a verification that found residual energy; clean check
+  int nslots, sb;    // registry slots in use, storage bank (cur: index of the sorted order)
   int64_t off, samples;
   double sigma;
   uint64_t prefix;
@@ -149,37 +150,87 @@ __device__ void planted_setup(const KParams& kp, const KBatch& kb, char* slot, W
   __syncthreads();
 }
 
-// Registry rows of the exponential sum: C[2 P0 + e][s] = -a_e E_e[s].
+// Registry storage: entries live in slots that never move while the signal is
+// processed (new entries take the next free slot, pruned ones get a zero
+// coefficient and leave the order); ord[st.cur] lists the live slots in
+// lexicographic order of y.
+__device__ __forceinline__ int64_t* reg_y(const KParams& kp, char* slot, int bank) {
+  return reinterpret_cast<int64_t*>(slot + kp.lay.sy[bank]);
+}
+__device__ __forceinline__ double2* reg_a(const KParams& kp, char* slot, int bank) {
+  return reinterpret_cast<double2*>(slot + kp.lay.sa[bank]);
+}
+__device__ __forceinline__ int* reg_ord(const KParams& kp, char* slot, int which) {
+  return reinterpret_cast<int*>(slot + kp.lay.ord[which]);
+}
+
+// Exponential-sum operand of mode row j, set s: complex c into the MFMA A
+// fragments (FP32 path; same lane order as scatter_afrag) or the coefficient
+// rows (FP64 path).  Used for the registry rows when the residual is
+// subtracted from the samples.
 template <typename T>
-__device__ void registry_rows(const KParams& kp, char* slot, WgState& st, int P0) {
-  cpx<T>* cc = ws_cpx<T>(slot, kp.lay.ccomp);
-  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[st.cur]);
-  const double2* rE = reinterpret_cast<const double2*>(slot + kp.lay.rE[st.cur]);
-  const int S1 = kp.S1, S = kp.S;
-  const int base = 2 * P0;
-  for (int q = threadIdx.x; q < st.nR * S1; q += kWG) {
+__device__ __forceinline__ void put_row(const KParams& kp, char* slot, int j, int s,
+                                        cpx<double> c) {
+  if constexpr (sizeof(T) == 4) {
+    float* af = reinterpret_cast<float*>(slot + kp.lay.afrag);
+    const float cx = (float)c.x, cy = (float)c.y;
+    const int jsel = j & 1;
+#pragma unroll
+    for (int rpart = 0; rpart < 2; ++rpart) {
+      const int row = 2 * s + rpart;
+      float* base = af + ((size_t)(j >> 1) * kp.RT + (row >> 4)) * 64 + (row & 15);
+      base[(2 * jsel) * 16] = rpart == 0 ? cx : cy;       // K index of Re omega
+      base[(2 * jsel + 1) * 16] = rpart == 0 ? -cy : cx;  // K index of Im omega
+    }
+  } else {
+    cpx<double>* cc = reinterpret_cast<cpx<double>*>(slot + kp.lay.ccomp);
+    cc[(size_t)j * kp.S1 + s] = c;
+  }
+}
+
+// Registry rows of the exponential sum, mode row 2 P0 + slot: C[s] = -a E_s(y),
+// E_0 = 1, E_s the shift phase of set s.  All slots, or only those flagged
+// dirty (flags cleared).  The partner of an odd last slot gets a zero row.
+template <typename T>
+__device__ void rebuild_rows(const KParams& kp, char* slot, WgState& st, int P0, bool only_dirty) {
+  const int S1 = kp.S1, d2 = kp.d2, n = st.nslots;
+  const int64_t* sy = reg_y(kp, slot, st.sb);
+  const double2* sa = reg_a(kp, slot, st.sb);
+  int* dirty = reinterpret_cast<int*>(slot + kp.lay.dirty);
+  for (int q = threadIdx.x; q < n * S1; q += kWG) {
     const int e = q / S1, s = q - e * S1;
-    const cpx<double> a = cmk<double>(-ra[e].x, -ra[e].y);
+    if (only_dirty && !dirty[e]) continue;
+    const cpx<double> a = cmk<double>(-sa[e].x, -sa[e].y);
     cpx<double> v = a;
-    if (s > 0) v = cmul(a, cmk<double>(rE[(size_t)e * S + s - 1].x, rE[(size_t)e * S + s - 1].y));
-    cc[(size_t)(base + e) * S1 + s] = cmk<T>((T)v.x, (T)v.y);
+    if (s > 0 && (a.x != 0.0 || a.y != 0.0)) {
+      int n0;
+      int64_t K;
+      shift_of(kp, s, &n0, &K);
+      v = cmul(a, shift_phase(sy[(size_t)e * d2 + n0], K, kp.NB));
+    }
+    put_row<T>(kp, slot, 2 * P0 + e, s, v);
   }
-  if (threadIdx.x == 0 && (st.nR & 1)) {
-    for (int s = 0; s < S1; ++s) cc[(size_t)(base + st.nR) * S1 + s] = cmk<T>(0, 0);
-  }
+  if (n & 1)
+    for (int s = threadIdx.x; s < S1; s += kWG) put_row<T>(kp, slot, 2 * P0 + n, s, cmk<double>(0, 0));
   __syncthreads();
+  if (only_dirty) {
+    for (int e = threadIdx.x; e < n; e += kWG) dirty[e] = 0;
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ sampling ----
 // Line sampler for round st.i with prime st.p along axis st.m0 (0-based):
-// writes V[s][h] for all sets.  Planted rows [0, 2 P0), registry rows
-// [2 P0, 2 P0 + 2 ceil(nR/2)).
+// writes V[s][h] = f(t_h) + noise for all sets, f the planted signal (rows
+// [0, 2 P0)), minus g(t_h) (registry rows [2 P0, 2 P0 + 2 ceil(nslots / 2)))
+// when the residual is subtracted from the samples; otherwise the registry is
+// subtracted after the DFT (subtract_registry).
 template <typename T, int RT>
 __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, WgState& st,
                              int P0, char* lds, cpx<T>* V, int vstride) {
   const int p = st.p, m0 = st.m0, d2 = kp.d2;
-  const int PR = (st.nR + 1) / 2;
-  const int npairs = P0 + PR;
+  const int nreg = (kp.residual == 1) ? st.nslots : 0;
+  const int npairs = P0 + (nreg + 1) / 2;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
   // residues and column steps fit 16 bits (p <= 8192)
   uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
@@ -188,7 +239,7 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   float* abuf = reinterpret_cast<float*>(reinterpret_cast<char*>(rs) +
                                          align16(2 * (size_t)(kp.m_max + 4)));
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
-  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
+  const int64_t* ry = reg_y(kp, slot, st.sb);
   for (int x = threadIdx.x; x < p; x += kWG) {
     double c, s;
     expipi(2.0 * (double)x / (double)p, &c, &s);  // omega_p^x = exp(2 pi i x / p)
@@ -198,7 +249,7 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     int r = 0;
     if (j < st.M_pl) {
       r = (int)pmod64(ypl[(size_t)j * d2 + m0], p);
-    } else if (j >= 2 * P0 && j - 2 * P0 < st.nR) {
+    } else if (j >= 2 * P0 && j - 2 * P0 < nreg) {
       r = (int)pmod64(ry[(size_t)(j - 2 * P0) * d2 + m0], p);
     }
     rr[j] = (uint16_t)r;
@@ -238,15 +289,15 @@ template <typename T>
 __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, WgState& st,
                             char* lds, cpx<T>* V, int* sh_part) {
   const int p = st.p, d2 = kp.d2;
-  const int M = st.M_pl + st.nR;
+  const int M = st.M_pl + st.nslots;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
   uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
   cpx<T>* coef = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(rr) +
                                            align16(2 * (size_t)(kp.m_max + 4)));
   cpx<T>* part = coef + kp.m_max;
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
-  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
-  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[st.cur]);
+  const int64_t* ry = reg_y(kp, slot, st.sb);
+  const double2* ra = reg_a(kp, slot, st.sb);
   const cpx<T>* cc = ws_cpx<T>(slot, kp.lay.ccomp);
   const int64_t q = 1 + (st.i % (p - 1));
   for (int x = threadIdx.x; x < p; x += kWG) {
@@ -304,18 +355,6 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   __syncthreads();
 }
 
-// Prepare the exponential-sum operands of the registry for this round.
-template <typename T>
-__device__ void registry_operands(const KParams& kp, char* slot, WgState& st, int P0) {
-  registry_rows<T>(kp, slot, st, P0);
-  if constexpr (sizeof(T) == 4) {
-    const int PR = (st.nR + 1) / 2;
-    scatter_afrag(kp, ws_cpx<float>(slot, kp.lay.ccomp),
-                  reinterpret_cast<float*>(slot + kp.lay.afrag), 2 * P0, 2 * (P0 + PR));
-    __syncthreads();
-  }
-}
-
 // --------------------------------------------------------------- DFTs ------
 template <typename T>
 __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds, cpx<T>* V,
@@ -326,6 +365,70 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
   bluestein_setup<T>(st.p, st.L, st.log2L, chirp, bhat, buf);
   for (int s = 0; s < nsets; ++s)
     bluestein_dft<T>(V + (size_t)s * vstride, st.p, st.L, st.log2L, chirp, bhat, buf);
+}
+
+// ------------------------------------------- residual in the spectrum ------
+// Adaptive subtraction of the registry (Section 5.0) applied to the spectra:
+// by eq. (41) the DFT of g(t) = sum_e a_e exp(2 pi i y_e . t) on the sampling
+// line of set s is p sum_{e: y_{e,m} = h mod p} a_e E_s(y_e) in bucket h, with
+// E_0 = 1 and E_s = exp(2 pi i eps K_s y_{e,n_s}), so
+//   F_s[h] <- F_s[h] - p sum_{e in bucket h} a_e E_s(y_e)
+// equals the DFT of the residual samples f - g.  FP64 sums (entries of a
+// bucket in registry order), one rounding to T per spectrum value.
+template <typename T>
+__device__ void subtract_registry(const KParams& kp, char* slot, WgState& st, char* lds,
+                                  cpx<T>* V, int vstride, int nsets, int* sh_part) {
+  const int nR = st.nR;
+  if (nR == 0) return;
+  const int p = st.p, d2 = kp.d2, m0 = st.m0;
+  const int64_t* sy = reg_y(kp, slot, st.sb);
+  const double2* sa = reg_a(kp, slot, st.sb);
+  const int* ord = reg_ord(kp, slot, st.cur);
+  // LDS: bucket start [p + 1] | entries grouped by bucket [nR] | bucket of entry [nR]
+  int* start = reinterpret_cast<int*>(lds);
+  int* grp = start + (p + 1);
+  int* hb = grp + nR;
+  for (int h = threadIdx.x; h <= p; h += kWG) start[h] = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < nR; e += kWG) {
+    const int h = (int)pmod64(sy[(size_t)ord[e] * d2 + m0], p);
+    hb[e] = h;
+    atomicAdd(&start[h], 1);
+  }
+  __syncthreads();
+  block_exscan(start, p + 1, sh_part);
+  // deterministic placement: rank of e among the entries of its bucket
+  // (registry order), counted by the entries' own scan of their bucket run
+  for (int e = threadIdx.x; e < nR; e += kWG) {
+    const int h = hb[e];
+    int r = 0;
+    for (int f = 0; f < e; ++f) r += (hb[f] == h) ? 1 : 0;
+    grp[start[h] + r] = e;
+  }
+  __syncthreads();
+  const double pd = (double)p;
+  for (int q = threadIdx.x; q < p * nsets; q += kWG) {
+    const int h = q % p, s = q / p;
+    const int b0 = start[h], b1 = start[h + 1];
+    if (b1 == b0) continue;
+    int n0 = 0;
+    int64_t K = 0;
+    if (s > 0) shift_of(kp, s, &n0, &K);
+    double ax = 0.0, ay = 0.0;
+    for (int g = b0; g < b1; ++g) {
+      const int sl = ord[grp[g]];
+      double2 a = sa[sl];
+      if (s > 0) {
+        const cpx<double> E = shift_phase(sy[(size_t)sl * d2 + n0], K, kp.NB);
+        a = make_double2(a.x * E.x - a.y * E.y, a.x * E.y + a.y * E.x);
+      }
+      ax += a.x;
+      ay += a.y;
+    }
+    cpx<T>* v = V + (size_t)s * vstride + h;
+    *v = cmk<T>((T)((double)v->x - pd * ax), (T)((double)v->y - pd * ay));
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------ top-k* selection ---------
@@ -637,8 +740,9 @@ __device__ void export_round(const KParams& kp, const KBatch& kb, const KOut& ko
   const int p = st.p, d2 = kp.d2, m0 = st.m0;
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
   const int* psort = reinterpret_cast<const int*>(slot + kp.lay.pl_sorted);
-  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
-  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[st.cur]);
+  const int64_t* ry = reg_y(kp, slot, st.sb);
+  const double2* ra = reg_a(kp, slot, st.sb);
+  const int* ord = reg_ord(kp, slot, st.cur);
   const int* cand = reinterpret_cast<const int*>(slot + kp.lay.cand);
   const int* acc_ok = reinterpret_cast<const int*>(slot + kp.lay.acc_ok);
   const float* ftmp = reinterpret_cast<const float*>(slot + kp.lay.feat_tmp);
@@ -646,17 +750,17 @@ __device__ void export_round(const KParams& kp, const KBatch& kb, const KOut& ko
   __syncthreads();
   for (int j = threadIdx.x; j < st.M_pl; j += kWG) {
     const int64_t* yj = ypl + (size_t)j * d2;
-    const int pos = lower_bound_rows(ry, nullptr, st.nR, d2, yj);
+    const int pos = lower_bound_rows(ry, ord, st.nR, d2, yj);
     bool present = true;
-    if (pos < st.nR && lexcmp(ry + (size_t)pos * d2, yj, d2) == 0) {
-      const double rx = kb.coeffs[2 * (st.off + j)] - ra[pos].x;
-      const double ryy = kb.coeffs[2 * (st.off + j) + 1] - ra[pos].y;
+    if (pos < st.nR && lexcmp(ry + (size_t)ord[pos] * d2, yj, d2) == 0) {
+      const double rx = kb.coeffs[2 * (st.off + j)] - ra[ord[pos]].x;
+      const double ryy = kb.coeffs[2 * (st.off + j) + 1] - ra[ord[pos]].y;
       present = hypot(rx, ryy) >= kp.eta;
     }
     if (present) atomicAdd(&cnt[(int)pmod64(yj[m0], p)], 1);
   }
   for (int e = threadIdx.x; e < st.nR; e += kWG) {
-    const int64_t* ye = ry + (size_t)e * d2;
+    const int64_t* ye = ry + (size_t)ord[e] * d2;
     const int pos = lower_bound_rows(ypl, psort, st.M_pl, d2, ye);
     const bool planted = pos < st.M_pl && lexcmp(ypl + (size_t)psort[pos] * d2, ye, d2) == 0;
     if (!planted) atomicAdd(&cnt[(int)pmod64(ye[m0], p)], 1);
@@ -678,12 +782,16 @@ __device__ void export_round(const KParams& kp, const KBatch& kb, const KOut& ko
 
 // ------------------------------------------------------ registry merge ------
 // R[y] += a for the accepted buckets (ascending h), then prune |a| < eta.
-// The registry is kept sorted by lexicographic y; the accepted entries are
-// sorted (stable) and merged by binary search.
+// Entries keep their slot; the lexicographic order of y is an index array,
+// merged by binary search against the accepted entries (sorted, stable).  New
+// entries take the next free slots.  When the free slots run out, the live
+// entries are first compacted into the other storage bank.  With the residual
+// subtracted from the samples, the exponential-sum rows of new, updated and
+// pruned slots are rebuilt.
 template <typename T>
 __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* lds,
-                            int* sh_part) {
-  const int d2 = kp.d2, S = kp.S;
+                            int* sh_part, int P0) {
+  const int d2 = kp.d2;
   const int nC = st.ncand;
   const MergeLds ml = merge_lds(kp.k_max, kp.cap);
   char* mb = merge_base(kp, slot, lds);
@@ -697,15 +805,39 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
   int* keep = reinterpret_cast<int*>(mb + ml.keep);          // ranks, then prune flags
   const int64_t* acc_y = reinterpret_cast<const int64_t*>(slot + kp.lay.acc_y);
   const double2* acc_a = reinterpret_cast<const double2*>(slot + kp.lay.acc_a);
+  int* dirty = reinterpret_cast<int*>(slot + kp.lay.dirty);
+  const bool rows = kp.residual == 1;  // registry rows in the exponential sum to keep current
   const int nA = st.nacc;
   const int nR = st.nR;
+
+  // compaction: live entries into slots 0..nR-1 of the other bank
+  if (st.nslots + nA > kp.cap) {
+    const int nb = st.sb ^ 1;
+    const int64_t* y0 = reg_y(kp, slot, st.sb);
+    const double2* a0 = reg_a(kp, slot, st.sb);
+    int64_t* y1 = reg_y(kp, slot, nb);
+    double2* a1 = reg_a(kp, slot, nb);
+    int* o = reg_ord(kp, slot, st.cur);
+    for (int e = threadIdx.x; e < nR; e += kWG) {
+      const int src = o[e];
+      for (int i = 0; i < d2; ++i) y1[(size_t)e * d2 + i] = y0[(size_t)src * d2 + i];
+      a1[e] = a0[src];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nR; e += kWG) o[e] = e;
+    if (threadIdx.x == 0) {
+      st.sb = nb;
+      st.nslots = nR;
+    }
+    __syncthreads();
+    if (rows) rebuild_rows<T>(kp, slot, st, P0, false);
+  }
+  int64_t* sy = reg_y(kp, slot, st.sb);
+  double2* sa = reg_a(kp, slot, st.sb);
   const int cur = st.cur, nxt = cur ^ 1;
-  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[cur]);
-  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[cur]);
-  const double2* rE = reinterpret_cast<const double2*>(slot + kp.lay.rE[cur]);
-  int64_t* ry2 = reinterpret_cast<int64_t*>(slot + kp.lay.ry[nxt]);
-  double2* ra2 = reinterpret_cast<double2*>(slot + kp.lay.ra[nxt]);
-  double2* rE2 = reinterpret_cast<double2*>(slot + kp.lay.rE[nxt]);
+  const int* ord = reg_ord(kp, slot, cur);
+  int* ord2 = reg_ord(kp, slot, nxt);
+  const int ns0 = st.nslots;
 
   // accepted candidate indices in ascending h
   int N2 = 1;
@@ -751,7 +883,7 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
       __syncthreads();
     }
   }
-  // runs of equal y; lower_bound of each run in the registry
+  // runs of equal y; lower_bound of each run in the registry order
   for (int e = threadIdx.x; e <= nR; e += kWG) cnt[e] = 0;
   for (int e = threadIdx.x; e < nR; e += kWG) matchrun[e] = -1;
   __syncthreads();
@@ -760,16 +892,8 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
     const bool first = (u == 0) || lexcmp(acc_y + (size_t)ids[u - 1] * d2, yu, d2) != 0;
     int flagv = 0, pos = 0;
     if (first) {
-      int lo = 0, hi = nR;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (lexcmp(ry + (size_t)mid * d2, yu, d2) < 0)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      pos = lo;
-      const bool matched = (pos < nR) && lexcmp(ry + (size_t)pos * d2, yu, d2) == 0;
+      pos = lower_bound_rows(sy, ord, nR, d2, yu);
+      const bool matched = (pos < nR) && lexcmp(sy + (size_t)ord[pos] * d2, yu, d2) == 0;
       if (matched) {
         flagv = 1;
         matchrun[pos] = u;
@@ -782,59 +906,55 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
     runpos[u] = pos;
   }
   __syncthreads();
-  // unmatched ranks (reuse keep[] as scratch of nA ints)
+  // unmatched ranks (keep[] as scratch of nA ints)
   for (int u = threadIdx.x; u < nA; u += kWG) keep[u] = (runflag[u] == 2) ? 1 : 0;
   __syncthreads();
   const int nU = block_exscan(keep, nA, sh_part);
-  // cnt -> exclusive scan over registry positions 0..nR
-  {
-    // cnt has nR + 1 entries; scan in place
-    block_exscan(cnt, nR + 1, sh_part);
-  }
-  // old entries move to e + #unmatched runs with pos <= e
+  block_exscan(cnt, nR + 1, sh_part);
+  // old entries move to e + #new runs with pos <= e; matched ones add their run
   for (int e = threadIdx.x; e < nR; e += kWG) {
-    // inclusive count: exclusive(e + 1) = sum_{x <= e}
-    const int incl = cnt[e + 1];
-    const int dst = e + incl;
-    for (int i = 0; i < d2; ++i) ry2[(size_t)dst * d2 + i] = ry[(size_t)e * d2 + i];
-    double ax = ra[e].x, ay = ra[e].y;
+    const int dst = e + cnt[e + 1];
+    const int se = ord[e];
+    ord2[dst] = se;
     const int u0 = matchrun[e];
     if (u0 >= 0) {
+      double ax = sa[se].x, ay = sa[se].y;
       const int64_t* yu = acc_y + (size_t)ids[u0] * d2;
       for (int u = u0; u < nA && lexcmp(acc_y + (size_t)ids[u] * d2, yu, d2) == 0; ++u) {
         ax += acc_a[ids[u]].x;
         ay += acc_a[ids[u]].y;
       }
+      sa[se] = make_double2(ax, ay);
+      if (rows) dirty[se] = 1;
     }
-    ra2[dst] = make_double2(ax, ay);
-    for (int s = 0; s < S; ++s) rE2[(size_t)dst * S + s] = rE[(size_t)e * S + s];
   }
-  // new entries
+  // new entries take slots ns0 + rank
   for (int u = threadIdx.x; u < nA; u += kWG) {
     if (runflag[u] != 2) continue;
-    const int dst = runpos[u] + keep[u];
+    const int sl = ns0 + keep[u];
     const int64_t* yu = acc_y + (size_t)ids[u] * d2;
-    for (int i = 0; i < d2; ++i) ry2[(size_t)dst * d2 + i] = yu[i];
+    for (int i = 0; i < d2; ++i) sy[(size_t)sl * d2 + i] = yu[i];
     double ax = 0.0, ay = 0.0;
     for (int v = u; v < nA && lexcmp(acc_y + (size_t)ids[v] * d2, yu, d2) == 0; ++v) {
       ax += acc_a[ids[v]].x;
       ay += acc_a[ids[v]].y;
     }
-    ra2[dst] = make_double2(ax, ay);
-    for (int s = 1; s <= S; ++s) {
-      int n0;
-      int64_t K;
-      shift_of(kp, s, &n0, &K);
-      const cpx<double> e = shift_phase(yu[n0], K, kp.NB);
-      rE2[(size_t)dst * S + s - 1] = make_double2(e.x, e.y);
-    }
+    sa[sl] = make_double2(ax, ay);
+    if (rows) dirty[sl] = 1;
+    ord2[runpos[u] + keep[u]] = sl;
   }
   __syncthreads();
-  // prune |a| < eta (compact back into the other buffer only if needed)
+  if (threadIdx.x == 0) st.nslots = ns0 + nU;
+  // prune |a| < eta: zero coefficient (rows rebuilt as zero), dropped from the order
   const int nM = nR + nU;
   int npr = 0;
   for (int e = threadIdx.x; e < nM; e += kWG) {
-    const int k = (hypot(ra2[e].x, ra2[e].y) >= kp.eta) ? 1 : 0;
+    const int se = ord2[e];
+    const int k = (hypot(sa[se].x, sa[se].y) >= kp.eta) ? 1 : 0;
+    if (!k) {
+      sa[se] = make_double2(0.0, 0.0);
+      if (rows) dirty[se] = 1;
+    }
     keep[e] = k;
     npr += 1 - k;
   }
@@ -846,21 +966,16 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
     }
   } else {
     const int nK = block_exscan(keep, nM, sh_part);
-    int64_t* ry3 = reinterpret_cast<int64_t*>(slot + kp.lay.ry[cur]);
-    double2* ra3 = reinterpret_cast<double2*>(slot + kp.lay.ra[cur]);
-    double2* rE3 = reinterpret_cast<double2*>(slot + kp.lay.rE[cur]);
+    int* o = reg_ord(kp, slot, cur);
     for (int e = threadIdx.x; e < nM; e += kWG) {
       const int pos = keep[e];
       const int nx = (e + 1 < nM) ? keep[e + 1] : nK;
-      if (nx > pos) {
-        for (int i = 0; i < d2; ++i) ry3[(size_t)pos * d2 + i] = ry2[(size_t)e * d2 + i];
-        ra3[pos] = ra2[e];
-        for (int s = 0; s < S; ++s) rE3[(size_t)pos * S + s] = rE2[(size_t)e * S + s];
-      }
+      if (nx > pos) o[pos] = ord2[e];
     }
     if (threadIdx.x == 0) st.nR = nK;
   }
   __syncthreads();
+  if (rows) rebuild_rows<T>(kp, slot, st, P0, true);
 }
 
 // ------------------------------------------------------------- output ------
@@ -869,8 +984,9 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
 __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgState& st,
                                     char* lds) {
   const int d = kp.d, d1 = kp.d1, d2 = kp.d2, nR = st.nR;
-  const int64_t* ry = reinterpret_cast<const int64_t*>(slot + kp.lay.ry[st.cur]);
-  const double2* ra = reinterpret_cast<const double2*>(slot + kp.lay.ra[st.cur]);
+  const int64_t* ry = reg_y(kp, slot, st.sb);
+  const double2* ra = reg_a(kp, slot, st.sb);
+  const int* ord = reg_ord(kp, slot, st.cur);
   int64_t* fo = ko.freqs + (size_t)st.sig * kp.k_max * d;
   double* co = ko.coeffs + (size_t)st.sig * kp.k_max * 2;
   const int nOut = min(nR, kp.k_max);
@@ -878,7 +994,7 @@ __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgSt
   // entries in registry order first (lexicographic in y)
   for (int e = threadIdx.x; e < nOut; e += kWG) {
     for (int q = 0; q < d2; ++q) {
-      int64_t rest = ry[(size_t)e * d2 + q];
+      int64_t rest = ry[(size_t)ord[e] * d2 + q];
       for (int r = 0; r < d1; ++r) {
         const int64_t digit = pmod64(rest + half, kp.N) - half;
         fo[(size_t)e * d + d1 * q + r] = digit;
@@ -907,13 +1023,13 @@ __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgSt
       __syncthreads();
     }
     for (int e = threadIdx.x; e < nOut; e += kWG) {
-      co[2 * rank[e]] = ra[e].x;
-      co[2 * rank[e] + 1] = ra[e].y;
+      co[2 * rank[e]] = ra[ord[e]].x;
+      co[2 * rank[e] + 1] = ra[ord[e]].y;
     }
   } else {
     for (int e = threadIdx.x; e < nOut; e += kWG) {
-      co[2 * e] = ra[e].x;
-      co[2 * e + 1] = ra[e].y;
+      co[2 * e] = ra[ord[e]].x;
+      co[2 * e + 1] = ra[ord[e]].y;
     }
   }
   for (int e = nOut + threadIdx.x; e < kp.k_max; e += kWG) {
@@ -956,6 +1072,8 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
       st.sigma = kb.sigma[sig];
       st.nR = 0;
       st.cur = 0;
+      st.sb = 0;
+      st.nslots = 0;
       st.i = 1;
       st.samples = 0;
       st.status = 0;
@@ -1043,14 +1161,14 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
         if (st.flag) break;
         continue;
       }
-      registry_operands<T>(kp, slot, st, P0);
       sample_round<T, RT>(kp, kb, slot, st, P0, lds, V, vstride);
       dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
+      if (kp.residual == 0) subtract_registry<T>(kp, slot, st, lds, V, vstride, kp.S1, sh_part);
       select_round<T>(kp, slot, st, lds, V, sh_part);
       decode_round<T>(kp, ko, slot, st, V, vstride, lds, sh_part);
       if (ko.feat) export_round(kp, kb, ko, slot, st, lds);
       decode_finish(kp, st, lds, sh_part);
-      merge_round<T>(kp, slot, st, lds, sh_part);
+      merge_round<T>(kp, slot, st, lds, sh_part, P0);
       if (threadIdx.x == 0) {
         st.samples += (int64_t)kp.S1 * st.p;
         if (ko.trace) {
@@ -1093,32 +1211,28 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) s
       st.M_pl = min((int)(kb.mode_off[sig + 1] - st.off), kp.k_max);
       st.sigma = kb.sigma[sig];
       st.cur = 0;
+      st.sb = 0;
       st.i = round;
       st.p = p;
       st.m0 = m - 1;
       int nres = 0;
       if (res_off) nres = (int)(res_off[sig + 1] - res_off[sig]);
       st.nR = max(0, min(nres, kp.cap));
+      st.nslots = st.nR;
     }
     __syncthreads();
     planted_setup<T>(kp, kb, slot, st);
     const int P0 = (st.M_pl + 1) / 2;
-    // copy the caller's residual modes into registry buffer 0
+    // the caller's residual modes become registry slots 0..nR-1
     if (res_off) {
-      int64_t* ry = reinterpret_cast<int64_t*>(slot + kp.lay.ry[0]);
-      double2* ra = reinterpret_cast<double2*>(slot + kp.lay.ra[0]);
-      double2* rE = reinterpret_cast<double2*>(slot + kp.lay.rE[0]);
+      int64_t* ry = reg_y(kp, slot, 0);
+      double2* ra = reg_a(kp, slot, 0);
+      int* ord = reg_ord(kp, slot, 0);
       const int64_t r0 = res_off[sig];
       for (int e = threadIdx.x; e < st.nR; e += kWG) {
         for (int q = 0; q < kp.d2; ++q) ry[(size_t)e * kp.d2 + q] = res_y[(r0 + e) * kp.d2 + q];
         ra[e] = make_double2(res_c[2 * (r0 + e)], res_c[2 * (r0 + e) + 1]);
-        for (int s = 1; s <= kp.S; ++s) {
-          int n0;
-          int64_t K;
-          shift_of(kp, s, &n0, &K);
-          const cpx<double> e2 = shift_phase(res_y[(r0 + e) * kp.d2 + n0], K, kp.NB);
-          rE[(size_t)e * kp.S + s - 1] = make_double2(e2.x, e2.y);
-        }
+        ord[e] = e;
       }
       __syncthreads();
     }
@@ -1127,8 +1241,35 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) s
                     reinterpret_cast<float*>(slot + kp.lay.afrag), 0, 2 * P0);
       __syncthreads();
     }
-    registry_operands<T>(kp, slot, st, P0);
-    sample_round<T, RT>(kp, kb, slot, st, P0, lds, Vout + (size_t)sig * kp.S1 * p, p);
+    cpx<T>* Vs = Vout + (size_t)sig * kp.S1 * p;
+    if (kp.residual == 1) rebuild_rows<T>(kp, slot, st, P0, false);
+    sample_round<T, RT>(kp, kb, slot, st, P0, lds, Vs, p);
+    // spectrum-mode plans subtract the registry after the DFT; here the caller
+    // asked for samples: V[s][h] -= sum_e a_e exp(2 pi i y_e . t_{s,h}), FP64 per value
+    if (kp.residual == 0 && st.nR > 0) {
+      const int64_t* ry = reg_y(kp, slot, 0);
+      const double2* ra = reg_a(kp, slot, 0);
+      for (int q = threadIdx.x; q < kp.S1 * p; q += kWG) {
+        const int s = q / p, h = q - s * p;
+        int n0 = 0;
+        int64_t K = 0;
+        if (s > 0) shift_of(kp, s, &n0, &K);
+        double ax = 0.0, ay = 0.0;
+        for (int e = 0; e < st.nR; ++e) {
+          const int64_t* y = ry + (size_t)e * kp.d2;
+          // phase (h y_m / p + eps K y_n) mod 1 as an exact rational over 2 p N^d1
+          const int64_t hm = (int64_t)h * pmod64(y[st.m0], p) % p;
+          cpx<double> w;
+          expipi(2.0 * (double)hm / (double)p, &w.x, &w.y);
+          if (s > 0) w = cmul(w, shift_phase(y[n0], K, kp.NB));
+          ax += ra[e].x * w.x - ra[e].y * w.y;
+          ay += ra[e].x * w.y + ra[e].y * w.x;
+        }
+        cpx<T>* v = Vs + (size_t)s * p + h;
+        *v = cmk<T>((T)((double)v->x - ax), (T)((double)v->y - ay));
+      }
+      __syncthreads();
+    }
   }
 }
 

@@ -20,6 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsfft.so")
 
 SFFT_OK, SFFT_NOT_CONVERGED, SFFT_RESIDUAL_NONZERO = 0, 1, 2
+SFFT_RESIDUAL_SPECTRUM, SFFT_RESIDUAL_SAMPLES = 0, 1
 SFFT_EINVAL, SFFT_ERANGE, SFFT_ENOMEM, SFFT_EDEVICE = -1, -2, -3, -4
 SFFT_PRIME_PAPER, SFFT_PRIME_SMOOTH = 0, 1
 SFFT_FP64, SFFT_FP32 = 0, 1
@@ -44,6 +45,7 @@ class sfft_params(ctypes.Structure):
         ("feature_scale", ctypes.c_double),
         ("verify", ctypes.c_int32),
         ("verify_eta", ctypes.c_double),
+        ("residual", ctypes.c_int32),
     ]
 
 
@@ -156,13 +158,14 @@ class Params:
     feature_scale: float = 0.0
     verify: int = 0
     verify_eta: float = 0.0
+    residual: int = 0               # SFFT_RESIDUAL_SPECTRUM
 
     def to_c(self) -> sfft_params:
         return sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
                            self.p_min, self.ladder_K, self.tau, self.tau_noise, self.eta,
                            self.max_rounds, self.precision, self.robust, self.classifier,
                            _ptr(self.mlp_weights), self.mlp_threshold, self.feature_scale,
-                           self.verify, self.verify_eta)
+                           self.verify, self.verify_eta, self.residual)
 
 
 class Plan:

@@ -50,7 +50,7 @@ def _plan(cfg, k_max, B, **over):
     kw = dict(d=cfg["d"], N=cfg["N"], k_max=k_max, d1=cfg["d1"], c=cfg["c"],
               p_min=cfg["p_min"], ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
               precision=sfft.SFFT_FP32, robust=int(cfg["robust"]), verify=int(cfg["verify"]),
-              verify_eta=cfg["verify_eta"] or 0.0)
+              verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]))
     kw.update(over)
     return sfft.sfft_plan_create(sfft.Params(**kw), max_batch=B)
 

@@ -48,7 +48,7 @@ def _params(cfg, k_max, precision=None):
                        tau=(cfg["tau"] or 0.0), eta=cfg["eta"], max_rounds=cfg.get("max_rounds", 64),
                        precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64,
                        robust=int(cfg["robust"]), verify=int(cfg["verify"]),
-                       verify_eta=cfg["verify_eta"] or 0.0)
+                       verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]))
 
 
 def _oracle_params(cfg, k):
@@ -68,6 +68,9 @@ SAMPLER_CASES = [
     ("c2_fp32", "c2", {}, 256, 1283, 2, 40, 2),
     ("c3_fp32_ladder_noise", "c3b", {}, 200, 601, 4, 50, 2),
     ("c3_fp32_full_p", "c3b", {}, 1000, 3001, 2, 0, 2),
+    # registry rows in the exponential sum (residual subtracted from the samples)
+    ("c3_fp32_residual_rows", "c3b", {"residual": 1}, 200, 601, 4, 50, 2),
+    ("e4_fp64_residual_rows", "e4", {"residual": 1}, 100, 503, 3, 20, 2),
     # the large workload's first round: k = 4096, 41 sets, p = 8161, 6 row tiles
     ("c5_fp32_full_p", "c5", {}, 4096, 8161, 7, 64, 1),
 ]
@@ -202,6 +205,10 @@ RECOVER_CASES = [
     ("c3_fp32_uneven_k", "c3b", {}, 5, (20, 260), 1e-5),
     ("c2_fp32_round_cap", "c2", {"max_rounds": 1}, 2, 256, 1e-5),
     ("c1_fp64_round_cap", "c1", {"max_rounds": 1}, 4, 8, 1e-9),
+    # the residual subtracted from the samples on the matrix cores (the listing's step)
+    ("c1_fp64_residual_samples", "c1", {"residual": 1}, 8, 8, 1e-9),
+    ("c2_fp32_residual_samples", "c2", {"residual": 1}, 2, 256, 1e-5),
+    ("c3_fp32_residual_samples", "c3b", {"residual": 1}, 5, (20, 260), 1e-5),
 ]
 
 
@@ -266,6 +273,15 @@ def test_full_size_headline_batch():
         assert np.abs(h["coeffs"][b, :kf] - a[o]).max() < 1e-3, b
     rel = _compare(cfg, pb, h, 1e-5, signals=(0, 257, B - 1))
     _say(f"    all {B} exact; sampled oracle parity max rel {rel:.2e}")
+    plan.close()
+    # the same launch with the residual subtracted from the samples
+    cfg1 = workloads.config("c3b", residual=1)
+    plan = sfft.sfft_plan_create(_params(cfg1, cfg["k"]), max_batch=B)
+    h1 = sfft.outputs_to_host(sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb)))
+    torch.cuda.synchronize()
+    assert np.array_equal(h1["freqs"], h["freqs"]) and np.array_equal(h1["status"], h["status"])
+    rel1 = _compare(cfg1, pb, h1, 1e-5, signals=(257,))
+    _say(f"    residual from the samples: same supports; oracle parity max rel {rel1:.2e}")
     plan.close()
 
 

@@ -51,7 +51,7 @@ CONFIGS = {
 
 def config(name: str, **over):
     """A copy of the named recipe with fields overridden by keyword."""
-    cfg = dict(verify=False, verify_eta=None)
+    cfg = dict(verify=False, verify_eta=None, residual=0)
     cfg.update(copy.deepcopy(CONFIGS[name]))
     cfg.update(over)
     cfg["name"] = name
