@@ -198,10 +198,29 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
                           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0));  // sampler
   lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
   lds = std::max(lds, decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max);  // decode / export
-  lds = std::max(lds, 4 * ((size_t)kp.p_max + 1 + 2 * (size_t)kp.cap));  // registry subtraction
+  {
+    size_t n2 = 1;
+    while (n2 < (size_t)kp.cap) n2 <<= 1;
+    lds = std::max(lds, 4 * ((size_t)kp.p_max + 1 + 2 * (size_t)kp.cap));  // registry subtraction
+    lds = std::max(lds, align16(4 * ((size_t)kp.p_max + 1 + n2)) +
+                            16 * (size_t)kp.cap);                          // (FP32: sorted entries)
+  }
   lds = std::max(lds, 4 * (size_t)kp.k_max);                             // output
-  lds = std::max(lds, align16((size_t)kp.p_max * cs) + align16(2 * (size_t)(kp.m_max + 4)) +
-                          (size_t)kp.m_max * cs + (size_t)kWG * 16);     // verification
+  {
+    // verification rounds use the prime for k* = 1: the max_rounds-th table prime
+    // >= max(ceil(c), p_min)
+    const int64_t xv = std::max((int64_t)std::ceil(P.c), (int64_t)P.p_min);
+    int cntv = 0;
+    kp.p_vmax = 2;
+    for (int32_t q : primes)
+      if (q >= xv && cntv < P.max_rounds) {
+        kp.p_vmax = q;
+        ++cntv;
+      }
+    if (P.verify)
+      lds = std::max(lds, align16((size_t)kp.p_vmax * cs) + align16(2 * (size_t)(kp.m_max + 4)) +
+                              (size_t)kp.m_max * cs + 4 * (size_t)kWG * cs);  // verification
+  }
   const size_t merge_bytes = merge_lds(kp.k_max, kp.cap).bytes;
   kp.merge_global = merge_bytes > lds ? 1 : 0;
   if (!kp.merge_global) lds = merge_bytes > lds ? merge_bytes : lds;
@@ -221,6 +240,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   for (int b = 0; b < 2; ++b) {
     lay.sy[b] = o;  o = al256(o + 8 * (size_t)kp.cap * d2);
     lay.sa[b] = o;  o = al256(o + 16 * (size_t)kp.cap);
+    lay.sE[b] = o;  o = al256(o + 8 * (size_t)kp.cap * S);
     lay.ord[b] = o; o = al256(o + 4 * (size_t)kp.cap);
   }
   lay.dirty = o;  o = al256(o + 4 * (size_t)(kp.cap + 1));

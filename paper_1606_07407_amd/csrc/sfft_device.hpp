@@ -421,6 +421,158 @@ __device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* 
   __syncthreads();
 }
 
+// ---------------------------------------- batched small DFTs (FP32) ------
+// G independent L-point sequences back to back in LDS (G L <= MAXV kWG), one
+// Stockham radix-R pass over all of them: the later rounds' short transforms
+// then keep every thread busy instead of L / R of them.
+template <typename T, int R, int MAXV>
+__device__ void stockham_pass_b(cpx<T>* buf, int L, int lgn, int G, int Ns, const cpx<T>* T1,
+                                const cpx<T>* T2, bool inv) {
+  constexpr int NQ = MAXV / R;
+  cpx<T> v[MAXV];
+  const int nitems = L / R;  // per sequence, 1 << lgn
+  const int total = G * nitems;
+  const int tw_mul = L / (Ns * R);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int jj = tid + q * kWG;
+    if (jj < total) {
+      const int j = jj & (nitems - 1);
+      const cpx<T>* b = buf + (size_t)(jj >> lgn) * L;
+      const int k = j & (Ns - 1);
+      cpx<T> x[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = b[j + r * nitems];
+      if (Ns > 1) {
+        if (R == 16) {
+          cpx<T> w1 = twiddle(T1, T2, k * tw_mul);
+          cpx<T> w4 = twiddle(T1, T2, 4 * k * tw_mul);
+          cpx<T> w8 = twiddle(T1, T2, 8 * k * tw_mul);
+          if (inv) {
+            w1.y = -w1.y;
+            w4.y = -w4.y;
+            w8.y = -w8.y;
+          }
+          const cpx<T> w2 = cmul(w1, w1), w3 = cmul(w2, w1), w12 = cmul(w8, w4);
+          const cpx<T> lo[4] = {cmk<T>(1, 0), w1, w2, w3};
+          const cpx<T> hi[4] = {cmk<T>(1, 0), w4, w8, w12};
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const cpx<T> wr = (r & 3) == 0 ? hi[r >> 2]
+                              : (r >> 2) == 0 ? lo[r & 3]
+                                              : cmul(hi[r >> 2], lo[r & 3]);
+            x[r] = cmul(x[r], wr);
+          }
+        } else {
+          cpx<T> w1 = twiddle(T1, T2, k * tw_mul);
+          if (inv) w1.y = -w1.y;
+          cpx<T> wr = w1;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            x[r] = cmul(x[r], wr);
+            if (r + 1 < R) wr = cmul(wr, w1);
+          }
+        }
+      }
+      butterfly<T, R>(x, inv);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q * R + r] = x[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int jj = tid + q * kWG;
+    if (jj < total) {
+      const int j = jj & (nitems - 1);
+      cpx<T>* b = buf + (size_t)(jj >> lgn) * L;
+      const int k = j & (Ns - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) b[base + r * Ns] = v[q * R + r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int MAXV>
+__device__ __forceinline__ void fft_lds_batch(cpx<T>* buf, int L, int log2L, int G,
+                                              const cpx<T>* T1, const cpx<T>* T2, bool inv) {
+  int Ns = 1;
+  const int b = log2L & 3;
+  if (b & 1) {
+    stockham_pass_b<T, 2, MAXV>(buf, L, log2L - 1, G, Ns, T1, T2, inv);
+    Ns = 2;
+  }
+  if (b & 2) {
+    stockham_pass_b<T, 4, MAXV>(buf, L, log2L - 2, G, Ns, T1, T2, inv);
+    Ns *= 4;
+  }
+  while (Ns < L) {
+    stockham_pass_b<T, 16, MAXV>(buf, L, log2L - 4, G, Ns, T1, T2, inv);
+    Ns *= 16;
+  }
+}
+
+// Bluestein set-up with the twiddle tables at `tab` (outside the batch area):
+// chirp and the filter spectrum bhat as in bluestein_setup.
+template <typename T>
+__device__ __noinline__ void bluestein_setup_at(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
+                                   cpx<T>* buf, cpx<T>* tab) {
+  const int tid = threadIdx.x;
+  cpx<T>* T1 = tab;
+  cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
+  twiddle_tables<T>(L, T1, T2);
+  for (int n = tid; n < p; n += kWG) {
+    const int64_t q = ((int64_t)n * n) % (2 * (int64_t)p);
+    double c, s;
+    expipi(-(double)q / (double)p, &c, &s);
+    chirp[n] = cmk<T>((T)c, (T)s);
+  }
+  __syncthreads();
+  for (int n = tid; n < L; n += kWG) {
+    cpx<T> v = cmk<T>(0, 0);
+    if (n < p) {
+      v = chirp[n];
+    } else if (n > L - p) {
+      v = chirp[L - n];
+    }
+    v.y = -v.y;
+    buf[n] = v;
+  }
+  __syncthreads();
+  fft_lds<T>(buf, L, log2L, T1, T2, false);
+  for (int n = tid; n < L; n += kWG) bhat[n] = buf[n];
+  __syncthreads();
+}
+
+// G sequences x_g = x0 + g vstride (length p) transformed together, in place.
+template <typename T, int MAXV>
+__device__ __noinline__ void bluestein_dft_batch(cpx<T>* x0, int vstride, int G, int p, int L, int log2L,
+                                    const cpx<T>* chirp, const cpx<T>* bhat, cpx<T>* buf,
+                                    const cpx<T>* tab) {
+  const int tid = threadIdx.x;
+  const cpx<T>* T1 = tab;
+  const cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
+  const int n_all = G * L;
+  for (int n = tid; n < n_all; n += kWG) {
+    const int g = n >> log2L, m = n & (L - 1);
+    buf[n] = (m < p) ? cmul(x0[(size_t)g * vstride + m], chirp[m]) : cmk<T>(0, 0);
+  }
+  __syncthreads();
+  fft_lds_batch<T, MAXV>(buf, L, log2L, G, T1, T2, false);
+  for (int n = tid; n < n_all; n += kWG) buf[n] = cmul(buf[n], bhat[n & (L - 1)]);
+  __syncthreads();
+  fft_lds_batch<T, MAXV>(buf, L, log2L, G, T1, T2, true);
+  const T invL = (T)1 / (T)L;
+  for (int n = tid; n < G * p; n += kWG) {
+    const int g = n / p, m = n - g * p;
+    x0[(size_t)g * vstride + m] = cscale(cmul(buf[(size_t)g * L + m], chirp[m]), invL);
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------- exponential sums -------
 // (h * r) mod p exactly, for h, r < 2^16 with h * r < 2^32: the FP32 quotient
 // estimate is off by at most one, fixed branch-free in each direction

@@ -50,6 +50,7 @@ struct WsLayout {
   size_t afrag;    // float  [pairs_max][RT][64] MFMA A fragments (FP32 path)
   size_t sy[2];    // int64  [cap][d2]          registry keys by slot (two banks)
   size_t sa[2];    // double2[cap]              registry coefficients by slot
+  size_t sE[2];    // float2 [cap][S]           shift phases E_s(y) by slot (FP32 plans)
   size_t ord[2];   // int32  [cap]              slots in lexicographic order of y
   size_t dirty;    // int32  [cap]              slots whose exponential-sum rows are stale
   size_t V;        // cplx T [S1][vstride]      samples, then spectra
@@ -87,6 +88,7 @@ struct KParams {
   int lds_bytes;
   int merge_global;       // 1: the merge/sort arrays live in the slot, not in LDS
   int verify;             // verification round when |R| reaches k
+  int p_vmax;             // largest prime a verification round can use
   double verify_eta;
   int residual;           // 0: registry subtracted from the spectra, 1: from the samples
 };

@@ -22,6 +22,16 @@ __device__ __forceinline__ int64_t pmod64(int64_t a, int64_t m) {
   return r < 0 ? r + m : r;
 }
 
+// a mod p in [0, p) for |a| < 2^52 and 2 <= p < 2^20: the FP64 quotient
+// estimate is off by at most one, corrected in each direction.
+__device__ __forceinline__ int pmod_small(int64_t a, int p, double inv_p) {
+  const int64_t q = (int64_t)floor((double)a * inv_p);
+  int64_t r = a - q * (int64_t)p;
+  if (r < 0) r += p;
+  if (r >= p) r -= p;
+  return (int)r;
+}
+
 // Unwrapped shift phase exp(2 pi i eps K y) with eps = 1 / (2 NB):
 // q = K y mod 2 NB exactly, angle = pi q / NB.
 __device__ __forceinline__ cpx<double> shift_phase(int64_t y, int64_t K, int64_t NB) {
@@ -163,6 +173,9 @@ __device__ __forceinline__ double2* reg_a(const KParams& kp, char* slot, int ban
 __device__ __forceinline__ int* reg_ord(const KParams& kp, char* slot, int which) {
   return reinterpret_cast<int*>(slot + kp.lay.ord[which]);
 }
+__device__ __forceinline__ cpx<float>* reg_E(const KParams& kp, char* slot, int bank) {
+  return reinterpret_cast<cpx<float>*>(slot + kp.lay.sE[bank]);
+}
 
 // Exponential-sum operand of mode row j, set s: complex c into the MFMA A
 // fragments (FP32 path; same lane order as scatter_afrag) or the coefficient
@@ -291,7 +304,8 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   const int p = st.p, d2 = kp.d2;
   const int M = st.M_pl + st.nslots;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
-  uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
+  // LDS: twiddles [p] | residues [m_max + 4] | coefficients [m_max] | partial sums
+  uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16((size_t)p * sizeof(cpx<T>)));
   cpx<T>* coef = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(rr) +
                                            align16(2 * (size_t)(kp.m_max + 4)));
   cpx<T>* part = coef + kp.m_max;
@@ -305,12 +319,22 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     expipi(2.0 * (double)x / (double)p, &c, &sn);
     tw[x] = cmk<T>((T)c, (T)sn);
   }
+  const double inv_pd = 1.0 / (double)p;
   for (int j = threadIdx.x; j < M; j += kWG) {
     const int64_t* y = (j < st.M_pl) ? ypl + (size_t)j * d2 : ry + (size_t)(j - st.M_pl) * d2;
     int64_t r = 0, v = 1;
-    for (int n = 0; n < d2; ++n) {
-      r = (r + v * pmod64(y[n], p)) % p;
-      v = (v * q) % p;
+    if constexpr (sizeof(T) == 4) {
+      int r32 = 0, v32 = 1;
+      for (int n = 0; n < d2; ++n) {
+        r32 = (r32 + v32 * pmod_small(y[n], p, inv_pd)) % p;
+        v32 = (v32 * (int)q) % p;
+      }
+      r = r32;
+    } else {
+      for (int n = 0; n < d2; ++n) {
+        r = (r + v * pmod64(y[n], p)) % p;
+        v = (v * q) % p;
+      }
     }
     rr[j] = (uint16_t)r;
     if (j < st.M_pl) {
@@ -321,18 +345,52 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     }
   }
   __syncthreads();
-  // G threads per point when p is small; partial sums reduced through LDS
-  const int G = (p < kWG) ? kWG / p : 1;
+  // G threads per point when p is small; partial sums reduced through LDS.
+  // FP32: each thread takes 4 consecutive points (index stepped by r) so one
+  // residue and coefficient read feeds 4 products.
   const float inv_p = 1.0f / (float)p;
-  for (int t = threadIdx.x; t < G * p; t += kWG) {
-    const int h = t % p, g = t / p;
-    cpx<T> acc = cmk<T>(0, 0);
-    for (int j = g; j < M; j += G)
-      acc = cadd(acc, cmul(coef[j], tw[mulmod((uint32_t)h, (uint32_t)rr[j], p, inv_p)]));
-    if (G == 1)
-      V[h] = acc;
-    else
-      part[g * p + h] = acc;
+  int G;
+  if constexpr (sizeof(T) == 4) {
+    const int npg = (p + 3) / 4;
+    G = max(1, kWG / npg);
+    for (int t = threadIdx.x; t < G * npg; t += kWG) {
+      const int h0 = 4 * (t % npg), g = t / npg;
+      cpx<T> acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = cmk<T>(0, 0);
+      for (int j = g; j < M; j += G) {
+        const uint32_t r = rr[j];
+        const cpx<T> c = coef[j];
+        uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc[u] = cadd(acc[u], cmul(c, tw[idx]));
+          const uint32_t nx = idx + r;
+          idx = min(nx, nx - (uint32_t)p);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (h0 + u < p) {
+          if (G == 1)
+            V[h0 + u] = acc[u];
+          else
+            part[g * p + h0 + u] = acc[u];
+        }
+      }
+    }
+  } else {
+    G = (p < kWG) ? kWG / p : 1;
+    for (int t = threadIdx.x; t < G * p; t += kWG) {
+      const int h = t % p, g = t / p;
+      cpx<T> acc = cmk<T>(0, 0);
+      for (int j = g; j < M; j += G)
+        acc = cadd(acc, cmul(coef[j], tw[mulmod((uint32_t)h, (uint32_t)rr[j], p, inv_p)]));
+      if (G == 1)
+        V[h] = acc;
+      else
+        part[g * p + h] = acc;
+    }
   }
   __syncthreads();
   if (G > 1) {
@@ -362,6 +420,22 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
   cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
   cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
+  if constexpr (sizeof(T) == 4) {
+    // FP32: the twiddle tables sit after the whole L_max buffer so that up to
+    // min(L_max, 8192) / L sets are transformed together
+    constexpr int MAXV = MaxL<T>::value / 2 / kWG;
+    if (st.L <= MAXV * kWG && 2 * st.L <= kp.L_max) {
+      cpx<T>* tab = buf + kp.L_max;
+      bluestein_setup_at<T>(st.p, st.L, st.log2L, chirp, bhat, buf, tab);
+      const int cap = min(kp.L_max, MAXV * kWG) / st.L;
+      for (int s0 = 0; s0 < nsets; s0 += cap) {
+        const int g = min(cap, nsets - s0);
+        bluestein_dft_batch<T, MAXV>(V + (size_t)s0 * vstride, vstride, g, st.p, st.L, st.log2L,
+                                     chirp, bhat, buf, tab);
+      }
+      return;
+    }
+  }
   bluestein_setup<T>(st.p, st.L, st.log2L, chirp, bhat, buf);
   for (int s = 0; s < nsets; ++s)
     bluestein_dft<T>(V + (size_t)s * vstride, st.p, st.L, st.log2L, chirp, bhat, buf);
@@ -375,11 +449,93 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
 //   F_s[h] <- F_s[h] - p sum_{e in bucket h} a_e E_s(y_e)
 // equals the DFT of the residual samples f - g.  FP64 sums (entries of a
 // bucket in registry order), one rounding to T per spectrum value.
+// FP32 plans: entries grouped by bucket with a bitonic sort of (bucket, registry
+// position) keys, and the shift phases read from the per-slot cache.
+__device__ void subtract_registry_f32(const KParams& kp, char* slot, WgState& st, char* lds,
+                                      cpx<float>* V, int vstride, int nsets, int* sh_part) {
+  const int nR = st.nR;
+  const int p = st.p, d2 = kp.d2, m0 = st.m0, S = kp.S;
+  const int64_t* sy = reg_y(kp, slot, st.sb);
+  const double2* sa = reg_a(kp, slot, st.sb);
+  const cpx<float>* sE = reg_E(kp, slot, st.sb);
+  const int* ord = reg_ord(kp, slot, st.cur);
+  int N2 = 1;
+  while (N2 < nR) N2 <<= 1;
+  // LDS: bucket start [p + 1] | keys [N2], key = bucket << 16 | registry position,
+  // then the slot of each sorted position | coefficients in sorted order [nR]
+  int* start = reinterpret_cast<int*>(lds);
+  int* key = start + (p + 1);
+  double2* asort = reinterpret_cast<double2*>(lds + align16(4 * ((size_t)p + 1 + N2)));
+  for (int h = threadIdx.x; h <= p; h += kWG) start[h] = 0;
+  __syncthreads();
+  const double inv_pd = 1.0 / (double)p;
+  for (int e = threadIdx.x; e < N2; e += kWG) {
+    if (e < nR) {
+      int h = pmod_small(sy[(size_t)ord[e] * d2 + m0], p, inv_pd);
+      h = min(max(h, 0), p - 1);
+      key[e] = (h << 16) | e;
+      atomicAdd(&start[h], 1);
+    } else {
+      key[e] = 0x7fffffff;
+    }
+  }
+  __syncthreads();
+  block_exscan(start, p + 1, sh_part);
+  for (int size = 2; size <= N2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < N2 / 2; t += kWG) {
+        const int lo_i = 2 * t - (t & (stride - 1));
+        const int hi_i = lo_i + stride;
+        const bool asc = ((lo_i & size) == 0);
+        const int a = key[lo_i], b = key[hi_i];
+        if ((a > b) == asc) {
+          key[lo_i] = b;
+          key[hi_i] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int g = threadIdx.x; g < nR; g += kWG) {
+    const int sl = ord[key[g] & 0xffff];
+    key[g] = sl;
+    asort[g] = sa[sl];
+  }
+  __syncthreads();
+  const double pd = (double)p;
+  // set index fastest: neighbouring threads share a bucket's entries and read
+  // consecutive cached phases
+  for (int q = threadIdx.x; q < p * nsets; q += kWG) {
+    const int h = q / nsets, s = q - h * nsets;
+    const int b0 = start[h], b1 = start[h + 1];
+    if (b1 == b0) continue;
+    double ax = 0.0, ay = 0.0;
+    for (int g = b0; g < b1; ++g) {
+      const int sl = key[g];
+      double2 a = asort[g];
+      if (s > 0) {
+        const cpx<float> E = sE[(size_t)sl * S + s - 1];
+        a = make_double2(a.x * (double)E.x - a.y * (double)E.y,
+                         a.x * (double)E.y + a.y * (double)E.x);
+      }
+      ax += a.x;
+      ay += a.y;
+    }
+    cpx<float>* v = V + (size_t)s * vstride + h;
+    *v = cmk<float>((float)((double)v->x - pd * ax), (float)((double)v->y - pd * ay));
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __device__ void subtract_registry(const KParams& kp, char* slot, WgState& st, char* lds,
                                   cpx<T>* V, int vstride, int nsets, int* sh_part) {
   const int nR = st.nR;
   if (nR == 0) return;
+  if constexpr (sizeof(T) == 4) {
+    subtract_registry_f32(kp, slot, st, lds, V, vstride, nsets, sh_part);
+    return;
+  }
   const int p = st.p, d2 = kp.d2, m0 = st.m0;
   const int64_t* sy = reg_y(kp, slot, st.sb);
   const double2* sa = reg_a(kp, slot, st.sb);
@@ -822,6 +978,11 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
       const int src = o[e];
       for (int i = 0; i < d2; ++i) y1[(size_t)e * d2 + i] = y0[(size_t)src * d2 + i];
       a1[e] = a0[src];
+      if (sizeof(T) == 4 && !rows) {
+        const cpx<float>* E0 = reg_E(kp, slot, st.sb);
+        cpx<float>* E1 = reg_E(kp, slot, nb);
+        for (int s = 0; s < kp.S; ++s) E1[(size_t)e * kp.S + s] = E0[(size_t)src * kp.S + s];
+      }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nR; e += kWG) o[e] = e;
@@ -944,6 +1105,22 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
     ord2[runpos[u] + keep[u]] = sl;
   }
   __syncthreads();
+  // FP32 spectrum plans: shift phases of the new slots for subtract_registry
+  if (sizeof(T) == 4 && !rows) {
+    cpx<float>* sE = reg_E(kp, slot, st.sb);
+    for (int q = threadIdx.x; q < nU * kp.S; q += kWG) {
+      const int sl = ns0 + q / kp.S, s = 1 + q % kp.S;
+      int n0;
+      int64_t K;
+      shift_of(kp, s, &n0, &K);
+      // exp(i pi q / NB), q = K y mod 2 NB exact; the FP32 phase is what is stored
+      const int64_t qq = pmod64(K * sy[(size_t)sl * d2 + n0], 2 * kp.NB);
+      float sn, cs;
+      sincospif((float)((double)qq / (double)kp.NB), &sn, &cs);
+      sE[(size_t)sl * kp.S + s - 1] = cmk<float>(cs, sn);
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) st.nslots = ns0 + nU;
   // prune |a| < eta: zero coefficient (rows rebuilt as zero), dropped from the order
   const int nM = nR + nU;
