@@ -68,30 +68,41 @@ def exact_support(pb, h) -> np.ndarray:
     return ok
 
 
-def cpu_baseline(cfg, pb, n_sig: int) -> dict:
-    import oracle
+def _oracle_one(args):
+    """One signal through the FP64 oracle on one thread (run in a worker process)."""
+    cfg, b, w, a, k, sigma, seed = args
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
+        threadpool_limits(limits=1)
     except Exception:  # pragma: no cover
-        limiter = None
-    n_ok = 0
-    t0 = time.perf_counter()
+        pass
+    import oracle
+    P = oracle.Params(d=cfg["d"], N=cfg["N"], k=int(k), d1=cfg["d1"], c=cfg["c"],
+                      ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
+                      p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
+                      verify_eta=cfg["verify_eta"])
+    r = oracle.multiphaseshift(w, a, P, sigma=float(sigma), seed=seed, signal=b)
+    o = np.lexsort(w.T[::-1])
+    return int(r.status == 0 and r.freqs.shape == w.shape and np.array_equal(r.freqs, w[o]))
+
+
+def cpu_baseline(cfg, pb, n_sig: int, workers: int) -> dict:
+    """The oracle on the host: one signal per worker process (spawned, one thread each)."""
+    import multiprocessing as mp
+    jobs = []
     for b in range(n_sig):
         w, a = pb.signal(b)
-        P = oracle.Params(d=cfg["d"], N=cfg["N"], k=int(pb.k[b]), d1=cfg["d1"], c=cfg["c"],
-                          ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
-                          p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
-                          verify_eta=cfg["verify_eta"])
-        r = oracle.multiphaseshift(w, a, P, sigma=float(pb.sigma[b]), seed=pb.seed, signal=b)
-        o = np.lexsort(w.T[::-1])
-        n_ok += int(r.status == 0 and r.freqs.shape == w.shape and np.array_equal(r.freqs, w[o]))
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    return {"value": n_ok / dt, "unit": "recoveries/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sig} of the {pb.B} signals, FP64 NumPy oracle, one thread, "
-                      f"{dt:.1f} s, {n_ok}/{n_sig} exact"}
+        jobs.append((cfg, b, w, a, pb.k[b], pb.sigma[b], pb.seed))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_one, jobs[:workers])   # start-up outside the timed region
+        t0 = time.perf_counter()
+        n_ok = sum(pool.map(_oracle_one, jobs))
+        dt = time.perf_counter() - t0
+    return {"value": n_ok / dt, "unit": "recoveries/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {n_sig} of the {pb.B} signals, FP64 NumPy oracle, one process "
+                      f"per signal on {workers} host cores, {dt:.1f} s wall, "
+                      f"{n_ok}/{n_sig} exact"}
 
 
 def sources_sha256() -> str:
@@ -124,21 +135,66 @@ def profiled_traffic(workload: str):
 
 
 def time_recover(sfft, plan, db, B, steps, warmup):
+    """Warm-up launches, then `steps` timed launches: HIP events around each launch
+    and around the whole timed region, on the launch stream."""
     import torch
     out = sfft.alloc_outputs(plan, B)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         sfft.sfft_recover(plan, db, out, stream)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(steps):
+    evs[0].record(stream)
+    for i in range(steps):
         sfft.sfft_recover(plan, db, out, stream)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return out, wall / steps, ev0.elapsed_time(ev1) / steps
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return out, wall / steps, evs[0].elapsed_time(evs[steps]) / steps, per
+
+
+def main_part_share(sfft, plan, db, B) -> float:
+    """Fraction of the work-groups' busy time spent outside the planted-signal
+    sampler (the paper times its method without sampling), from the kernel's
+    phase timestamps of one extra launch."""
+    import torch
+    out = sfft.alloc_outputs(plan, B, phase=True)
+    sfft.sfft_recover(plan, db, out)
+    torch.cuda.synchronize()
+    ph = out["phase"].cpu().numpy().astype(np.float64)
+    tr = out["trace"].cpu().numpy()
+    rounds = out["rounds"].cpu().numpy()
+    samp = busy = 0.0
+    for b in range(B):
+        for r in range(int(rounds[b])):
+            if tr[b, r, 7]:
+                busy += ph[b, r, 6] - ph[b, r, 0]
+            else:
+                samp += ph[b, r, 1] - ph[b, r, 0]
+                busy += ph[b, r, 5] - ph[b, r, 0]
+    return 1.0 - samp / busy if busy > 0 else float("nan")
+
+
+def tolerance_curve(sfft, base, extra, kind, db, pb, B):
+    """Success rate and recoveries/s over the decision threshold: tau for the plain
+    ratio test, the probability threshold for the learned classifier."""
+    pts = []
+    grid = (3e-4, 1e-3, 3e-3, 1e-2) if kind == "plain" else (0.3, 0.5, 0.7, 0.9)
+    for x in grid:
+        over = dict(tau=x) if kind == "plain" else dict(mlp_threshold=x)
+        prm = dict(base)
+        prm.update(extra)
+        prm.update(over)
+        plan = sfft.sfft_plan_create(sfft.Params(**prm), max_batch=B)
+        out, step_s, gpu_ms, _ = time_recover(sfft, plan, db, B, 3, 1)
+        ok = exact_support(pb, sfft.outputs_to_host(out))
+        pts.append({("tau" if kind == "plain" else "threshold"): x,
+                    "success_rate": float(ok.mean()), "value": int(ok.sum()) / (gpu_ms * 1e-3),
+                    "kernel_ms": gpu_ms})
+        plan.close()
+    return pts
 
 
 def components(sfft, plan, pb, db, S1, p, m, steps):
@@ -203,9 +259,12 @@ def main():
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--classifier", default="both", choices=["both", "plain", "mlp"])
     ap.add_argument("--train-rows", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-components", action="store_true")
+    ap.add_argument("--no-curves", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="host processes for the oracle baseline (0: all cores, at most 16)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain copy of this size (traffic-counter calibration)")
     args = ap.parse_args()
@@ -236,7 +295,7 @@ def main():
                 robust=int(cfg["robust"]), verify=int(cfg["verify"]),
                 verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]))
     kinds = ["plain", "mlp"] if args.classifier == "both" else [args.classifier]
-    results, train_info, comp = {}, None, None
+    results, train_info, comp, curves = {}, None, None, {}
     for kind in kinds:
         extra = {}
         if kind == "mlp":
@@ -252,14 +311,22 @@ def main():
             del x, y, sid
             extra = dict(classifier=sfft.SFFT_CLS_MLP, mlp_weights=w, mlp_threshold=0.5)
         plan = sfft.sfft_plan_create(sfft.Params(**base, **extra), max_batch=B)
-        out, step_s, gpu_ms = time_recover(sfft, plan, db, B, args.steps, args.warmup)
+        out, step_s, gpu_ms, per = time_recover(sfft, plan, db, B, args.steps, args.warmup)
         h = sfft.outputs_to_host(out)
         ok = exact_support(pb, h)
         flops = algorithmic_flops(h["trace"], pb.k, plan.num_sets, int(cfg["residual"]))
         results[kind] = dict(value=int(ok.sum()) / step_s, success_rate=float(ok.mean()),
                              ms_per_step=step_s * 1e3, kernel_ms=gpu_ms,
+                             launch_ms_median=float(np.median(per)),
+                             launch_ms_min=float(np.min(per)),
                              mean_rounds=float(np.mean(h["rounds"])),
                              mean_samples=float(np.mean(h["samples"])), flops=flops)
+        if kind == "plain":
+            share = main_part_share(sfft, plan, db, B)
+            results[kind]["main_part_ms"] = gpu_ms * share
+            results[kind]["main_part_share"] = share
+        if not args.no_curves:
+            curves[kind] = tolerance_curve(sfft, base, extra, kind, db, pb, B)
         if kind == kinds[0] and not args.no_components:
             tr0 = h["trace"][0, 0]
             comp = components(sfft, plan, pb, db, plan.num_sets, int(tr0[2]), int(tr0[3]),
@@ -269,7 +336,7 @@ def main():
     # cores), same launch, plain classifier
     if not args.no_components:
         plan = sfft.sfft_plan_create(sfft.Params(**dict(base, residual=1)), max_batch=B)
-        out, step_s, gpu_ms = time_recover(sfft, plan, db, B, args.steps, args.warmup)
+        out, step_s, gpu_ms, _ = time_recover(sfft, plan, db, B, args.steps, args.warmup)
         h = sfft.outputs_to_host(out)
         ok = exact_support(pb, h)
         results["plain_residual_from_samples"] = dict(
@@ -312,6 +379,7 @@ def main():
         "learned_vs_plain": {k: {kk: v for kk, v in results[k].items() if kk != "flops"}
                              for k in results},
         "classifier_training": train_info,
+        "learned_vs_plain_curves": curves or None,
         "roofline": {
             "bound": "mfma",
             "achieved": achieved,
@@ -328,7 +396,9 @@ def main():
     if comp is not None:
         line["components"] = comp
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, pb, min(args.cpu_sample, B))
+        workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        line["cpu_baseline"] = cpu_baseline(cfg, pb, min(max(args.cpu_sample, workers), B),
+                                            workers)
     print(json.dumps(line), flush=True)
 
 

@@ -149,6 +149,12 @@ typedef struct {
   int32_t* feat_meta; /* [feat_cap][4] signal, round, bucket h, accepted (0/1)      */
   int64_t* feat_count;/* [1] records produced                                       */
   int64_t feat_cap;
+  /* Phase timestamps (optional, NULL = off): [B][max_rounds][SFFT_TRACE_W] device
+   * wall-clock ticks (100 MHz) taken by each work-group at the start of round i
+   * (0) and after its sampler (1), DFTs (2), registry subtraction and selection
+   * (3), test and decode (4) and merge (5); a verification round writes 0 and 6.
+   * Unused entries are left as they were. */
+  int64_t* phase;
 } sfft_outputs;
 
 /* Create a plan: validates `params` (SFFT_EINVAL / SFFT_ERANGE), derives the

@@ -369,6 +369,7 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
   ko.meta = out->feat_meta;
   ko.count = out->feat_count;
   ko.cap = nexp ? out->feat_cap : 0;
+  ko.phase = out->phase;
   int e = launch_zero_queue(plan->kp, out->feat_count, stream);
   if (e) return hip_fail((hipError_t)e, "queue reset launch");
   const int grid = std::min(batch->B, plan->kp.n_slots);

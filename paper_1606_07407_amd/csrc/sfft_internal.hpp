@@ -116,6 +116,7 @@ struct KOut {
   int32_t* meta;
   int64_t* count;
   int64_t cap;
+  int64_t* phase;         // [B][max_rounds][8] wall-clock ticks per phase (NULL: off)
 };
 
 // Launchers (defined in the .hip file).  Return a hipError_t as int.

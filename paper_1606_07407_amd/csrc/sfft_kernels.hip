@@ -1227,6 +1227,13 @@ __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgSt
   __syncthreads();
 }
 
+// Phase timestamp (device wall clock, 100 MHz) of the current round, when asked for.
+__device__ __forceinline__ void phase_mark(const KParams& kp, const KOut& ko, const WgState& st,
+                                           int ph) {
+  if (ko.phase && threadIdx.x == 0 && st.i <= kp.max_rounds)
+    ko.phase[((size_t)st.sig * kp.max_rounds + (st.i - 1)) * 8 + ph] = (int64_t)wall_clock64();
+}
+
 // ---------------------------------------------------------- the kernel ------
 template <typename T, int RT>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
@@ -1306,8 +1313,10 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
         __syncthreads();
         break;
       }
+      phase_mark(kp, ko, st, 0);
       if (at_k) {
         verify_round<T>(kp, kb, slot, st, lds, V, sh_part);
+        phase_mark(kp, ko, st, 6);
         if (threadIdx.x == 0) {
           st.samples += st.p;
           if (ko.trace) {
@@ -1339,13 +1348,18 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
         continue;
       }
       sample_round<T, RT>(kp, kb, slot, st, P0, lds, V, vstride);
+      phase_mark(kp, ko, st, 1);
       dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
+      phase_mark(kp, ko, st, 2);
       if (kp.residual == 0) subtract_registry<T>(kp, slot, st, lds, V, vstride, kp.S1, sh_part);
       select_round<T>(kp, slot, st, lds, V, sh_part);
+      phase_mark(kp, ko, st, 3);
       decode_round<T>(kp, ko, slot, st, V, vstride, lds, sh_part);
       if (ko.feat) export_round(kp, kb, ko, slot, st, lds);
       decode_finish(kp, st, lds, sh_part);
+      phase_mark(kp, ko, st, 4);
       merge_round<T>(kp, slot, st, lds, sh_part, P0);
+      phase_mark(kp, ko, st, 5);
       if (threadIdx.x == 0) {
         st.samples += (int64_t)kp.S1 * st.p;
         if (ko.trace) {

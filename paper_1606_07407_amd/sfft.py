@@ -64,6 +64,7 @@ class sfft_outputs(ctypes.Structure):
         ("trace", ctypes.c_void_p), ("feat", ctypes.c_void_p), ("label", ctypes.c_void_p),
         ("feat_meta", ctypes.c_void_p), ("feat_count", ctypes.c_void_p),
         ("feat_cap", ctypes.c_int64),
+        ("phase", ctypes.c_void_p),
     ]
 
 
@@ -259,7 +260,7 @@ class DeviceBatch:
 
 
 def alloc_outputs(plan: Plan, B: int, trace: bool = True, device="cuda",
-                  export_cap: int = 0) -> dict:
+                  export_cap: int = 0, phase: bool = False) -> dict:
     torch = _torch()
     P = plan.params
     if export_cap > 0:
@@ -279,6 +280,8 @@ def alloc_outputs(plan: Plan, B: int, trace: bool = True, device="cuda",
         samples=torch.zeros(B, dtype=torch.int64, device=device),
         trace=(torch.zeros((B, P.max_rounds, SFFT_TRACE_W), dtype=torch.int32, device=device)
                if trace else None),
+        phase=(torch.zeros((B, P.max_rounds, SFFT_TRACE_W), dtype=torch.int64, device=device)
+               if phase else None),
     )
     return out
 
@@ -290,7 +293,8 @@ def sfft_recover(plan: Plan, batch: DeviceBatch, out: dict | None = None, stream
     o = sfft_outputs(_ptr(out["freqs"]), _ptr(out["coeffs"]), _ptr(out["k_found"]),
                      _ptr(out["status"]), _ptr(out.get("rounds")), _ptr(out.get("samples")),
                      _ptr(out.get("trace")), _ptr(out.get("feat")), _ptr(out.get("label")),
-                     _ptr(out.get("feat_meta")), _ptr(out.get("feat_count")), cap)
+                     _ptr(out.get("feat_meta")), _ptr(out.get("feat_count")), cap,
+                     _ptr(out.get("phase")))
     b = batch.to_c()
     _check(lib().sfft_recover(plan.handle, ctypes.byref(b), ctypes.byref(o), _stream(stream)),
            "sfft_recover")
