@@ -367,6 +367,75 @@ __device__ __forceinline__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx
     fft_lds_large<T>(buf, L, log2L, T1, T2, inv);
 }
 
+// Element-wise Bluestein steps with the global loads of U consecutive thread
+// strides issued together (one memory latency per U elements instead of per
+// element).  buf has n_all points of G sequences of length L (2^log2L).
+constexpr int kLoadBlock = 8;
+
+template <typename T>
+__device__ __forceinline__ void bs_chirp_in(cpx<T>* buf, const cpx<T>* x0, int vstride, int n_all,
+                                            int p, int L, int log2L, const cpx<T>* chirp) {
+  for (int n0 = threadIdx.x; n0 < n_all; n0 += kLoadBlock * kWG) {
+    cpx<T> xv[kLoadBlock], cv[kLoadBlock];
+#pragma unroll
+    for (int u = 0; u < kLoadBlock; ++u) {
+      const int n = n0 + u * kWG;
+      const int g = n >> log2L, m = n & (L - 1);
+      xv[u] = cmk<T>(0, 0);
+      cv[u] = cmk<T>(0, 0);
+      if (n < n_all && m < p) {
+        xv[u] = x0[(size_t)g * vstride + m];
+        cv[u] = chirp[m];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBlock; ++u) {
+      const int n = n0 + u * kWG;
+      if (n < n_all) buf[n] = cmul(xv[u], cv[u]);
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bs_filter(cpx<T>* buf, int n_all, int L, const cpx<T>* bhat) {
+  for (int n0 = threadIdx.x; n0 < n_all; n0 += kLoadBlock * kWG) {
+    cpx<T> hv[kLoadBlock];
+#pragma unroll
+    for (int u = 0; u < kLoadBlock; ++u) {
+      const int n = n0 + u * kWG;
+      hv[u] = (n < n_all) ? bhat[n & (L - 1)] : cmk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBlock; ++u) {
+      const int n = n0 + u * kWG;
+      if (n < n_all) buf[n] = cmul(buf[n], hv[u]);
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bs_chirp_out(cpx<T>* x0, int vstride, int G, int p, int L,
+                                             const cpx<T>* buf, const cpx<T>* chirp) {
+  const T invL = (T)1 / (T)L;
+  const int n_out = G * p;
+  for (int n0 = threadIdx.x; n0 < n_out; n0 += kLoadBlock * kWG) {
+    cpx<T> cv[kLoadBlock];
+#pragma unroll
+    for (int u = 0; u < kLoadBlock; ++u) {
+      const int n = n0 + u * kWG;
+      cv[u] = (n < n_out) ? chirp[n % p] : cmk<T>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBlock; ++u) {
+      const int n = n0 + u * kWG;
+      if (n < n_out) {
+        const int g = n / p, m = n - g * p;
+        x0[(size_t)g * vstride + m] = cscale(cmul(buf[(size_t)g * L + m], cv[u]), invL);
+      }
+    }
+  }
+}
+
 // Bluestein set-up for prime length p and power-of-two L >= 2p - 1:
 // chirp[n] = exp(-i pi (n^2 mod 2p) / p) and bhat = FFT_L(b),
 // b[n] = conj(chirp[n]) for |n| < p (wrapped mod L), 0 elsewhere.  Also
@@ -410,6 +479,17 @@ __device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* 
   const int tid = threadIdx.x;
   const cpx<T>* T1 = buf + L;
   const cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
+  if constexpr (sizeof(T) == 4) {
+    bs_chirp_in<T>(buf, x, 0, L, p, L, log2L, chirp);
+    __syncthreads();
+    fft_lds<T>(buf, L, log2L, T1, T2, false);
+    bs_filter<T>(buf, L, L, bhat);
+    __syncthreads();
+    fft_lds<T>(buf, L, log2L, T1, T2, true);
+    bs_chirp_out<T>(x, 0, 1, p, L, buf, chirp);
+    __syncthreads();
+    return;
+  }
   for (int n = tid; n < L; n += kWG) buf[n] = (n < p) ? cmul(x[n], chirp[n]) : cmk<T>(0, 0);
   __syncthreads();
   fft_lds<T>(buf, L, log2L, T1, T2, false);
@@ -556,20 +636,14 @@ __device__ __noinline__ void bluestein_dft_batch(cpx<T>* x0, int vstride, int G,
   const cpx<T>* T1 = tab;
   const cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
   const int n_all = G * L;
-  for (int n = tid; n < n_all; n += kWG) {
-    const int g = n >> log2L, m = n & (L - 1);
-    buf[n] = (m < p) ? cmul(x0[(size_t)g * vstride + m], chirp[m]) : cmk<T>(0, 0);
-  }
+  (void)tid;
+  bs_chirp_in<T>(buf, x0, vstride, n_all, p, L, log2L, chirp);
   __syncthreads();
   fft_lds_batch<T, MAXV>(buf, L, log2L, G, T1, T2, false);
-  for (int n = tid; n < n_all; n += kWG) buf[n] = cmul(buf[n], bhat[n & (L - 1)]);
+  bs_filter<T>(buf, n_all, L, bhat);
   __syncthreads();
   fft_lds_batch<T, MAXV>(buf, L, log2L, G, T1, T2, true);
-  const T invL = (T)1 / (T)L;
-  for (int n = tid; n < G * p; n += kWG) {
-    const int g = n / p, m = n - g * p;
-    x0[(size_t)g * vstride + m] = cscale(cmul(buf[(size_t)g * L + m], chirp[m]), invL);
-  }
+  bs_chirp_out<T>(x0, vstride, G, p, L, buf, chirp);
   __syncthreads();
 }
 
