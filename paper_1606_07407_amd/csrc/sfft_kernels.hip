@@ -504,25 +504,44 @@ __device__ void subtract_registry_f32(const KParams& kp, char* slot, WgState& st
   __syncthreads();
   const double pd = (double)p;
   // set index fastest: neighbouring threads share a bucket's entries and read
-  // consecutive cached phases
-  for (int q = threadIdx.x; q < p * nsets; q += kWG) {
-    const int h = q / nsets, s = q - h * nsets;
-    const int b0 = start[h], b1 = start[h + 1];
-    if (b1 == b0) continue;
-    double ax = 0.0, ay = 0.0;
-    for (int g = b0; g < b1; ++g) {
-      const int sl = key[g];
-      double2 a = asort[g];
-      if (s > 0) {
-        const cpx<float> E = sE[(size_t)sl * S + s - 1];
-        a = make_double2(a.x * (double)E.x - a.y * (double)E.y,
-                         a.x * (double)E.y + a.y * (double)E.x);
+  // consecutive cached phases.  U items per thread at a time, so that the
+  // phase loads of their first entries are in flight together.
+  constexpr int U = 8;
+  const int nq = p * nsets;
+  for (int q0 = threadIdx.x; q0 < nq; q0 += U * kWG) {
+    int hh[U], ss[U], bb0[U], bb1[U];
+    cpx<float> E0[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * kWG;
+      hh[u] = 0;
+      ss[u] = 0;
+      bb0[u] = 0;
+      bb1[u] = 0;
+      E0[u] = cmk<float>(1.f, 0.f);
+      if (q < nq) {
+        hh[u] = q / nsets;
+        ss[u] = q - hh[u] * nsets;
+        bb0[u] = start[hh[u]];
+        bb1[u] = start[hh[u] + 1];
+        if (bb1[u] > bb0[u] && ss[u] > 0) E0[u] = sE[(size_t)key[bb0[u]] * S + ss[u] - 1];
       }
-      ax += a.x;
-      ay += a.y;
     }
-    cpx<float>* v = V + (size_t)s * vstride + h;
-    *v = cmk<float>((float)((double)v->x - pd * ax), (float)((double)v->y - pd * ay));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (bb1[u] == bb0[u]) continue;
+      const int s = ss[u];
+      double ax = 0.0, ay = 0.0;
+      for (int g = bb0[u]; g < bb1[u]; ++g) {
+        const cpx<float> E = (g == bb0[u]) ? E0[u]
+                             : (s > 0 ? sE[(size_t)key[g] * S + s - 1] : cmk<float>(1.f, 0.f));
+        const double2 a = asort[g];
+        ax += a.x * (double)E.x - a.y * (double)E.y;
+        ay += a.x * (double)E.y + a.y * (double)E.x;
+      }
+      cpx<float>* v = V + (size_t)s * vstride + hh[u];
+      *v = cmk<float>((float)((double)v->x - pd * ax), (float)((double)v->y - pd * ay));
+    }
   }
   __syncthreads();
 }
