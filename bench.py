@@ -28,6 +28,8 @@ import workloads  # noqa: E402
 METRIC = "signal recoveries/sec at exact support, d=10 k=1000; learned vs plain"
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X FP32 vector
+TUNE_C_OFFSETS = (-1.0, -0.5, 0.0, 0.5)  # c values the autotuner measures around the recipe's c
+TUNE_WARMUP, TUNE_STEPS = 1, 5
 
 
 def algorithmic_flops(trace: np.ndarray, k: np.ndarray, S1: int, residual: int = 0) -> float:
@@ -77,13 +79,15 @@ def _oracle_one(args):
     except Exception:  # pragma: no cover
         pass
     import oracle
+    t0 = time.perf_counter()
     P = oracle.Params(d=cfg["d"], N=cfg["N"], k=int(k), d1=cfg["d1"], c=cfg["c"],
                       ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
                       p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
                       verify_eta=cfg["verify_eta"])
     r = oracle.multiphaseshift(w, a, P, sigma=float(sigma), seed=seed, signal=b)
     o = np.lexsort(w.T[::-1])
-    return int(r.status == 0 and r.freqs.shape == w.shape and np.array_equal(r.freqs, w[o]))
+    ok = int(r.status == 0 and r.freqs.shape == w.shape and np.array_equal(r.freqs, w[o]))
+    return ok, time.perf_counter() - t0
 
 
 def cpu_baseline(cfg, pb, n_sig: int, workers: int) -> dict:
@@ -97,12 +101,16 @@ def cpu_baseline(cfg, pb, n_sig: int, workers: int) -> dict:
     with ctx.Pool(workers) as pool:
         pool.map(_oracle_one, jobs[:workers])   # start-up outside the timed region
         t0 = time.perf_counter()
-        n_ok = sum(pool.map(_oracle_one, jobs))
+        res = pool.map(_oracle_one, jobs)
         dt = time.perf_counter() - t0
+    n_ok = sum(r[0] for r in res)
+    busy = sum(r[1] for r in res)
     return {"value": n_ok / dt, "unit": "recoveries/s", "cores": workers, "kind": "oracle",
+            "value_one_core": n_ok / busy,
             "sample": f"first {n_sig} of the {pb.B} signals, FP64 NumPy oracle, one process "
                       f"per signal on {workers} host cores, {dt:.1f} s wall, "
-                      f"{n_ok}/{n_sig} exact"}
+                      f"{n_ok}/{n_sig} exact; value_one_core = exact signals per second "
+                      f"of single-thread oracle time ({busy:.1f} s)"}
 
 
 def sources_sha256() -> str:
@@ -119,9 +127,15 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(workload: str):
+def plan_key(params) -> str:
+    """The launch configuration a profile was taken with: c and the kernel schedules."""
+    nt = "-".join(str(int(v)) for v in params.sched_nt)
+    return f"c:{params.c:g},nt:{nt},fft:{params.sched_fft},batch:{params.sched_dft_batch}"
+
+
+def profiled_traffic(workload: str, params):
     """HBM bytes per recover_kernel launch from the committed counter summary, or None
-    when that summary was taken on other sources than the current ones."""
+    when that summary was taken on other sources or another launch configuration."""
     path = os.path.join(ROOT, "profiles", f"recover_kernel_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -130,8 +144,19 @@ def profiled_traffic(workload: str):
             kv = dict(t.split("=", 1) for t in line.split()[1:])
             if kv.get("sources_sha256") != sources_sha256():
                 return None
+            if kv.get("plan", plan_key(params)) != plan_key(params):
+                return None
             return float(kv["read_bytes"]) + float(kv["write_bytes"])
     return None
+
+
+def autotune(sfft, params, db, c_values=None):
+    """c and the kernel schedules picked by the library's autotuner on the batch itself
+    (c_values: default the recipe's c - 1, c - 0.5, c and c + 0.5)."""
+    if c_values is None:
+        c_values = [round(params.c + dc, 4) for dc in TUNE_C_OFFSETS if params.c + dc > 1.0]
+    return sfft.sfft_autotune(params, db, c_values=c_values, warmup=TUNE_WARMUP,
+                              steps=TUNE_STEPS)
 
 
 def time_recover(sfft, plan, db, B, steps, warmup):
@@ -253,8 +278,8 @@ def calibration_copy(mib: int, reps: int = 3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c3b")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--classifier", default="both", choices=["both", "plain", "mlp"])
@@ -267,6 +292,11 @@ def main():
                     help="host processes for the oracle baseline (0: all cores, at most 16)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain copy of this size (traffic-counter calibration)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (use --c / --sched or the recipe's values)")
+    ap.add_argument("--c", type=float, default=None, help="c instead of the recipe's")
+    ap.add_argument("--sched", default=None,
+                    help="kernel schedules nt0-nt1-nt2-nt3,fft,batch (e.g. 0-0-0-0,2,0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); signals are "
@@ -294,6 +324,24 @@ def main():
                 precision=sfft.SFFT_FP32 if cfg["precision"] == "fp32" else sfft.SFFT_FP64,
                 robust=int(cfg["robust"]), verify=int(cfg["verify"]),
                 verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]))
+    if args.c is not None:
+        base["c"] = args.c
+    if args.sched:
+        nt, fft, batch = args.sched.split(",")
+        base.update(sched_nt=tuple(int(v) for v in nt.split("-")), sched_fft=int(fft),
+                    sched_dft_batch=int(batch))
+    tune_info = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tuned, log = autotune(sfft, sfft.Params(**base), db)
+        base.update(c=tuned.c, sched_nt=tuned.sched_nt, sched_fft=tuned.sched_fft,
+                    sched_dft_batch=tuned.sched_dft_batch)
+        tune_info = {"chosen": plan_key(tuned), "seconds": time.perf_counter() - t0,
+                     "candidates": [[e["c"], "-".join(map(str, e["sched_nt"])), e["sched_fft"],
+                                     e["sched_dft_batch"], e["status"], e["exact"],
+                                     round(e["ms"], 4)] for e in log],
+                     "columns": ["c", "sched_nt", "sched_fft", "sched_dft_batch", "status",
+                                 "exact", "median_ms"]}
     kinds = ["plain", "mlp"] if args.classifier == "both" else [args.classifier]
     results, train_info, comp, curves = {}, None, None, {}
     for kind in kinds:
@@ -368,11 +416,13 @@ def main():
             "workload": f"{args.config}: B={B} d={cfg['d']} N={cfg['N']} k={cfg['k']} "
                         f"sigma={cfg['sigma']} |a|~U{list(cfg['mag'])}",
             "batch": B, "d": cfg["d"], "N": cfg["N"], "k": cfg["k"], "d1": cfg["d1"],
-            "c": cfg["c"], "ladder_K": cfg["ladder_K"], "tau": cfg["tau"], "eta": cfg["eta"],
+            "c": base["c"], "ladder_K": cfg["ladder_K"], "tau": cfg["tau"], "eta": cfg["eta"],
             "p_min": cfg["p_min"], "verify": cfg["verify"], "verify_eta": cfg["verify_eta"],
             "classifier": best,
+            "plan": plan_key(sfft.Params(**base)),
             "parallelism": "one GPU, one work-group per signal",
         },
+        "autotune": tune_info,
         "success_rate": r["success_rate"],
         "mean_rounds": r["mean_rounds"],
         "mean_samples": r["mean_samples"],
@@ -386,7 +436,8 @@ def main():
             "peak": PEAK_FP32_MFMA,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_MFMA,
-            "traffic": profiled_traffic(args.config) if best == "plain" else None,
+            "traffic": (profiled_traffic(args.config, sfft.Params(**base)) if best == "plain"
+                        else None),
             "traffic_unit": "bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
             "kernel": f"recover_kernel (persistent, whole recovery, {best} classifier)",
             "kernel_ms": r["kernel_ms"],

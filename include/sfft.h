@@ -106,6 +106,20 @@ typedef struct {
                               entries of each bucket, subtracted from the spectra in
                               FP64 -- the same spectra with O(|R| (S+1)) instead of
                               O(p |R| (S+1)) work                                      */
+  /* Kernel schedules: how the kernels tile their work.  Every choice gives the
+   * same results up to FP32 rounding; 0 takes the built-in choice, and
+   * sfft_autotune picks them by measurement. */
+  int32_t sched_nt[4];     /* FP32 sampler: 16-point column tiles per wave in rounds
+                              with p < 320, < 640, < 1600 and >= 1600: 2 or 4, or 8 in
+                              the last two bands (below 640 points the chunked FP32
+                              accumulation needs at most 4); 0 = chosen from p      */
+  int32_t sched_fft;       /* passes of the power-of-two FFTs inside Bluestein, L = 2^n:
+                              1 = a radix-2 (n odd) and a radix-4 (n mod 4 >= 2) head
+                              pass, then radix 16; 2 = the same, except one radix-8
+                              head pass when n = 3 mod 4; 0 = 1                      */
+  int32_t sched_dft_batch; /* FP32: most sample sets transformed together in one
+                              Bluestein pass over the LDS buffer: 1 = one set at a
+                              time, 2..64, 0 = as many as fit                        */
 } sfft_params;
 
 /* A batch of synthetic black-box signals with planted spectra.  All pointers
@@ -222,6 +236,41 @@ sfft_status sfft_mlp_train(void* w, const float* x, const uint8_t* y, int64_t n,
  * per round (S+1). */
 int32_t sfft_plan_max_prime(sfft_plan plan);
 int32_t sfft_plan_num_sets(sfft_plan plan);
+
+/* One candidate measured by sfft_autotune. */
+typedef struct {
+  double c;                /* oversampling factor                                    */
+  int32_t sched_nt[4];     /* schedules, as in sfft_params                           */
+  int32_t sched_fft;
+  int32_t sched_dft_batch;
+  int32_t status;          /* SFFT_OK, or why the candidate's plan was refused       */
+  int32_t exact;           /* signals with status SFFT_OK whose recovered support
+                              equals the batch's planted support                    */
+  double ms;               /* median duration of the timed launches                 */
+} sfft_tune_entry;
+
+/* Autotuner (a measurement around the method, not part of it): picks c and the
+ * kernel schedules for `batch` by timing whole recoveries on `stream`.
+ * Stage 1 measures every c of c_values (host array of n_c values; n_c = 0 keeps
+ * params->c) with the schedules of *params.  Stage 2 changes one schedule at a
+ * time from the best so far -- sched_fft; for FP32 plans also sched_dft_batch
+ * over {0, 1, 2, 4, 8} and each band of sched_nt over its allowed values -- and
+ * keeps a change only when it is more than 2% faster with at least as many
+ * exact recoveries.  Candidates rank by exact recoveries, then by the median
+ * of `steps` timed launches (HIP events on `stream`) after `warmup` untimed
+ * ones.  A candidate whose plan cannot be created (e.g. a c whose first prime
+ * needs more LDS than a work-group has) is logged with that status and skipped.
+ * On SFFT_OK, *params holds the winner (only c and the sched_* fields change),
+ * log[0 .. min(*n_log, log_cap)) the candidates in the order measured (log may
+ * be NULL when log_cap = 0) and *n_log their number.  Creates one plan per
+ * candidate and the output buffers of the batch (device memory, all freed
+ * before returning); copies the batch's planted frequencies and each
+ * candidate's results to the host; synchronises `stream`.  SFFT_EINVAL for bad
+ * arguments; plan and launch errors other than a refused candidate are
+ * returned as they are. */
+sfft_status sfft_autotune(sfft_params* params, const sfft_signal_batch* batch,
+                          const double* c_values, int32_t n_c, int32_t warmup, int32_t steps,
+                          sfft_tune_entry* log, int32_t log_cap, int32_t* n_log, void* stream);
 
 /* Text of the last error on this thread ("" if none). */
 const char* sfft_last_error(void);

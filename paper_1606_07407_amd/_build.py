@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsfft.so")
-SOURCES = ["sfft_kernels.hip", "sfft_mlp.hip", "sfft_abi.cpp"]
+SOURCES = ["sfft_kernels.hip", "sfft_mlp.hip", "sfft_abi.cpp", "sfft_tune.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

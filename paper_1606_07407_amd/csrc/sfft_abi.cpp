@@ -51,6 +51,11 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+namespace sfft {
+// Error text for the other host sources of the library (the autotuner).
+sfft_status set_error(sfft_status st, const char* msg) { return fail(st, "%s", msg); }
+}  // namespace sfft
+
 struct sfft_plan_s {
   sfft_params prm;
   int device = 0;
@@ -99,6 +104,15 @@ static sfft_status validate_params(const sfft_params* p) {
   if (!std::isfinite(p->verify_eta)) return fail(SFFT_EINVAL, "verify_eta must be finite");
   if (p->residual != SFFT_RESIDUAL_SPECTRUM && p->residual != SFFT_RESIDUAL_SAMPLES)
     return fail(SFFT_EINVAL, "unknown residual mode");
+  for (int b = 0; b < kNtBands; ++b) {
+    const int v = p->sched_nt[b];
+    const bool ok = v == 0 || v == 2 || v == 4 || (v == 8 && b >= 2);
+    if (!ok) return fail(SFFT_EINVAL, "sched_nt[%d] = %d is not allowed", b, v);
+  }
+  if (p->sched_fft < 0 || p->sched_fft > kFftRadix8Head)
+    return fail(SFFT_EINVAL, "unknown sched_fft %d", p->sched_fft);
+  if (p->sched_dft_batch < 0 || p->sched_dft_batch > 64)
+    return fail(SFFT_EINVAL, "sched_dft_batch must be in 0..64");
   return SFFT_OK;
 }
 
@@ -151,6 +165,9 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.feat_scale = (P.feature_scale > 0.0) ? P.feature_scale : kp.tau;
   kp.verify = P.verify;
   kp.residual = P.residual;
+  for (int b = 0; b < kNtBands; ++b) kp.sched_nt[b] = P.sched_nt[b];
+  kp.sched_fft = P.sched_fft ? P.sched_fft : kFftRadix24Head;
+  kp.sched_dft_batch = P.sched_dft_batch;
   kp.verify_eta = (P.verify_eta > 0.0) ? P.verify_eta : P.eta;
 
   // Largest prime a round can use: the max_rounds-th rule prime >= max(ceil(c k_max), p_min),

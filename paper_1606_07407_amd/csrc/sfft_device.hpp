@@ -207,6 +207,29 @@ __device__ __forceinline__ void butterfly(cpx<T>* x, bool inv) {
     for (int k1 = 0; k1 < 4; ++k1)
 #pragma unroll
       for (int k2 = 0; k2 < 4; ++k2) x[k1 + 4 * k2] = y[4 * k1 + k2];
+  } else if (R == 8) {
+    // n = 4 n1 + n2, k = k1 + 2 k2: DFT2 over n1, twiddle W8^{n2 k1}, DFT4 over n2.
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      const cpx<T> a = x[n2], b = x[4 + n2];
+      x[n2] = cadd(a, b);
+      x[4 + n2] = csub(a, b);
+    }
+    const T h = (T)0.70710678118654752440;
+    const T sg = inv ? (T)1 : (T)-1;  // sign of the imaginary part of W8^1 and W8^2
+    x[5] = cmul(x[5], cmk<T>(h, sg * h));
+    x[6] = cmul(x[6], cmk<T>(0, sg));
+    x[7] = cmul(x[7], cmk<T>(-h, sg * h));
+    dft4<T>(x, 1, inv);
+    dft4<T>(x + 4, 1, inv);
+    // x[4 k1 + k2] holds X[k1 + 2 k2]
+    cpx<T> y[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y[i] = x[i];
+#pragma unroll
+    for (int k1 = 0; k1 < 2; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) x[k1 + 2 * k2] = y[4 * k1 + k2];
   } else if (R == 2) {
     const cpx<T> a = x[0], b = x[1];
     x[0] = cadd(a, b);
@@ -329,14 +352,17 @@ __device__ void twiddle_tables(int L, cpx<T>* T1, cpx<T>* T2) {
 // passes for b, then a radix-16 passes.  MAXV = L / kWG items per thread.
 template <typename T, int MAXV>
 __device__ __forceinline__ void fft_lds_v(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
-                                          const cpx<T>* T2, bool inv) {
+                                          const cpx<T>* T2, bool inv, int fs) {
   int Ns = 1;
   const int b = log2L & 3;
-  if (b & 1) {
+  if (b == 3 && fs == kFftRadix8Head) {
+    stockham_pass<T, 8, MAXV>(buf, L, Ns, T1, T2, inv);
+    Ns = 8;
+  } else if (b & 1) {
     stockham_pass<T, 2, MAXV>(buf, L, Ns, T1, T2, inv);
     Ns = 2;
   }
-  if (b & 2) {
+  if ((b & 2) && Ns < 8) {
     stockham_pass<T, 4, MAXV>(buf, L, Ns, T1, T2, inv);
     Ns *= 4;
   }
@@ -351,20 +377,20 @@ __device__ __forceinline__ void fft_lds_v(cpx<T>* buf, int L, int log2L, const c
 // spills) of every caller for all lengths.
 template <typename T>
 __device__ __noinline__ void fft_lds_large(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
-                                           const cpx<T>* T2, bool inv) {
-  fft_lds_v<T, MaxL<T>::value / kWG>(buf, L, log2L, T1, T2, inv);
+                                           const cpx<T>* T2, bool inv, int fs) {
+  fft_lds_v<T, MaxL<T>::value / kWG>(buf, L, log2L, T1, T2, inv, fs);
 }
 
 // L <= MaxL<T>.  Lengths up to half the maximum take the inlined variant with
 // half the per-thread registers.
 template <typename T>
 __device__ __forceinline__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
-                                        const cpx<T>* T2, bool inv) {
+                                        const cpx<T>* T2, bool inv, int fs) {
   constexpr int HALF = MaxL<T>::value / 2 / kWG;
   if (L <= HALF * kWG)
-    fft_lds_v<T, HALF>(buf, L, log2L, T1, T2, inv);
+    fft_lds_v<T, HALF>(buf, L, log2L, T1, T2, inv, fs);
   else
-    fft_lds_large<T>(buf, L, log2L, T1, T2, inv);
+    fft_lds_large<T>(buf, L, log2L, T1, T2, inv, fs);
 }
 
 // Element-wise Bluestein steps with the global loads of U consecutive thread
@@ -442,7 +468,7 @@ __device__ __forceinline__ void bs_chirp_out(cpx<T>* x0, int vstride, int G, int
 // fills the LDS twiddle tables that follow the L-point buffer.
 template <typename T>
 __device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
-                                cpx<T>* buf) {
+                                cpx<T>* buf, int fs) {
   const int tid = threadIdx.x;
   cpx<T>* T1 = buf + L;
   cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
@@ -465,7 +491,7 @@ __device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* 
     buf[n] = v;
   }
   __syncthreads();
-  fft_lds<T>(buf, L, log2L, T1, T2, false);
+  fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
   for (int n = tid; n < L; n += kWG) bhat[n] = buf[n];
   __syncthreads();
 }
@@ -475,27 +501,27 @@ __device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* 
 // twiddle tables written by bluestein_setup.
 template <typename T>
 __device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* chirp,
-                              const cpx<T>* bhat, cpx<T>* buf) {
+                              const cpx<T>* bhat, cpx<T>* buf, int fs) {
   const int tid = threadIdx.x;
   const cpx<T>* T1 = buf + L;
   const cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
   if constexpr (sizeof(T) == 4) {
     bs_chirp_in<T>(buf, x, 0, L, p, L, log2L, chirp);
     __syncthreads();
-    fft_lds<T>(buf, L, log2L, T1, T2, false);
+    fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
     bs_filter<T>(buf, L, L, bhat);
     __syncthreads();
-    fft_lds<T>(buf, L, log2L, T1, T2, true);
+    fft_lds<T>(buf, L, log2L, T1, T2, true, fs);
     bs_chirp_out<T>(x, 0, 1, p, L, buf, chirp);
     __syncthreads();
     return;
   }
   for (int n = tid; n < L; n += kWG) buf[n] = (n < p) ? cmul(x[n], chirp[n]) : cmk<T>(0, 0);
   __syncthreads();
-  fft_lds<T>(buf, L, log2L, T1, T2, false);
+  fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
   for (int n = tid; n < L; n += kWG) buf[n] = cmul(buf[n], bhat[n]);
   __syncthreads();
-  fft_lds<T>(buf, L, log2L, T1, T2, true);
+  fft_lds<T>(buf, L, log2L, T1, T2, true, fs);
   const T invL = (T)1 / (T)L;
   for (int n = tid; n < p; n += kWG) x[n] = cscale(cmul(buf[n], chirp[n]), invL);
   __syncthreads();
@@ -578,14 +604,18 @@ __device__ void stockham_pass_b(cpx<T>* buf, int L, int lgn, int G, int Ns, cons
 
 template <typename T, int MAXV>
 __device__ __forceinline__ void fft_lds_batch(cpx<T>* buf, int L, int log2L, int G,
-                                              const cpx<T>* T1, const cpx<T>* T2, bool inv) {
+                                              const cpx<T>* T1, const cpx<T>* T2, bool inv,
+                                              int fs) {
   int Ns = 1;
   const int b = log2L & 3;
-  if (b & 1) {
+  if (b == 3 && fs == kFftRadix8Head) {
+    stockham_pass_b<T, 8, MAXV>(buf, L, log2L - 3, G, Ns, T1, T2, inv);
+    Ns = 8;
+  } else if (b & 1) {
     stockham_pass_b<T, 2, MAXV>(buf, L, log2L - 1, G, Ns, T1, T2, inv);
     Ns = 2;
   }
-  if (b & 2) {
+  if ((b & 2) && Ns < 8) {
     stockham_pass_b<T, 4, MAXV>(buf, L, log2L - 2, G, Ns, T1, T2, inv);
     Ns *= 4;
   }
@@ -599,7 +629,7 @@ __device__ __forceinline__ void fft_lds_batch(cpx<T>* buf, int L, int log2L, int
 // chirp and the filter spectrum bhat as in bluestein_setup.
 template <typename T>
 __device__ __noinline__ void bluestein_setup_at(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
-                                   cpx<T>* buf, cpx<T>* tab) {
+                                   cpx<T>* buf, cpx<T>* tab, int fs) {
   const int tid = threadIdx.x;
   cpx<T>* T1 = tab;
   cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
@@ -622,7 +652,7 @@ __device__ __noinline__ void bluestein_setup_at(int p, int L, int log2L, cpx<T>*
     buf[n] = v;
   }
   __syncthreads();
-  fft_lds<T>(buf, L, log2L, T1, T2, false);
+  fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
   for (int n = tid; n < L; n += kWG) bhat[n] = buf[n];
   __syncthreads();
 }
@@ -631,7 +661,7 @@ __device__ __noinline__ void bluestein_setup_at(int p, int L, int log2L, cpx<T>*
 template <typename T, int MAXV>
 __device__ __noinline__ void bluestein_dft_batch(cpx<T>* x0, int vstride, int G, int p, int L, int log2L,
                                     const cpx<T>* chirp, const cpx<T>* bhat, cpx<T>* buf,
-                                    const cpx<T>* tab) {
+                                    const cpx<T>* tab, int fs) {
   const int tid = threadIdx.x;
   const cpx<T>* T1 = tab;
   const cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
@@ -639,10 +669,10 @@ __device__ __noinline__ void bluestein_dft_batch(cpx<T>* x0, int vstride, int G,
   (void)tid;
   bs_chirp_in<T>(buf, x0, vstride, n_all, p, L, log2L, chirp);
   __syncthreads();
-  fft_lds_batch<T, MAXV>(buf, L, log2L, G, T1, T2, false);
+  fft_lds_batch<T, MAXV>(buf, L, log2L, G, T1, T2, false, fs);
   bs_filter<T>(buf, n_all, L, bhat);
   __syncthreads();
-  fft_lds_batch<T, MAXV>(buf, L, log2L, G, T1, T2, true);
+  fft_lds_batch<T, MAXV>(buf, L, log2L, G, T1, T2, true, fs);
   bs_chirp_out<T>(x0, vstride, G, p, L, buf, chirp);
   __syncthreads();
 }

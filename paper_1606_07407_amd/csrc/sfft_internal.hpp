@@ -14,6 +14,16 @@ constexpr int kMaxRT = 8;         // MFMA row tiles: 2 (S+1) real rows <= 128
 constexpr int kChunk = 16;        // sampler: A-fragment pairs staged in LDS per chunk
 constexpr int kTwiddleBits = 6;   // DFT twiddles exp(-2 pi i t / L) = T1[t >> 6] * T2[t & 63]
 constexpr int kTwiddleEntries = 64 + 16384 / 64;  // LDS entries of T1 and T2 for L <= 16384
+// FFT radix schedules of a power-of-two length L = 2^n (n = 4 q + b): radix-2
+// (b odd) and radix-4 (b >= 2) head passes, then radix 16; or, when b = 3,
+// one radix-8 head pass in place of the radix-2 and radix-4 ones.
+constexpr int kFftRadix24Head = 1;
+constexpr int kFftRadix8Head = 2;
+// Sampler column-tile bands: rounds with p below 320, 640, 1600, and above.
+constexpr int kNtBands = 4;
+__host__ __device__ inline int nt_band(int p) {
+  return p < 320 ? 0 : p < 640 ? 1 : p < 1600 ? 2 : 3;
+}
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -91,6 +101,9 @@ struct KParams {
   int p_vmax;             // largest prime a verification round can use
   double verify_eta;
   int residual;           // 0: registry subtracted from the spectra, 1: from the samples
+  int sched_nt[kNtBands]; // sampler column tiles per wave per p band (0: built-in choice)
+  int sched_fft;          // kFftRadix24Head or kFftRadix8Head
+  int sched_dft_batch;    // FP32: most sets per batched Bluestein pass (0: all that fit)
 };
 
 struct KBatch {

@@ -273,7 +273,8 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     const float* af = reinterpret_cast<const float*>(slot + kp.lay.afrag);
     // RT * NT accumulator tiles per wave: at most 24 (96 accumulator registers)
     constexpr int NTMAX = (RT <= 3) ? 8 : (RT <= 6) ? 4 : 2;
-    const int nt = min(choose_nt(p), NTMAX);
+    const int nt_plan = kp.sched_nt[nt_band(p)];
+    const int nt = min(nt_plan > 0 ? nt_plan : choose_nt(p), NTMAX);
     const cpx<float>* twc = (const cpx<float>*)tw;
     cpx<float>* Vf = (cpx<float>*)V;
     if (nt >= 8 && NTMAX >= 8)
@@ -424,21 +425,22 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
     // FP32: the twiddle tables sit after the whole L_max buffer so that up to
     // min(L_max, 8192) / L sets are transformed together
     constexpr int MAXV = MaxL<T>::value / 2 / kWG;
-    if (st.L <= MAXV * kWG && 2 * st.L <= kp.L_max) {
+    if (kp.sched_dft_batch != 1 && st.L <= MAXV * kWG && 2 * st.L <= kp.L_max) {
       cpx<T>* tab = buf + kp.L_max;
-      bluestein_setup_at<T>(st.p, st.L, st.log2L, chirp, bhat, buf, tab);
-      const int cap = min(kp.L_max, MAXV * kWG) / st.L;
+      bluestein_setup_at<T>(st.p, st.L, st.log2L, chirp, bhat, buf, tab, kp.sched_fft);
+      int cap = min(kp.L_max, MAXV * kWG) / st.L;
+      if (kp.sched_dft_batch > 1) cap = min(cap, kp.sched_dft_batch);
       for (int s0 = 0; s0 < nsets; s0 += cap) {
         const int g = min(cap, nsets - s0);
         bluestein_dft_batch<T, MAXV>(V + (size_t)s0 * vstride, vstride, g, st.p, st.L, st.log2L,
-                                     chirp, bhat, buf, tab);
+                                     chirp, bhat, buf, tab, kp.sched_fft);
       }
       return;
     }
   }
-  bluestein_setup<T>(st.p, st.L, st.log2L, chirp, bhat, buf);
+  bluestein_setup<T>(st.p, st.L, st.log2L, chirp, bhat, buf, kp.sched_fft);
   for (int s = 0; s < nsets; ++s)
-    bluestein_dft<T>(V + (size_t)s * vstride, st.p, st.L, st.log2L, chirp, bhat, buf);
+    bluestein_dft<T>(V + (size_t)s * vstride, st.p, st.L, st.log2L, chirp, bhat, buf, kp.sched_fft);
 }
 
 // ------------------------------------------- residual in the spectrum ------
@@ -1503,9 +1505,9 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) d
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
   cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
   cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
-  bluestein_setup<T>(p, st.L, st.log2L, chirp, bhat, buf);
+  bluestein_setup<T>(p, st.L, st.log2L, chirp, bhat, buf, kp.sched_fft);
   for (int q = blockIdx.x; q < count; q += gridDim.x)
-    bluestein_dft<T>(data + (size_t)q * p, p, st.L, st.log2L, chirp, bhat, buf);
+    bluestein_dft<T>(data + (size_t)q * p, p, st.L, st.log2L, chirp, bhat, buf, kp.sched_fft);
 }
 
 __global__ void zero_queue_kernel(int* q, int64_t* count) {

@@ -2,7 +2,8 @@
 
 The names mirror the C ABI of include/sfft.h: sfft_plan_create,
 sfft_plan_destroy, sfft_recover, sfft_sample_lines, sfft_dft,
-sfft_plan_max_prime, sfft_plan_num_sets, sfft_last_error, sfft_version.
+sfft_plan_max_prime, sfft_plan_num_sets, sfft_autotune, sfft_last_error,
+sfft_version (and the classifier kernels sfft_mlp_forward / _grad / _train).
 PyTorch provides device memory and the current stream; every step of the
 recovery runs in the HIP kernels of libsfft.so.  Loading fails loudly when
 the library has not been built.
@@ -26,6 +27,7 @@ SFFT_PRIME_PAPER, SFFT_PRIME_SMOOTH = 0, 1
 SFFT_FP64, SFFT_FP32 = 0, 1
 SFFT_CLS_PLAIN, SFFT_CLS_MLP = 0, 1
 SFFT_TRACE_W = 8
+SFFT_FFT_RADIX24_HEAD, SFFT_FFT_RADIX8_HEAD = 1, 2
 SFFT_MLP_PARAMS = 4866
 SFFT_MLP_FEATURES = 8
 
@@ -46,6 +48,17 @@ class sfft_params(ctypes.Structure):
         ("verify", ctypes.c_int32),
         ("verify_eta", ctypes.c_double),
         ("residual", ctypes.c_int32),
+        ("sched_nt", ctypes.c_int32 * 4),
+        ("sched_fft", ctypes.c_int32),
+        ("sched_dft_batch", ctypes.c_int32),
+    ]
+
+
+class sfft_tune_entry(ctypes.Structure):
+    _fields_ = [
+        ("c", ctypes.c_double), ("sched_nt", ctypes.c_int32 * 4), ("sched_fft", ctypes.c_int32),
+        ("sched_dft_batch", ctypes.c_int32), ("status", ctypes.c_int32),
+        ("exact", ctypes.c_int32), ("ms", ctypes.c_double),
     ]
 
 
@@ -112,6 +125,11 @@ def lib() -> ctypes.CDLL:
         L.sfft_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_double,
                                      ctypes.c_uint64, vp, vp]
         L.sfft_mlp_train.restype = i32
+        L.sfft_autotune.argtypes = [ctypes.POINTER(sfft_params), ctypes.POINTER(sfft_signal_batch),
+                                    ctypes.POINTER(ctypes.c_double), i32, i32, i32,
+                                    ctypes.POINTER(sfft_tune_entry), i32,
+                                    ctypes.POINTER(i32), vp]
+        L.sfft_autotune.restype = i32
         _lib = L
     return _lib
 
@@ -160,13 +178,18 @@ class Params:
     verify: int = 0
     verify_eta: float = 0.0
     residual: int = 0               # SFFT_RESIDUAL_SPECTRUM
+    sched_nt: tuple = (0, 0, 0, 0)  # kernel schedules; 0 = built-in choice
+    sched_fft: int = 0
+    sched_dft_batch: int = 0
 
     def to_c(self) -> sfft_params:
         return sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
                            self.p_min, self.ladder_K, self.tau, self.tau_noise, self.eta,
                            self.max_rounds, self.precision, self.robust, self.classifier,
                            _ptr(self.mlp_weights), self.mlp_threshold, self.feature_scale,
-                           self.verify, self.verify_eta, self.residual)
+                           self.verify, self.verify_eta, self.residual,
+                           (ctypes.c_int32 * 4)(*[int(v) for v in self.sched_nt]),
+                           self.sched_fft, self.sched_dft_batch)
 
 
 class Plan:
@@ -321,6 +344,29 @@ def sfft_dft(plan: Plan, data, stream=None):
     count, p = int(data.shape[0]), int(data.shape[1])
     _check(lib().sfft_dft(plan.handle, _ptr(data), count, p, _stream(stream)), "sfft_dft")
     return data
+
+
+def sfft_autotune(params: Params, batch: DeviceBatch, c_values=(), warmup: int = 1,
+                  steps: int = 3, stream=None):
+    """Measure candidate c values and kernel schedules on `batch` (sfft_autotune of
+    the C ABI).  Returns the winning Params (a copy of `params` with c and the
+    sched_* fields replaced) and the list of measured candidates as dicts."""
+    import dataclasses
+    p = params.to_c()
+    cs = (ctypes.c_double * max(1, len(c_values)))(*[float(c) for c in c_values])
+    cap = 256
+    log = (sfft_tune_entry * cap)()
+    n = ctypes.c_int32(0)
+    b = batch.to_c()
+    _check(lib().sfft_autotune(ctypes.byref(p), ctypes.byref(b), cs, len(c_values), int(warmup),
+                               int(steps), log, cap, ctypes.byref(n), _stream(stream)),
+           "sfft_autotune")
+    best = dataclasses.replace(params, c=float(p.c), sched_nt=tuple(int(v) for v in p.sched_nt),
+                               sched_fft=int(p.sched_fft), sched_dft_batch=int(p.sched_dft_batch))
+    entries = [dict(c=e.c, sched_nt=tuple(int(v) for v in e.sched_nt), sched_fft=e.sched_fft,
+                    sched_dft_batch=e.sched_dft_batch, status=e.status, exact=e.exact, ms=e.ms)
+               for e in log[:min(n.value, cap)]]
+    return best, entries
 
 
 def sfft_mlp_forward(w, x, prob=None, stream=None):

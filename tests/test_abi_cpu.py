@@ -40,7 +40,8 @@ def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "lay.c"
     fields = {"sfft_params": [f[0] for f in sfft.sfft_params._fields_],
               "sfft_signal_batch": [f[0] for f in sfft.sfft_signal_batch._fields_],
-              "sfft_outputs": [f[0] for f in sfft.sfft_outputs._fields_]}
+              "sfft_outputs": [f[0] for f in sfft.sfft_outputs._fields_],
+              "sfft_tune_entry": [f[0] for f in sfft.sfft_tune_entry._fields_]}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sfft.h"', "int main(void){"]
     for st, fs in fields.items():
         lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
@@ -66,6 +67,9 @@ BAD = [
     (dict(ladder_K=0), -1), (dict(eta=0.0), -1), (dict(tau_noise=-1.0), -1),
     (dict(max_rounds=0), -1), (dict(max_rounds=1000), -1), (dict(precision=5), -1),
     (dict(robust=2), -1), (dict(classifier=3), -1),
+    (dict(sched_nt=(8, 0, 0, 0)), -1),               # 8 column tiles below p = 640
+    (dict(sched_nt=(0, 0, 3, 0)), -1), (dict(sched_fft=3), -1), (dict(sched_fft=-1), -1),
+    (dict(sched_dft_batch=65), -1), (dict(sched_dft_batch=-1), -1),
     (dict(d=200, d1=1), -2),                         # d2 beyond 64
     (dict(d=6, d1=6, N=1024), -2),                   # N^d1 = 2^60 > 2^40
     (dict(k_max=20000, c=5.0), -2),                  # primes beyond the DFT size
@@ -98,6 +102,18 @@ def test_null_arguments():
     assert L.sfft_dft(None, None, 1, 7, None) == sfft.SFFT_EINVAL
     assert L.sfft_plan_destroy(None) == sfft.SFFT_OK
     assert L.sfft_plan_max_prime(None) == 0
+    n = ctypes.c_int32(7)
+    assert L.sfft_autotune(None, None, None, 0, 1, 3, None, 0, ctypes.byref(n), None) == \
+        sfft.SFFT_EINVAL
+    b = sfft.sfft_signal_batch()
+    for args in [(None, 1, 1, 3), (None, 0, -1, 3), (None, 0, 1, 0)]:
+        c_values, n_c, warmup, steps = args
+        assert L.sfft_autotune(ctypes.byref(p), ctypes.byref(b), c_values, n_c, warmup, steps,
+                               None, 0, ctypes.byref(n), None) == sfft.SFFT_EINVAL
+    # a batch with NULL arrays is refused before any device call
+    assert L.sfft_autotune(ctypes.byref(p), ctypes.byref(b), None, 0, 1, 3, None, 0,
+                           ctypes.byref(n), None) == sfft.SFFT_EINVAL
+    assert "autotune" in sfft.sfft_last_error()
 
 
 def test_product_path_does_not_import_oracle():

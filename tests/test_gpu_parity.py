@@ -136,20 +136,23 @@ def test_sampler_matches_oracle(name, cname, over, k, p, m, nres, B):
 
 # ---------------------------------------------------------------- DFT -------
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_dft_matches_numpy(prec):
+@pytest.mark.parametrize("prec,fsched", [("fp32", 1), ("fp64", 1), ("fp32", 2), ("fp64", 2)])
+def test_dft_matches_numpy(prec, fsched):
     import torch
     sfft = _sfft()
     # largest plans of each precision: Bluestein lengths up to 16384 (FP32) / 8192 (FP64),
-    # both register variants of the in-LDS FFT
+    # both register variants of the in-LDS FFT; both radix schedules (the radix-8 head
+    # pass differs where log2 L = 3 mod 4: L = 8, 128, 2048 below)
     params = sfft.Params(d=2, N=64, k_max=1600 if prec == "fp32" else 800, c=5.0,
-                         precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64)
+                         precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64,
+                         sched_fft=fsched)
     plan = sfft.sfft_plan_create(params, max_batch=4)
     pmax = plan.max_prime
     assert pmax > (4096 if prec == "fp32" else 2048)
     rng = np.random.default_rng(11)
-    for p in sorted(q for q in {2, 3, 5, 13, 41, 127, 1283, 2053, 4093, 4099, pmax} if q <= pmax):
-        _say(f"[dft] {prec} p={p}")
+    ps = {2, 3, 5, 13, 41, 127, 907, 1283, 2053, 4093, 4099, pmax}
+    for p in sorted(q for q in ps if q <= pmax):
+        _say(f"[dft] {prec} schedule {fsched} p={p}")
         x = rng.normal(size=(5, p)) + 1j * rng.normal(size=(5, p))
         dt = torch.complex64 if prec == "fp32" else torch.complex128
         t = torch.as_tensor(x, dtype=dt, device="cuda").contiguous()
@@ -209,20 +212,31 @@ RECOVER_CASES = [
     ("c1_fp64_residual_samples", "c1", {"residual": 1}, 8, 8, 1e-9),
     ("c2_fp32_residual_samples", "c2", {"residual": 1}, 2, 256, 1e-5),
     ("c3_fp32_residual_samples", "c3b", {"residual": 1}, 5, (20, 260), 1e-5),
+    # kernel schedules other than the built-in ones (what the autotuner may pick)
+    ("c1_fp64_sched_radix8", "c1", {"sched": dict(sched_fft=2)}, 8, 8, 1e-9),
+    ("c2_fp32_sched_radix8_unbatched", "c2", {"sched": dict(sched_fft=2, sched_dft_batch=1)},
+     2, 256, 1e-5),
+    ("c3_fp32_sched_radix8_batch2_nt2", "c3b",
+     {"sched": dict(sched_fft=2, sched_dft_batch=2, sched_nt=(2, 2, 2, 2))}, 5, (20, 260), 1e-5),
+    ("c3_fp32_sched_nt4_nt8_batch8", "c3b",
+     {"sched": dict(sched_nt=(4, 4, 8, 8), sched_dft_batch=8)}, 3, 150, 1e-5),
 ]
 
 
 @pytest.mark.parametrize("name,cname,over,B,k,tol", RECOVER_CASES)
 def test_recover_matches_oracle(name, cname, over, B, k, tol):
+    import dataclasses
     import torch
     sfft = _sfft()
+    over = dict(over)
+    sched = over.pop("sched", {})
     cfg = workloads.config(cname, **over)
     ks = workloads.planted.uneven_k(cfg["seed"], B, *k) if isinstance(k, tuple) else k
     _say(f"[recover] {name} B={B} k={k}")
     pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], ks, cfg["mag"],
                                  cfg["sigma"])
     k_max = int(np.max(pb.k))
-    plan = sfft.sfft_plan_create(_params(cfg, k_max), max_batch=B)
+    plan = sfft.sfft_plan_create(dataclasses.replace(_params(cfg, k_max), **sched), max_batch=B)
     out = sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb))
     torch.cuda.synchronize()
     h = sfft.outputs_to_host(out)
@@ -248,18 +262,28 @@ def test_recover_deterministic_and_reusable():
 
 
 def test_full_size_headline_batch():
-    """The bench's launch: 512 signals, d = 10, N = 65536, k = 1000, sigma = 1e-3.
-    Every signal's support equals its planted set (a property at any size);
-    sampled signals are checked against the oracle in full."""
+    """The bench's launch: 512 signals, d = 10, N = 65536, k = 1000, sigma = 1e-3, with
+    c and the kernel schedules picked by the autotuner as the bench picks them.  Every
+    candidate the tuner measured recovers every signal's planted support (a property at
+    any size); the tuned launch is checked in full and on sampled signals against the
+    oracle."""
+    import dataclasses
     import torch
+    import bench
     sfft = _sfft()
-    cfg = workloads.config("c3b")
-    B = cfg["B"]
-    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], cfg["k"], cfg["mag"],
-                                 cfg["sigma"])
-    _say(f"[full] c3b B={B} k={cfg['k']}")
-    plan = sfft.sfft_plan_create(_params(cfg, cfg["k"]), max_batch=B)
-    out = sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb))
+    cfg0 = workloads.config("c3b")
+    B = cfg0["B"]
+    pb = workloads.planted_batch(cfg0["seed"], B, cfg0["d"], cfg0["N"], cfg0["k"], cfg0["mag"],
+                                 cfg0["sigma"])
+    db = sfft.DeviceBatch.from_planted(pb)
+    tuned, log = bench.autotune(sfft, _params(cfg0, cfg0["k"]), db)
+    _say(f"[full] c3b B={B} k={cfg0['k']}: {len(log)} tuned candidates, c = {tuned.c}, "
+         f"nt {tuned.sched_nt} fft {tuned.sched_fft} batch {tuned.sched_dft_batch}")
+    for e in log:
+        assert e["status"] != 0 or e["exact"] == B, e
+    cfg = workloads.config("c3b", c=tuned.c)
+    plan = sfft.sfft_plan_create(tuned, max_batch=B)
+    out = sfft.sfft_recover(plan, db)
     torch.cuda.synchronize()
     h = sfft.outputs_to_host(out)
     for b in range(B):
@@ -275,13 +299,45 @@ def test_full_size_headline_batch():
     _say(f"    all {B} exact; sampled oracle parity max rel {rel:.2e}")
     plan.close()
     # the same launch with the residual subtracted from the samples
-    cfg1 = workloads.config("c3b", residual=1)
-    plan = sfft.sfft_plan_create(_params(cfg1, cfg["k"]), max_batch=B)
+    cfg1 = workloads.config("c3b", residual=1, c=tuned.c)
+    plan = sfft.sfft_plan_create(dataclasses.replace(tuned, residual=1), max_batch=B)
     h1 = sfft.outputs_to_host(sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb)))
     torch.cuda.synchronize()
     assert np.array_equal(h1["freqs"], h["freqs"]) and np.array_equal(h1["status"], h["status"])
     rel1 = _compare(cfg1, pb, h1, 1e-5, signals=(257,))
     _say(f"    residual from the samples: same supports; oracle parity max rel {rel1:.2e}")
+    plan.close()
+
+
+def test_autotune_log_and_winner():
+    """sfft_autotune: every c value is measured, the winner is a logged candidate with
+    the most exact recoveries, and a refused candidate (a c whose first prime needs
+    more than the in-LDS DFT) is logged and skipped."""
+    sfft = _sfft()
+    cfg = workloads.config("c3a")
+    B = 32
+    ks = workloads.planted.uneven_k(cfg["seed"], B, 64, 300)
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], ks, cfg["mag"],
+                                 cfg["sigma"])
+    db = sfft.DeviceBatch.from_planted(pb)
+    base = _params(cfg, int(pb.k.max()))
+    tuned, log = sfft.sfft_autotune(base, db, c_values=(2.5, 3.0, 40.0), warmup=1, steps=2)
+    _say(f"[autotune] {len(log)} candidates; winner c={tuned.c} nt={tuned.sched_nt} "
+         f"fft={tuned.sched_fft} batch={tuned.sched_dft_batch}")
+    assert [e["c"] for e in log[:3]] == [2.5, 3.0, 40.0]
+    assert log[2]["status"] == sfft.SFFT_ERANGE       # 40 * 300 > the largest prime
+    assert len(log) >= 3 + 1 + 4 + 2 + 2 + 3 + 3
+    ok = [e for e in log if e["status"] == 0]
+    best_exact = max(e["exact"] for e in ok)
+    assert best_exact == B
+    win = [e for e in ok if e["c"] == tuned.c and e["sched_nt"] == tuned.sched_nt
+           and e["sched_fft"] == tuned.sched_fft and e["sched_dft_batch"] == tuned.sched_dft_batch]
+    assert win and win[0]["exact"] == best_exact
+    # the tuned plan against the oracle on two signals
+    plan = sfft.sfft_plan_create(tuned, max_batch=B)
+    h = sfft.outputs_to_host(sfft.sfft_recover(plan, db))
+    rel = _compare(workloads.config("c3a", c=tuned.c), pb, h, 1e-5, signals=(0, B - 1))
+    _say(f"    tuned plan: oracle parity max rel {rel:.2e}")
     plan.close()
 
 
