@@ -28,7 +28,7 @@ import workloads  # noqa: E402
 METRIC = "signal recoveries/sec at exact support, d=10 k=1000; learned vs plain"
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X FP32 vector
-TUNE_C_OFFSETS = (-1.0, -0.5, 0.0, 0.5)  # c values the autotuner measures around the recipe's c
+TUNE_C_OFFSETS = (-1.5, -1.0, -0.5, 0.0, 0.5)  # c values the autotuner measures around the recipe's c
 TUNE_WARMUP, TUNE_STEPS = 1, 5
 
 
@@ -130,7 +130,8 @@ def sources_sha256() -> str:
 def plan_key(params) -> str:
     """The launch configuration a profile was taken with: c and the kernel schedules."""
     nt = "-".join(str(int(v)) for v in params.sched_nt)
-    return f"c:{params.c:g},nt:{nt},fft:{params.sched_fft},batch:{params.sched_dft_batch}"
+    fft = params.sched_fft or 1   # 0 is the built-in schedule 1
+    return f"c:{params.c:g},nt:{nt},fft:{fft},batch:{params.sched_dft_batch}"
 
 
 def profiled_traffic(workload: str, params):
@@ -152,7 +153,7 @@ def profiled_traffic(workload: str, params):
 
 def autotune(sfft, params, db, c_values=None):
     """c and the kernel schedules picked by the library's autotuner on the batch itself
-    (c_values: default the recipe's c - 1, c - 0.5, c and c + 0.5)."""
+    (c_values: default the recipe's c - 1.5 ... c + 0.5 in steps of 0.5, those above 1)."""
     if c_values is None:
         c_values = [round(params.c + dc, 4) for dc in TUNE_C_OFFSETS if params.c + dc > 1.0]
     return sfft.sfft_autotune(params, db, c_values=c_values, warmup=TUNE_WARMUP,
