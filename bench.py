@@ -207,6 +207,41 @@ def main_part_share(sfft, plan, db, B) -> float:
     return 1.0 - samp / busy if busy > 0 else float("nan")
 
 
+def paper_sweep(sfft, steps: int, warmup: int) -> list:
+    """The paper's experiment (Section 5) at d = 100: d1 = 5, N = 20, c = 5,
+    unit-magnitude random-phase coefficients, noiseless, FP64 end to end; one batch of
+    100 trials (signals) per k = 2^0 .. 2^9.  Per k: exact-support rate, largest
+    coefficient error against the planted values, rounds, samples (and samples / (d k),
+    which the paper's analysis keeps bounded), launch time and its main part."""
+    cfg = workloads.config("e1")
+    B = cfg["B"]
+    rows = []
+    for j in range(10):
+        k = 2 ** j
+        pb = workloads.planted_batch(cfg["seed"] + j, B, cfg["d"], cfg["N"], k, cfg["mag"], 0.0)
+        db = sfft.DeviceBatch.from_planted(pb)
+        prm = sfft.Params(d=cfg["d"], N=cfg["N"], k_max=k, d1=cfg["d1"], c=cfg["c"],
+                          tau=cfg["tau"], eta=cfg["eta"], precision=sfft.SFFT_FP64)
+        plan = sfft.sfft_plan_create(prm, max_batch=B)
+        out, step_s, gpu_ms, per = time_recover(sfft, plan, db, B, steps, warmup)
+        h = sfft.outputs_to_host(out)
+        ok = exact_support(pb, h)
+        err = 0.0
+        for b in np.nonzero(ok)[0]:
+            w, a = pb.signal(int(b))
+            o = np.lexsort(w.T[::-1])
+            err = max(err, float(np.abs(h["coeffs"][b, :k] - a[o]).max()))
+        share = main_part_share(sfft, plan, db, B)
+        samples = float(np.mean(h["samples"]))
+        rows.append(dict(k=k, trials=B, success_rate=float(ok.mean()), max_coeff_err=err,
+                         mean_rounds=float(np.mean(h["rounds"])), mean_samples=samples,
+                         samples_per_dk=samples / (cfg["d"] * k), batch_ms=gpu_ms,
+                         ms_per_signal=gpu_ms / B, main_part_ms=gpu_ms * share,
+                         prime_round1=int(h["trace"][0, 0, 2])))
+        plan.close()
+    return rows
+
+
 def tolerance_curve(sfft, base, extra, kind, db, pb, B):
     """Success rate and recoveries/s over the decision threshold: tau for the plain
     ratio test, the probability threshold for the learned classifier."""
@@ -297,6 +332,8 @@ def main():
                     help="host processes for the oracle baseline (0: all cores, at most 16)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain copy of this size (traffic-counter calibration)")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="instead of the headline: the paper's d = 100 sweep over k (FP64)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (use --c / --sched or the recipe's values)")
     ap.add_argument("--c", type=float, default=None, help="c instead of the recipe's")
@@ -312,6 +349,17 @@ def main():
     import torch
     from paper_1606_07407_amd import classifier as cls
     from paper_1606_07407_amd import sfft
+
+    if args.paper_sweep:
+        torch.cuda.set_device(0)
+        rows = paper_sweep(sfft, args.steps, args.warmup)
+        print(json.dumps({
+            "metric": "paper sweep: exact-support rate and time per recovery over k",
+            "config": {"workload": "e1: d=100 d1=5 N=20 c=5 |a|=1 noiseless, 100 trials per k",
+                       "precision": "fp64"},
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "data": "synthetic planted spectra (seeded)", "rows": rows}), flush=True)
+        return
 
     cfg = workloads.config(args.config)
     B = args.batch or cfg["B"]

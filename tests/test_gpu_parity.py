@@ -202,6 +202,10 @@ RECOVER_CASES = [
     ("c1_fp64_d1", "c1", {}, 16, 8, 1e-9),
     ("c1_fp64_d2", "c1", {"d1": 2}, 8, 8, 1e-9),
     ("e4_fp64", "e4", {}, 2, 100, 1e-8),
+    # the paper's experiment at d = 100 (d1 = 5, N = 20); 1e-8: the oracle's own FP64
+    # evaluation of exp(2 pi i w . t) at arguments of up to 1.6e6 cycles
+    ("e1_fp64_d100", "e1", {}, 4, 16, 1e-8),
+    ("e1_fp64_d100_k128", "e1", {}, 2, 128, 1e-8),
     ("c2_fp32", "c2", {}, 2, 256, 1e-5),
     ("c2_fp32_single_mode", "c2", {}, 3, 1, 1e-5),
     ("c3_fp32_noisy_small", "c3b", {}, 3, 150, 1e-5),

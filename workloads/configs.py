@@ -13,6 +13,9 @@ measured single-GPU configurations:
   c4      d=6,  N=4096,  k=2000, |a|~U[1,2], sigma~U[0,1e-2]  (classifier data)
   c5      d=20, N=65536, k=4096, |a|~U[1,4], sigma=1e-2, B=64  (p ~ 2k)
   e4      d=20, N=20, d1=4, k=100 (the worked example of Section 4.1)
+  e1      d=100, N=20, d1=5, k in 2^0..2^9, |a|=1, noiseless, FP64, 100 trials
+          (the paper's experiment at d = 100; k = 2^10 needs p > 4096, beyond
+          the FP64 in-LDS DFT)
 """
 from __future__ import annotations
 
@@ -45,6 +48,9 @@ CONFIGS = {
                verify_eta=1e-2),
     "e4": dict(d=20, N=20, k=100, B=1, mag=(1.0, 1.0), sigma=0.0, seed=6000,
                d1=4, c=5.0, ladder_K=1, tau=1e-6, eta=1e-8, precision="fp64",
+               p_min=0, robust=False),
+    "e1": dict(d=100, N=20, k=64, B=100, mag=(1.0, 1.0), sigma=0.0, seed=6100,
+               d1=5, c=5.0, ladder_K=1, tau=1e-6, eta=1e-8, precision="fp64",
                p_min=0, robust=False),
 }
 
