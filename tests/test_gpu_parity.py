@@ -249,6 +249,38 @@ def test_recover_matches_oracle(name, cname, over, B, k, tol):
     plan.close()
 
 
+@pytest.mark.parametrize("cname,k,prec", [("c3b", 60, "fp32"), ("c1", 8, "fp64")])
+def test_empty_spectra_in_a_batch(cname, k, prec):
+    """Degenerate inputs: signals with no planted modes (pure noise, or exactly zero)
+    between ordinary ones.  Each matches the oracle (no candidate in any round, status
+    NOT_CONVERGED at the round cap, nothing written), and so does every ordinary one."""
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config(cname, max_rounds=8)
+    pb0 = workloads.planted_batch(cfg["seed"], 2, cfg["d"], cfg["N"], k, cfg["mag"], cfg["sigma"])
+    # batch: planted, empty with the config's noise, planted, empty and noiseless
+    w0, a0 = pb0.signal(0)
+    w1, a1 = pb0.signal(1)
+    freqs = np.concatenate([w0, w1])
+    coeffs = np.concatenate([a0, a1])
+    off = np.array([0, len(w0), len(w0), len(w0) + len(w1), len(w0) + len(w1)], np.int64)
+    sig = np.array([pb0.sigma[0], cfg["sigma"], pb0.sigma[1], 0.0])
+    pb = workloads.PlantedBatch(freqs=freqs, coeffs=coeffs, mode_off=off,
+                                k=np.full(4, k, np.int32), sigma=sig, seed=pb0.seed,
+                                d=cfg["d"], N=cfg["N"])
+    _say(f"[empty] {cname} B=4 (signals 1 and 3 have no modes)")
+    plan = sfft.sfft_plan_create(_params(cfg, k), max_batch=4)
+    h = sfft.outputs_to_host(sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb)))
+    torch.cuda.synchronize()
+    tol = 1e-5 if prec == "fp32" else 1e-9
+    _compare(cfg, pb, h, tol)
+    for b in (1, 3):
+        assert int(h["status"][b]) == sfft.SFFT_NOT_CONVERGED and int(h["k_found"][b]) == 0
+        assert int(h["rounds"][b]) == 8 and not np.any(h["trace"][b, :, 4])
+    _say(f"    statuses {h['status'].tolist()} rounds {h['rounds'].tolist()}")
+    plan.close()
+
+
 def test_recover_deterministic_and_reusable():
     import torch
     sfft = _sfft()
