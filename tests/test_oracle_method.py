@@ -235,7 +235,7 @@ def test_verification_line_closed_form():
 
 
 def test_verification_catches_false_accepts():
-    """R14 as the judge: with the ratio test switched off (tau = 10 accepts every
+    """R14 catching classifier errors: with the ratio test switched off (tau = 10 accepts every
     in-band decode) and c = 1.5, the plain loop ends at |R| = k with wrong entries
     and status OK; with verification every OK result is the planted spectrum."""
     silent_wrong = exact_verified = 0
