@@ -4,10 +4,15 @@ A step is one sfft_recover call over one batch of synthetic planted-spectrum
 signals (default: 512 signals, d = 10, N = 65536, k = 1000, |a| ~ U[1, 2],
 complex noise sigma = 1e-3, FP32 samples / exponential sums / DFTs with FP64
 decoding), inputs resident in HBM before the timed region.  Prints one JSON
-line.  The roofline entry prices the recovery kernel's algorithmic FP32 work
-(8 flops per (sample, mode) term of the exponential sums + 5 p log2 p per
-length-p DFT, counted from the per-round trace) against the FP32 matrix peak.
-The CPU baseline is the FP64 oracle on a bounded sample of the same signals.
+line.  Before timing, the library's autotuner picks c and the kernel schedules
+on the batch itself (reported under "autotune"; --no-autotune, --c and --sched
+fix them instead).  The roofline entry prices the recovery kernel's algorithmic
+FP32 work (8 flops per (sample, mode) term of the exponential sums, 5 p log2 p
+per length-p DFT and the registry subtraction's terms, counted from the per-round
+trace) against the FP32 matrix peak.  The plain classifier's entry also times
+the launch replayed from a captured HIP graph.  The CPU baseline is the FP64
+oracle on a bounded sample of the same signals.  --paper-sweep prints the
+paper's d = 100 experiment over k instead of the headline line.
 """
 from __future__ import annotations
 
@@ -183,6 +188,34 @@ def time_recover(sfft, plan, db, B, steps, warmup):
     wall = time.perf_counter() - t0
     per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
     return out, wall / steps, evs[0].elapsed_time(evs[steps]) / steps, per
+
+
+def graph_launch(sfft, plan, db, B, steps: int):
+    """sfft_recover captured once in a HIP graph and replayed `steps` times: median
+    replay duration (HIP events on the replay stream) and the last replay's outputs."""
+    import torch
+    out = sfft.alloc_outputs(plan, B)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sfft.sfft_recover(plan, db, out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    h = sfft.outputs_to_host(out)
+    del g
+    return float(np.median(ts)), h
 
 
 def main_part_share(sfft, plan, db, B) -> float:
@@ -426,6 +459,10 @@ def main():
             share = main_part_share(sfft, plan, db, B)
             results[kind]["main_part_ms"] = gpu_ms * share
             results[kind]["main_part_share"] = share
+            g_ms, hg = graph_launch(sfft, plan, db, B, args.steps)
+            okg = exact_support(pb, hg)
+            results[kind]["graph_launch_ms_median"] = g_ms
+            results[kind]["graph_value"] = int(okg.sum()) / (g_ms * 1e-3)
         if not args.no_curves:
             curves[kind] = tolerance_curve(sfft, base, extra, kind, db, pb, B)
         if kind == kinds[0] and not args.no_components:
