@@ -73,6 +73,9 @@ SAMPLER_CASES = [
     ("e4_fp64_residual_rows", "e4", {"residual": 1}, 100, 503, 3, 20, 2),
     # the large workload's first round: k = 4096, 41 sets, p = 8161, 6 row tiles
     ("c5_fp32_full_p", "c5", {}, 4096, 8161, 7, 64, 1),
+    # partial unwrapping: blocks of 2 in FP32 (N^d1 = 2^20), blocks of 5 at d = 100 in FP64
+    ("c2_fp32_d1_2", "c2", {"d1": 2}, 128, 641, 1, 20, 2),
+    ("e1_fp64_d100", "e1", {}, 64, 331, 7, 16, 2),
 ]
 
 

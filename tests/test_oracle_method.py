@@ -185,7 +185,7 @@ def test_pins_hold_unmutated():
 
 
 @pytest.mark.parametrize("mutation", ["dft_sign", "unwrap_power", "no_residual",
-                                      "shift_axis", "coef_scale", "arg_sign"])
+                                      "shift_axis", "coef_scale", "arg_sign", "round_floor"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
     if mutation == "dft_sign":
         monkeypatch.setattr(mps_mod, "dft", lambda v: np.fft.ifft(v) * v.shape[-1])
@@ -202,6 +202,9 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         monkeypatch.setattr(mps_mod, "_coefficient", lambda F0h, p: complex(F0h) / (p - 1))
     elif mutation == "arg_sign":
         monkeypatch.setattr(mps_mod, "_arg", lambda z: -math.atan2(z.imag, z.real))
+    elif mutation == "round_floor":
+        # R11 misread: truncation towards -inf instead of rounding to nearest
+        monkeypatch.setattr(mps_mod, "_round_half_away", lambda x: math.floor(x))
     assert not _pins_hold()
 
 
