@@ -12,7 +12,7 @@ per length-p DFT and the registry subtraction's terms, counted from the per-roun
 trace) against the FP32 matrix peak.  The plain classifier's entry also times
 the launch replayed from a captured HIP graph.  The CPU baseline is the FP64
 oracle on a bounded sample of the same signals.  --paper-sweep prints the
-paper's d = 100 experiment over k instead of the headline line.
+paper's experiment over k (d = 100 and d = 1000) instead of the headline line.
 """
 from __future__ import annotations
 
@@ -240,13 +240,14 @@ def main_part_share(sfft, plan, db, B) -> float:
     return 1.0 - samp / busy if busy > 0 else float("nan")
 
 
-def paper_sweep(sfft, steps: int, warmup: int) -> list:
-    """The paper's experiment (Section 5) at d = 100: d1 = 5, N = 20, c = 5,
-    unit-magnitude random-phase coefficients, noiseless, FP64 end to end; one batch of
-    100 trials (signals) per k = 2^0 .. 2^9.  Per k: exact-support rate, largest
-    coefficient error against the planted values, rounds, samples (and samples / (d k),
-    which the paper's analysis keeps bounded), launch time and its main part."""
-    cfg = workloads.config("e1")
+def paper_sweep(sfft, steps: int, warmup: int, name: str = "e1") -> list:
+    """The paper's experiment (Section 5) at d = 100 ("e1") or d = 1000 ("e2"): d1 = 5,
+    N = 20, c = 5, unit-magnitude random-phase coefficients, noiseless, FP64 end to end;
+    one batch of 100 trials (signals) per k = 2^0 .. 2^9.  Per k: exact-support rate,
+    largest coefficient error against the planted values, rounds, samples (and
+    samples / (d k), which the paper's analysis keeps bounded), launch time and its
+    main part."""
+    cfg = workloads.config(name)
     B = cfg["B"]
     rows = []
     for j in range(10):
@@ -266,12 +267,15 @@ def paper_sweep(sfft, steps: int, warmup: int) -> list:
             err = max(err, float(np.abs(h["coeffs"][b, :k] - a[o]).max()))
         share = main_part_share(sfft, plan, db, B)
         samples = float(np.mean(h["samples"]))
-        rows.append(dict(k=k, trials=B, success_rate=float(ok.mean()), max_coeff_err=err,
+        rows.append(dict(d=cfg["d"], k=k, trials=B, success_rate=float(ok.mean()),
+                         max_coeff_err=err,
                          mean_rounds=float(np.mean(h["rounds"])), mean_samples=samples,
                          samples_per_dk=samples / (cfg["d"] * k), batch_ms=gpu_ms,
                          ms_per_signal=gpu_ms / B, main_part_ms=gpu_ms * share,
                          prime_round1=int(h["trace"][0, 0, 2])))
         plan.close()
+        print(f"[paper sweep] d={cfg['d']} k={k}: success {ok.mean():.2f}, "
+              f"{gpu_ms:.3f} ms per launch", file=sys.stderr, flush=True)
     return rows
 
 
@@ -366,7 +370,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain copy of this size (traffic-counter calibration)")
     ap.add_argument("--paper-sweep", action="store_true",
-                    help="instead of the headline: the paper's d = 100 sweep over k (FP64)")
+                    help="instead of the headline: the paper's d = 100 and 1000 sweeps "
+                         "over k (FP64)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (use --c / --sched or the recipe's values)")
     ap.add_argument("--c", type=float, default=None, help="c instead of the recipe's")
@@ -385,11 +390,12 @@ def main():
 
     if args.paper_sweep:
         torch.cuda.set_device(0)
-        rows = paper_sweep(sfft, args.steps, args.warmup)
+        rows = (paper_sweep(sfft, args.steps, args.warmup, "e1")
+                + paper_sweep(sfft, args.steps, args.warmup, "e2"))
         print(json.dumps({
             "metric": "paper sweep: exact-support rate and time per recovery over k",
-            "config": {"workload": "e1: d=100 d1=5 N=20 c=5 |a|=1 noiseless, 100 trials per k",
-                       "precision": "fp64"},
+            "config": {"workload": "e1/e2: d=100 and d=1000, d1=5 N=20 c=5 |a|=1 noiseless, "
+                                   "100 trials per k", "precision": "fp64"},
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "data": "synthetic planted spectra (seeded)", "rows": rows}), flush=True)
         return

@@ -70,7 +70,8 @@ enum { SFFT_RESIDUAL_SPECTRUM = 0, SFFT_RESIDUAL_SAMPLES = 1 };
  * listing, plus the readings the paper leaves open). */
 typedef struct {
   int32_t d;          /* dimension, >= 1                                            */
-  int32_t d1;         /* unwrapping block size; d % d1 == 0; d2 = d / d1            */
+  int32_t d1;         /* unwrapping block size; d % d1 == 0; d2 = d / d1 <= 256;
+                         FP32 also needs 2 (S+1) <= 128 (else SFFT_ERANGE)          */
   int64_t N;          /* per-dimension bandwidth, even, >= 2; N^d1 <= 2^40          */
   int32_t k_max;      /* largest sparsity of any signal recovered with this plan    */
   double c;           /* p_i = i-th prime >= max(ceil(c k*), p_min); c > 1          */

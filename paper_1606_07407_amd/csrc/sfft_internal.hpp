@@ -8,8 +8,7 @@
 namespace sfft {
 
 constexpr int kWG = 256;          // threads per work-group (4 waves of 64)
-constexpr int kMaxD2 = 64;        // largest number of unwrapped coordinates
-constexpr int kMaxSets = 2 * kMaxD2 + 1;
+constexpr int kMaxD2 = 256;       // largest number of unwrapped coordinates (FP32: also 2 (S+1) <= 128)
 constexpr int kMaxRT = 8;         // MFMA row tiles: 2 (S+1) real rows <= 128
 constexpr int kChunk = 16;        // sampler: A-fragment pairs staged in LDS per chunk
 constexpr int kTwiddleBits = 6;   // DFT twiddles exp(-2 pi i t / L) = T1[t >> 6] * T2[t & 63]

@@ -70,7 +70,8 @@ BAD = [
     (dict(sched_nt=(8, 0, 0, 0)), -1),               # 8 column tiles below p = 640
     (dict(sched_nt=(0, 0, 3, 0)), -1), (dict(sched_fft=3), -1), (dict(sched_fft=-1), -1),
     (dict(sched_dft_batch=65), -1), (dict(sched_dft_batch=-1), -1),
-    (dict(d=200, d1=1), -2),                         # d2 beyond 64
+    (dict(d=300, d1=1, precision=0), -2),            # d2 beyond 256
+    (dict(d=100, d1=1), -2),                         # FP32: 2 (S+1) = 202 real rows > 128
     (dict(d=6, d1=6, N=1024), -2),                   # N^d1 = 2^60 > 2^40
     (dict(k_max=20000, c=5.0), -2),                  # primes beyond the DFT size
     (dict(k_max=1700, c=5.0), -2),                   # first round needs p >= 8500 > 8192

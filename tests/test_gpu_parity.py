@@ -76,6 +76,8 @@ SAMPLER_CASES = [
     # partial unwrapping: blocks of 2 in FP32 (N^d1 = 2^20), blocks of 5 at d = 100 in FP64
     ("c2_fp32_d1_2", "c2", {"d1": 2}, 128, 641, 1, 20, 2),
     ("e1_fp64_d100", "e1", {}, 64, 331, 7, 16, 2),
+    # d = 1000: 200 unwrapped coordinates, 201 sets, sampled on the last axis
+    ("e2_fp64_d1000", "e2", {}, 32, 163, 200, 8, 2),
 ]
 
 
@@ -209,6 +211,9 @@ RECOVER_CASES = [
     # evaluation of exp(2 pi i w . t) at arguments of up to 1.6e6 cycles
     ("e1_fp64_d100", "e1", {}, 4, 16, 1e-8),
     ("e1_fp64_d100_k128", "e1", {}, 2, 128, 1e-8),
+    # and at d = 1000 (200 unwrapped coordinates, 201 sets per round)
+    ("e2_fp64_d1000", "e2", {}, 2, 16, 1e-8),
+    ("e2_fp64_d1000_k64", "e2", {}, 2, 64, 1e-8),
     ("c2_fp32", "c2", {}, 2, 256, 1e-5),
     ("c2_fp32_single_mode", "c2", {}, 3, 1, 1e-5),
     ("c3_fp32_noisy_small", "c3b", {}, 3, 150, 1e-5),

@@ -43,7 +43,7 @@ def _closed_form(y_pl, a_pl, y_R, a_R, P, p, m, tab):
 
 @pytest.mark.parametrize("name,over", [("c1", {}), ("c1", {"d1": 2}), ("c2", {}),
                                        ("e4", {}), ("c3b", {"k": 60, "sigma": 0.0}),
-                                       ("e1", {"k": 24})])
+                                       ("e1", {"k": 24}), ("e2", {"k": 12})])
 def test_round_spectra_match_eq41(name, over):
     w, a, P, _ = _run(name, **over)
     r = oracle.multiphaseshift(w, a, P, keep_spectra=True)
@@ -95,12 +95,13 @@ def test_bruteforce_full_grid(d, N, d1, k, seed):
     assert np.abs(r.coeffs - fa).max() < 1e-9
 
 
-# coefficient tolerance: 1e-9, and 1e-8 for the d = 100 recipe, where the oracle
+# coefficient tolerance: 1e-9, and 1e-8 for the d = 100 and 1000 recipes, where the oracle
 # evaluates exp(2 pi i w . t) at arguments of up to N^d1 / 2 = 1.6e6 cycles in FP64
 # (a phase error of about 1e-9 rad per term)
 @pytest.mark.parametrize("name,over,trials,tol", [("c1", {}, 40, 1e-9), ("c1", {"d1": 2}, 20, 1e-9),
                                                   ("c2", {}, 3, 1e-9), ("e4", {}, 3, 1e-9),
-                                                  ("e1", {"k": 32}, 3, 1e-8)])
+                                                  ("e1", {"k": 32}, 3, 1e-8),
+                                                  ("e2", {"k": 16}, 2, 1e-8)])
 def test_exact_recovery_noiseless(name, over, trials, tol):
     cfg = workloads.config(name, **over)
     for t in range(trials):

@@ -16,6 +16,7 @@ measured single-GPU configurations:
   e1      d=100, N=20, d1=5, k in 2^0..2^9, |a|=1, noiseless, FP64, 100 trials
           (the paper's experiment at d = 100; k = 2^10 needs p > 4096, beyond
           the FP64 in-LDS DFT)
+  e2      as e1 at d=1000 (d2 = 200 unwrapped coordinates, 201 sets per round)
 """
 from __future__ import annotations
 
@@ -50,6 +51,9 @@ CONFIGS = {
                d1=4, c=5.0, ladder_K=1, tau=1e-6, eta=1e-8, precision="fp64",
                p_min=0, robust=False),
     "e1": dict(d=100, N=20, k=64, B=100, mag=(1.0, 1.0), sigma=0.0, seed=6100,
+               d1=5, c=5.0, ladder_K=1, tau=1e-6, eta=1e-8, precision="fp64",
+               p_min=0, robust=False),
+    "e2": dict(d=1000, N=20, k=64, B=100, mag=(1.0, 1.0), sigma=0.0, seed=6200,
                d1=5, c=5.0, ladder_K=1, tau=1e-6, eta=1e-8, precision="fp64",
                p_min=0, robust=False),
 }
