@@ -22,7 +22,7 @@ learned classifier (classifier.py) is pinned by finite differences, a
 hand-computed network and the feature definitions.
 """
 from .primes import is_prime, ith_prime_at_least, primes_upto
-from .unwrapping import unwrap_matrix, unwrap, wrap, y_range
+from .unwrapping import partition, unwrap_matrix, unwrap, wrap, y_range
 from .philox import philox4x64_10, sample_noise
 from .signal import evaluate, sample_points
 from .transforms import dft_direct, dft
@@ -31,7 +31,7 @@ from .method import Params, Result, multiphaseshift, round_samples, shift_table,
 
 __all__ = [
     "is_prime", "ith_prime_at_least", "primes_upto",
-    "unwrap_matrix", "unwrap", "wrap", "y_range",
+    "partition", "unwrap_matrix", "unwrap", "wrap", "y_range",
     "philox4x64_10", "sample_noise", "evaluate", "sample_points",
     "dft_direct", "dft", "phaseshift_1d",
     "Params", "Result", "multiphaseshift", "round_samples", "shift_table", "READINGS",

@@ -32,7 +32,7 @@ from .philox import sample_noise
 from .primes import ith_prime_at_least
 from .signal import evaluate, sample_points
 from .classifier import bf16_round, bucket_features, bucket_label, prob_single
-from .unwrapping import unwrap, unwrap_matrix, wrap, y_range
+from .unwrapping import partition, unwrap, unwrap_matrix, wrap, y_range
 
 READINGS = {
     "R1": "Phaseshift listing labels the shifted and unshifted sample vectors the other "
@@ -80,6 +80,12 @@ READINGS = {
     "R19": "Noise (not in the paper): sigma/sqrt(2) (g1 + i g2) per sample from "
            "Philox4x64-10, key (seed, signal), counter (h // 2, set, round, 0), output "
            "words 0, 1 for even h and 2, 3 for odd h.",
+    "R22": "General partitions (Section 4.1 on the free order of a block's coordinates and "
+           "blocks of different sizes; Section 4.1.2 on prime d): blocks of sizes d_q "
+           "(sum d) over a coordinate order pi, y_q = sum_r w_{pi(s_q + r)} N^r with s_q the "
+           "block's first position; one shift eps = 1/(2 N^max d_q) on every axis, below the "
+           "inverse of the largest block bandwidth as the paper chooses (not one eps per "
+           "block); the band check of R16 uses each coordinate's own block size.",
 }
 
 STATUS_OK = 0
@@ -93,6 +99,8 @@ class Params:
     N: int
     k: int
     d1: int = 1
+    blocks: tuple | None = None        # R22: block sizes (sum d); None = uniform d1
+    order: tuple | None = None         # R22: coordinate order; None = natural
     c: float = 5.0
     ladder_K: int = 1
     tau: float | None = None
@@ -110,17 +118,22 @@ class Params:
     verify_eta: float | None = None    # None: eta
 
     @property
+    def block_sizes(self) -> tuple:
+        """Size of each unwrapped block (d2 entries)."""
+        return partition(self.d, self.d1, self.blocks, self.order)[0]
+
+    @property
     def d2(self) -> int:
-        return self.d // self.d1
+        return len(self.block_sizes)
 
     @property
     def NB(self) -> int:
-        """Bandwidth of one unwrapped coordinate, N^d1."""
-        return int(self.N) ** self.d1
+        """Largest bandwidth of an unwrapped coordinate, N^d1 (R22: N^max d_q)."""
+        return int(self.N) ** max(self.block_sizes)
 
     @property
     def eps(self) -> float:
-        """Shift eps = 1 / (2 N^d1) (Section 5)."""
+        """Shift eps = 1 / (2 N^d1) (Section 5); one eps for every axis (R22)."""
         return 1.0 / (2.0 * self.NB)
 
     @property
@@ -128,8 +141,9 @@ class Params:
         return self.eps if self.tau is None else float(self.tau)
 
     def validate(self):
-        if self.d < 1 or self.d1 < 1 or self.d % self.d1:
-            raise ValueError("d must be a positive multiple of d1")
+        if self.d < 1:
+            raise ValueError("d must be positive")
+        partition(self.d, self.d1, self.blocks, self.order)  # raises on a bad partition
         if self.N < 2 or self.N % 2:
             raise ValueError("N must be even and >= 2")
         if self.k < 1 or self.c <= 1.0 or self.ladder_K < 1:
@@ -185,7 +199,8 @@ def verify_samples(freqs, coeffs, P: Params, p: int, q: int, i: int, yR, aR,
     """R14: residual samples f(t_h) + noise - g(t_h) on the tilted line
     t_h = (h/p) U v, v_n = q^(n-1) mod p, h = 0..p-1 (noise of set 0, round i)."""
     v = np.array([pow(int(q), n, int(p)) for n in range(P.d2)], dtype=np.int64)
-    direction = unwrap_matrix(P.d, P.d1, P.N).astype(np.float64) @ v.astype(np.float64)
+    direction = (unwrap_matrix(P.d, P.d1, P.N, P.blocks, P.order).astype(np.float64)
+                 @ v.astype(np.float64))
     h = np.arange(p)
     t = (h.astype(np.float64) / p)[:, None] * direction[None, :]
     out = evaluate(freqs, coeffs, t) + sample_noise(seed, signal, i, 0, h, sigma)
@@ -228,9 +243,10 @@ def _decode(F, h, p, m, P: Params):
             if P.robust and abs(yc_real - yn) > NB / (4.0 * K):
                 valid = False
         y[n - 1] = yn
-    lo, hi = y_range(P.N, P.d1)                # R16: out-of-band decodes are no mode
-    if np.any(y < lo) or np.any(y > hi):
-        valid = False
+    for n, dn in enumerate(P.block_sizes):     # R16: out-of-band decodes are no mode
+        lo, hi = y_range(P.N, dn)
+        if y[n] < lo or y[n] > hi:
+            valid = False
     if P.robust and (int(y[m - 1]) % p) != h:  # R17
         valid = False
     return y, valid
@@ -262,7 +278,7 @@ def round_samples(freqs, coeffs, P: Params, p: int, m: int, i: int, yR, aR,
     V = []
     for s, (n, K) in enumerate([(1, 0)] + tab):
         shift = P.eps * K
-        t = sample_points(d, d1, N, p, m, n, shift)[h]
+        t = sample_points(d, d1, N, p, m, n, shift, P.blocks, P.order)[h]
         v = evaluate(freqs, coeffs, t)
         v = v + sample_noise(seed, signal, i, s, h, sigma)
         if len(aR):                                        # adaptive subtraction of g
@@ -283,7 +299,7 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
     freqs = np.asarray(freqs, dtype=np.int64)
     coeffs = np.asarray(coeffs, dtype=np.complex128)
     d, d1, d2, N = P.d, P.d1, P.d2, P.N
-    y_planted = unwrap(freqs, d1, N) if collect is not None else None
+    y_planted = unwrap(freqs, d1, N, P.blocks, P.order) if collect is not None else None
     tab = shift_table(d2, P.ladder_K)
     R: dict = {}
     trace, spectra, registry = [], [], []
@@ -364,7 +380,7 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
     if R:
         ys = np.array(list(R.keys()), dtype=np.int64).reshape(-1, d2)
         a = np.array(list(R.values()), dtype=np.complex128)
-        w = wrap(ys, d1, N)
+        w = wrap(ys, d1, N, P.blocks, P.order)
         order = np.lexsort(w.T[::-1])
         w, a, ys = w[order], a[order], ys[order]
     else:

@@ -9,6 +9,17 @@ which is injective on [-N/2, N/2)^d1 (balanced base-N digits).  In time, the
 same map reads t_l = N^r t~_q for l = d1 q + r (eq. (36); the block index of
 l is floor(l / d1) in 0-based terms).
 
+General partitions (Section 4.1: the coordinates of a block need not be in
+their natural order, and blocks need not have one size; Section 4.1.2, last
+paragraph: d prime, components of different bandwidths): blocks of sizes
+d_0, ..., d_{d2-1} (sum d) taken over a coordinate order pi (a permutation of
+0..d-1).  Block q starts at s_q = d_0 + ... + d_{q-1} and
+
+    y_q = sum_{r < d_q} w_{pi(s_q + r)} N^r,
+
+of bandwidth N^{d_q}.  blocks=None is the uniform partition into blocks of d1,
+order=None the natural order; together they are eq. (35).
+
 Reading: eq. (35)/(38) use powers N^0 .. N^(d1-1); the sampling lines of the
 MultiPhaseshift listing write N^1 .. N^d1, which would scale y by N and break
 the bound |y| < 1/(2 eps).  The oracle follows eq. (35).
@@ -18,41 +29,61 @@ from __future__ import annotations
 import numpy as np
 
 
-def unwrap_matrix(d: int, d1: int, N: int) -> np.ndarray:
-    """U in Z^{d x d2} with U[d1 q + r, q] = N^r, so that y = U^T w."""
-    if d % d1:
-        raise ValueError("d must be a multiple of d1")
-    d2 = d // d1
-    U = np.zeros((d, d2), dtype=object)
-    for q in range(d2):
-        for r in range(d1):
-            U[d1 * q + r, q] = int(N) ** r
+def partition(d: int, d1: int, blocks=None, order=None):
+    """(block sizes, coordinate order, block starts) of a partition of d coordinates."""
+    if blocks is None:
+        if d1 < 1 or d % d1:
+            raise ValueError("d must be a multiple of d1")
+        blocks = (int(d1),) * (d // d1)
+    blocks = tuple(int(b) for b in blocks)
+    if not blocks or any(b < 1 for b in blocks) or sum(blocks) != d:
+        raise ValueError("block sizes must be positive and sum to d")
+    order = tuple(range(d)) if order is None else tuple(int(x) for x in order)
+    if sorted(order) != list(range(d)):
+        raise ValueError("order must be a permutation of 0..d-1")
+    starts = [0]
+    for b in blocks:
+        starts.append(starts[-1] + b)
+    return blocks, order, tuple(starts)
+
+
+def unwrap_matrix(d: int, d1: int, N: int, blocks=None, order=None) -> np.ndarray:
+    """U in Z^{d x d2} with U[pi(s_q + r), q] = N^r, so that y = U^T w."""
+    blocks, order, starts = partition(d, d1, blocks, order)
+    U = np.zeros((d, len(blocks)), dtype=object)
+    for q, dq in enumerate(blocks):
+        for r in range(dq):
+            U[order[starts[q] + r], q] = int(N) ** r
     return U
 
 
-def unwrap(w: np.ndarray, d1: int, N: int) -> np.ndarray:
+def unwrap(w: np.ndarray, d1: int, N: int, blocks=None, order=None) -> np.ndarray:
     """y = U^T w for each row of w (int64 [k, d] -> int64 [k, d2]), eq. (35)."""
     w = np.asarray(w, dtype=np.int64)
     k, d = w.shape
-    d2 = d // d1
-    y = np.zeros((k, d2), dtype=np.int64)
-    for q in range(d2):
-        for r in range(d1):
-            y[:, q] += w[:, d1 * q + r] * (int(N) ** r)
+    blocks, order, starts = partition(d, d1, blocks, order)
+    y = np.zeros((k, len(blocks)), dtype=np.int64)
+    for q, dq in enumerate(blocks):
+        for r in range(dq):
+            y[:, q] += w[:, order[starts[q] + r]] * (int(N) ** r)
     return y
 
 
-def wrap(y: np.ndarray, d1: int, N: int) -> np.ndarray:
+def wrap(y: np.ndarray, d1: int, N: int, blocks=None, order=None) -> np.ndarray:
     """Inverse of eq. (35): balanced base-N digits in [-N/2, N/2)."""
     y = np.asarray(y, dtype=np.int64)
     k, d2 = y.shape
-    w = np.zeros((k, d2 * d1), dtype=np.int64)
+    d = d2 * d1 if blocks is None else sum(int(b) for b in blocks)
+    blocks, order, starts = partition(d, d1, blocks, order)
+    if len(blocks) != d2:
+        raise ValueError("y has the wrong number of unwrapped coordinates")
+    w = np.zeros((k, d), dtype=np.int64)
     half = N // 2
-    for q in range(d2):
+    for q, dq in enumerate(blocks):
         rest = y[:, q].copy()
-        for r in range(d1):
+        for r in range(dq):
             digit = np.mod(rest + half, N) - half
-            w[:, d1 * q + r] = digit
+            w[:, order[starts[q] + r]] = digit
             rest = (rest - digit) // N
         if np.any(rest != 0):
             raise ValueError("value outside the unwrapped range")
@@ -60,6 +91,7 @@ def wrap(y: np.ndarray, d1: int, N: int) -> np.ndarray:
 
 
 def y_range(N: int, d1: int) -> tuple[int, int]:
-    """Inclusive range of an unwrapped coordinate: [-(N/2) S, (N/2 - 1) S], S = sum N^r."""
+    """Inclusive range of a coordinate unwrapped from a block of d1:
+    [-(N/2) S, (N/2 - 1) S], S = sum N^r."""
     S = sum(int(N) ** r for r in range(d1))
     return -(N // 2) * S, (N // 2 - 1) * S

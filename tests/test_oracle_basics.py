@@ -52,6 +52,38 @@ def test_unwrap_bijection_exhaustive(N, d1):
     assert y[0, 0] == sum((-N // 2) * N ** r for r in range(d1))
 
 
+@pytest.mark.parametrize("N,blocks,order", [(4, (2, 3), (4, 0, 3, 1, 2)), (6, (1, 2), (1, 2, 0)),
+                                            (20, (3, 1), None), (2, (1, 4, 2), (6, 5, 4, 3, 2, 1, 0))])
+def test_unwrap_general_bijection_exhaustive(N, blocks, order):
+    # a general partition maps [-N/2, N/2)^d one to one onto the product of its blocks' bands
+    d = sum(blocks)
+    grids = np.meshgrid(*[np.arange(-N // 2, N // 2)] * d, indexing="ij")
+    w = np.stack([g.reshape(-1) for g in grids], axis=1).astype(np.int64)
+    y = uw.unwrap(w, 1, N, blocks, order)
+    assert y.shape == (N ** d, len(blocks))
+    assert len(np.unique(y, axis=0)) == N ** d
+    for q, dq in enumerate(blocks):
+        lo, hi = uw.y_range(N, dq)
+        assert y[:, q].min() == lo and y[:, q].max() == hi
+    assert np.array_equal(uw.wrap(y, 1, N, blocks, order), w)
+    U = uw.unwrap_matrix(d, 1, N, blocks, order)
+    assert np.array_equal((w.astype(object) @ U).astype(np.int64), y)
+
+
+def test_unwrap_general_by_hand():
+    # d = 3, blocks (2, 1), order (2, 0, 1): y_0 = w_2 + N w_0, y_1 = w_1
+    y = uw.unwrap(np.array([[1, -2, 3]]), 1, 8, (2, 1), (2, 0, 1))
+    assert y.tolist() == [[3 + 8 * 1, -2]]
+    # the paper's uneven split of its 20-dimensional example: four blocks of 3, two of 4
+    P = oracle.Params(d=20, N=20, k=1, blocks=(3, 3, 3, 3, 4, 4))
+    assert P.d2 == 6 and P.NB == 20 ** 4 and P.eps == 1.0 / 320000.0
+    lo, hi = uw.y_range(20, 3)
+    assert hi - lo + 1 == 8000
+    for bad in [dict(blocks=(3, 3)), dict(blocks=(0, 20)), dict(order=tuple(range(19)) + (0,))]:
+        with pytest.raises(ValueError):
+            oracle.Params(d=20, N=20, k=1, **bad).validate()
+
+
 def test_unwrap_paper_example():
     ex = GOLD["worked_example"]
     lo, hi = uw.y_range(ex["N"], ex["d1"])

@@ -24,7 +24,8 @@ def _run(name, b=0, **over):
     w, a = batch.signal(b)
     P = oracle.Params(d=cfg["d"], N=cfg["N"], k=int(batch.k[b]), d1=cfg["d1"], c=cfg["c"],
                       ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
-                      p_min=cfg["p_min"], robust=cfg["robust"])
+                      p_min=cfg["p_min"], robust=cfg["robust"], blocks=cfg["blocks"],
+                      order=cfg["order"])
     return w, a, P, batch
 
 
@@ -43,11 +44,12 @@ def _closed_form(y_pl, a_pl, y_R, a_R, P, p, m, tab):
 
 @pytest.mark.parametrize("name,over", [("c1", {}), ("c1", {"d1": 2}), ("c2", {}),
                                        ("e4", {}), ("c3b", {"k": 60, "sigma": 0.0}),
-                                       ("e1", {"k": 24}), ("e2", {"k": 12})])
+                                       ("e1", {"k": 24}), ("e2", {"k": 12}), ("e3", {}),
+                                       ("c2", {"blocks": (2, 1, 1), "order_seed": 2001})])
 def test_round_spectra_match_eq41(name, over):
     w, a, P, _ = _run(name, **over)
     r = oracle.multiphaseshift(w, a, P, keep_spectra=True)
-    y_pl = uw.unwrap(w, P.d1, P.N)
+    y_pl = uw.unwrap(w, P.d1, P.N, P.blocks, P.order)
     tab = oracle.shift_table(P.d2, P.ladder_K)
     for tr, F, (yR, aR) in zip(r.trace, r.spectra, r.registry):
         ref = _closed_form(y_pl, a, yR, aR, P, tr["p"], tr["m"], tab)
@@ -65,6 +67,23 @@ def test_single_mode_round_one(d, N, d1):
         w = rng.integers(-N // 2, N // 2, size=(1, d))
         a = np.exp(2j * np.pi * rng.uniform(size=1)) * rng.uniform(1, 3)
         r = oracle.multiphaseshift(w, a, oracle.Params(d=d, N=N, k=1, d1=d1))
+        assert r.rounds == 1 and r.status == 0
+        assert np.array_equal(r.freqs, w)
+        assert abs(r.coeffs[0] - a[0]) < 1e-9
+
+
+@pytest.mark.parametrize("d,N,blocks", [(7, 20, (4, 3)), (5, 64, (2, 1, 2)), (3, 1024, (1, 2))])
+def test_single_mode_round_one_uneven(d, N, blocks):
+    # k = 1 with blocks of different sizes (d prime: Section 4.1.2) over a random order:
+    # the ratios are e^{2 pi i eps y_n} with one eps = 1/(2 N^max d_q), exact in round 1
+    rng = np.random.default_rng(d * 7 + N)
+    for _ in range(5):
+        order = tuple(int(x) for x in rng.permutation(d))
+        w = rng.integers(-N // 2, N // 2, size=(1, d))
+        a = np.exp(2j * np.pi * rng.uniform(size=1)) * rng.uniform(1, 3)
+        P = oracle.Params(d=d, N=N, k=1, blocks=blocks, order=order)
+        assert P.NB == N ** max(blocks)
+        r = oracle.multiphaseshift(w, a, P)
         assert r.rounds == 1 and r.status == 0
         assert np.array_equal(r.freqs, w)
         assert abs(r.coeffs[0] - a[0]) < 1e-9
@@ -95,19 +114,37 @@ def test_bruteforce_full_grid(d, N, d1, k, seed):
     assert np.abs(r.coeffs - fa).max() < 1e-9
 
 
+@pytest.mark.parametrize("d,N,blocks,order,k,seed", [(3, 16, (2, 1), (2, 0, 1), 6, 21),
+                                                     (5, 4, (3, 2), (3, 1, 4, 0, 2), 5, 23),
+                                                     (4, 8, (1, 3), (3, 2, 1, 0), 5, 25)])
+def test_bruteforce_full_grid_uneven(d, N, blocks, order, k, seed):
+    # general partitions recover what the d-dim DFT of the full grid finds
+    w, a = workloads.planted_signal(seed, 0, d, N, k)
+    fw, fa = _bruteforce_spectrum(w, a, d, N)
+    assert fw.shape == (k, d)
+    r = oracle.multiphaseshift(w, a, oracle.Params(d=d, N=N, k=k, blocks=blocks, order=order))
+    assert r.status == 0
+    assert np.array_equal(r.freqs, fw)
+    assert np.abs(r.coeffs - fa).max() < 1e-9
+
+
 # coefficient tolerance: 1e-9, and 1e-8 for the d = 100 and 1000 recipes, where the oracle
 # evaluates exp(2 pi i w . t) at arguments of up to N^d1 / 2 = 1.6e6 cycles in FP64
 # (a phase error of about 1e-9 rad per term)
 @pytest.mark.parametrize("name,over,trials,tol", [("c1", {}, 40, 1e-9), ("c1", {"d1": 2}, 20, 1e-9),
                                                   ("c2", {}, 3, 1e-9), ("e4", {}, 3, 1e-9),
                                                   ("e1", {"k": 32}, 3, 1e-8),
-                                                  ("e2", {"k": 16}, 2, 1e-8)])
+                                                  ("e2", {"k": 16}, 2, 1e-8),
+                                                  ("e3", {}, 3, 1e-9),
+                                                  ("c2", {"blocks": (2, 1, 1),
+                                                          "order_seed": 2001}, 2, 1e-9)])
 def test_exact_recovery_noiseless(name, over, trials, tol):
     cfg = workloads.config(name, **over)
     for t in range(trials):
         w, a = workloads.planted_signal(cfg["seed"] + t, 0, cfg["d"], cfg["N"], cfg["k"], cfg["mag"])
         P = oracle.Params(d=cfg["d"], N=cfg["N"], k=cfg["k"], d1=cfg["d1"], c=cfg["c"],
-                          tau=cfg["tau"], eta=cfg["eta"])
+                          tau=cfg["tau"], eta=cfg["eta"], blocks=cfg["blocks"],
+                          order=cfg["order"])
         r = oracle.multiphaseshift(w, a, P)
         o = np.lexsort(w.T[::-1])
         assert r.status == 0
@@ -176,6 +213,7 @@ def _pins_hold(monkeypatch=None):
         test_exact_recovery_noiseless("c1", {}, 5, 1e-9)
         test_single_mode_round_one(2, 64, 1)
         test_bruteforce_full_grid(2, 64, 2, 8, 1001)
+        test_bruteforce_full_grid_uneven(3, 16, (2, 1), (2, 0, 1), 6, 21)
     except AssertionError:
         return False
     return True
@@ -186,19 +224,22 @@ def test_pins_hold_unmutated():
 
 
 @pytest.mark.parametrize("mutation", ["dft_sign", "unwrap_power", "no_residual",
-                                      "shift_axis", "coef_scale", "arg_sign", "round_floor"])
+                                      "shift_axis", "coef_scale", "arg_sign", "round_floor",
+                                      "wrap_natural_order", "block_digits_reversed"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
     if mutation == "dft_sign":
         monkeypatch.setattr(mps_mod, "dft", lambda v: np.fft.ifft(v) * v.shape[-1])
     elif mutation == "unwrap_power":
         orig = sig_mod.unwrap_matrix
-        monkeypatch.setattr(sig_mod, "unwrap_matrix", lambda d, d1, N: orig(d, d1, N) * N)
+        monkeypatch.setattr(sig_mod, "unwrap_matrix",
+                            lambda d, d1, N, *part: orig(d, d1, N, *part) * N)
     elif mutation == "no_residual":
         monkeypatch.setattr(mps_mod, "_residual", lambda yR, aR, p, m, n, shift: np.zeros(p, complex))
     elif mutation == "shift_axis":
         orig = sig_mod.sample_points
         monkeypatch.setattr(mps_mod, "sample_points",
-                            lambda d, d1, N, p, m, n, shift: orig(d, d1, N, p, m, m, shift))
+                            lambda d, d1, N, p, m, n, shift, *part:
+                            orig(d, d1, N, p, m, m, shift, *part))
     elif mutation == "coef_scale":
         monkeypatch.setattr(mps_mod, "_coefficient", lambda F0h, p: complex(F0h) / (p - 1))
     elif mutation == "arg_sign":
@@ -206,6 +247,20 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
     elif mutation == "round_floor":
         # R11 misread: truncation towards -inf instead of rounding to nearest
         monkeypatch.setattr(mps_mod, "_round_half_away", lambda x: math.floor(x))
+    elif mutation == "wrap_natural_order":
+        # R22 misread: the answer wrapped back without the coordinate order
+        orig = uw.wrap
+        monkeypatch.setattr(mps_mod, "wrap",
+                            lambda y, d1, N, blocks=None, order=None: orig(y, d1, N, blocks))
+    elif mutation == "block_digits_reversed":
+        # R22 misread: the last coordinate of a block is the least significant digit
+        orig = sig_mod.unwrap_matrix
+
+        def rev(d, d1, N, blocks=None, order=None):
+            b, o, s = uw.partition(d, d1, blocks, order)
+            o2 = sum((tuple(reversed(o[s[q]:s[q + 1]])) for q in range(len(b))), ())
+            return orig(d, d1, N, blocks, o2)
+        monkeypatch.setattr(sig_mod, "unwrap_matrix", rev)
     assert not _pins_hold()
 
 

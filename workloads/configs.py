@@ -17,10 +17,18 @@ measured single-GPU configurations:
           (the paper's experiment at d = 100; k = 2^10 needs p > 4096, beyond
           the FP64 in-LDS DFT)
   e2      as e1 at d=1000 (d2 = 200 unwrapped coordinates, 201 sets per round)
+  e3      e4 split unevenly as in Section 4.1: four blocks of 3 and two of 4, over a
+          shuffled coordinate order
+
+blocks / order_seed describe a general partition: block sizes (sum d; None:
+uniform blocks of d1) and the seed of a random coordinate order (None: the
+natural order), drawn here as a permutation of 0..d-1.
 """
 from __future__ import annotations
 
 import copy
+
+import numpy as np
 
 CONFIGS = {
     "c1": dict(d=2, N=64, k=8, B=1, mag=(1.0, 1.0), sigma=0.0, seed=1000,
@@ -56,13 +64,24 @@ CONFIGS = {
     "e2": dict(d=1000, N=20, k=64, B=100, mag=(1.0, 1.0), sigma=0.0, seed=6200,
                d1=5, c=5.0, ladder_K=1, tau=1e-6, eta=1e-8, precision="fp64",
                p_min=0, robust=False),
+    "e3": dict(d=20, N=20, k=100, B=1, mag=(1.0, 1.0), sigma=0.0, seed=6300,
+               d1=4, blocks=(3, 3, 3, 3, 4, 4), order_seed=6301, c=5.0, ladder_K=1,
+               tau=1e-6, eta=1e-8, precision="fp64", p_min=0, robust=False),
 }
 
 
 def config(name: str, **over):
     """A copy of the named recipe with fields overridden by keyword."""
-    cfg = dict(verify=False, verify_eta=None, residual=0)
+    cfg = dict(verify=False, verify_eta=None, residual=0, blocks=None, order_seed=None)
     cfg.update(copy.deepcopy(CONFIGS[name]))
     cfg.update(over)
     cfg["name"] = name
+    cfg["order"] = coordinate_order(cfg["order_seed"], cfg["d"])
     return cfg
+
+
+def coordinate_order(seed, d: int):
+    """A seeded random permutation of the d coordinates (None: natural order)."""
+    if seed is None:
+        return None
+    return tuple(int(x) for x in np.random.default_rng(seed).permutation(d))
