@@ -14,7 +14,8 @@ inconsistent are resolved as listed in `READINGS` below.
 
 Parity pins (tests under tests/test_oracle_*.py): closed forms of eqs. (3)
 and (41), a brute-force O(p^2) DFT, exhaustive unwrap/wrap bijections, the
-k = 1 special case, brute-force d-dimensional DFTs on tiny full grids, exact
+k = 1 special case, brute-force d-dimensional DFTs on tiny full grids (uniform
+and uneven partitions, shuffled coordinate orders, a hand-computed unwrapping), exact
 recovery of planted spectra, the d = 1 reduction to Phaseshift, per-round
 isolation statistics, the Philox known-answer vector, the closed form of the
 verification line (R14) and the false-accept experiment it is there for; the
