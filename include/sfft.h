@@ -71,8 +71,10 @@ enum { SFFT_RESIDUAL_SPECTRUM = 0, SFFT_RESIDUAL_SAMPLES = 1 };
 typedef struct {
   int32_t d;          /* dimension, >= 1                                            */
   int32_t d1;         /* unwrapping block size; d % d1 == 0; d2 = d / d1 <= 256;
-                         FP32 also needs 2 (S+1) <= 128 (else SFFT_ERANGE)          */
-  int64_t N;          /* per-dimension bandwidth, even, >= 2; N^d1 <= 2^40          */
+                         FP32 also needs 2 (S+1) <= 128 (else SFFT_ERANGE).
+                         Ignored when `blocks` is given                             */
+  int64_t N;          /* per-dimension bandwidth, even, >= 2; N^d1 <= 2^40 (with
+                         `blocks`: N^(largest block) <= 2^40)                       */
   int32_t k_max;      /* largest sparsity of any signal recovered with this plan    */
   double c;           /* p_i = i-th prime >= max(ceil(c k*), p_min); c > 1          */
   int32_t prime_rule; /* SFFT_PRIME_PAPER, or SFFT_PRIME_SMOOTH (p - 1 7-smooth)    */
@@ -121,6 +123,19 @@ typedef struct {
   int32_t sched_dft_batch; /* FP32: most sample sets transformed together in one
                               Bluestein pass over the LDS buffer: 1 = one set at a
                               time, 2..64, 0 = as many as fit                        */
+  /* General partitions (Section 4.1: a block's coordinates need not be in their
+   * natural order and blocks need not have one size; Section 4.1.2: d prime).
+   * Host arrays, read only by sfft_plan_create (and sfft_autotune), owned by the
+   * caller.  Block q (sizes d_0, d_1, ...) holds the coordinates
+   * order[s_q], ..., order[s_q + d_q - 1], s_q = d_0 + ... + d_{q-1}, the first
+   * the least significant base-N digit: y_q = sum_r w[order[s_q + r]] N^r.  One
+   * shift eps = 1 / (2 N^(largest block)) serves every axis; each coordinate's
+   * decoded value must lie in its own block's band.  Zero-filled fields give
+   * the uniform partition of d1 in the natural order (eq. (35)). */
+  const int32_t* blocks;   /* n_blocks sizes, each >= 1, summing to d; NULL: d / d1
+                              blocks of d1                                           */
+  int32_t n_blocks;        /* 1..256 with `blocks` (this is d2); 0 without           */
+  const int32_t* order;    /* a permutation of 0..d-1; NULL: 0, 1, ..., d-1          */
 } sfft_params;
 
 /* A batch of synthetic black-box signals with planted spectra.  All pointers
@@ -242,7 +257,7 @@ int32_t sfft_plan_num_sets(sfft_plan plan);
 typedef struct {
   double c;                /* oversampling factor                                    */
   int32_t sched_nt[4];     /* schedules, as in sfft_params                           */
-  int32_t sched_fft;
+  int32_t sched_fft;       /* as run: 0 in the candidate's params is logged as 1     */
   int32_t sched_dft_batch;
   int32_t status;          /* SFFT_OK, or why the candidate's plan was refused       */
   int32_t exact;           /* signals with status SFFT_OK whose recovered support

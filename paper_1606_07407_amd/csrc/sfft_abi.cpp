@@ -62,18 +62,59 @@ struct sfft_plan_s {
   int max_batch = 0;
   KParams kp;
   int32_t* d_primes = nullptr;
+  char* d_part = nullptr;
   char* d_ws = nullptr;
   int* d_queue = nullptr;
 };
 
+// The partition of the d coordinates: block sizes and coordinate order (uniform
+// blocks of d1 in the natural order unless `blocks` / `order` are given).
+static sfft_status resolve_partition(const sfft_params* p, std::vector<int32_t>* blocks,
+                                     std::vector<int32_t>* order) {
+  if (p->d < 1) return fail(SFFT_EINVAL, "d must be >= 1");
+  blocks->clear();
+  if (!p->blocks) {
+    if (p->n_blocks != 0) return fail(SFFT_EINVAL, "n_blocks without blocks");
+    if (p->d1 < 1 || p->d % p->d1 != 0)
+      return fail(SFFT_EINVAL, "d (%d) must be a positive multiple of d1 (%d)", p->d, p->d1);
+    if (p->d / p->d1 > kMaxD2) return fail(SFFT_ERANGE, "d2 = d/d1 exceeds %d", kMaxD2);
+    blocks->assign(p->d / p->d1, p->d1);
+  } else {
+    if (p->n_blocks < 1) return fail(SFFT_EINVAL, "n_blocks must be >= 1 with blocks");
+    if (p->n_blocks > kMaxD2) return fail(SFFT_ERANGE, "n_blocks exceeds %d", kMaxD2);
+    int64_t sum = 0;
+    for (int q = 0; q < p->n_blocks; ++q) {
+      if (p->blocks[q] < 1) return fail(SFFT_EINVAL, "block %d has size %d", q, p->blocks[q]);
+      sum += p->blocks[q];
+      blocks->push_back(p->blocks[q]);
+    }
+    if (sum != p->d) return fail(SFFT_EINVAL, "block sizes sum to %lld, not d = %d",
+                                 (long long)sum, p->d);
+  }
+  order->resize(p->d);
+  if (!p->order) {
+    for (int l = 0; l < p->d; ++l) (*order)[l] = l;
+  } else {
+    std::vector<char> seen(p->d, 0);
+    for (int l = 0; l < p->d; ++l) {
+      const int32_t v = p->order[l];
+      if (v < 0 || v >= p->d || seen[v]) return fail(SFFT_EINVAL, "order is not a permutation");
+      seen[v] = 1;
+      (*order)[l] = v;
+    }
+  }
+  return SFFT_OK;
+}
+
 static sfft_status validate_params(const sfft_params* p) {
   if (!p) return fail(SFFT_EINVAL, "params is NULL");
-  if (p->d < 1 || p->d1 < 1 || p->d % p->d1 != 0)
-    return fail(SFFT_EINVAL, "d (%d) must be a positive multiple of d1 (%d)", p->d, p->d1);
-  if (p->d / p->d1 > kMaxD2) return fail(SFFT_ERANGE, "d2 = d/d1 exceeds %d", kMaxD2);
+  std::vector<int32_t> blocks, order;
+  const sfft_status ps = resolve_partition(p, &blocks, &order);
+  if (ps != SFFT_OK) return ps;
+  const int dmax = *std::max_element(blocks.begin(), blocks.end());
   if (p->N < 2 || p->N % 2 != 0) return fail(SFFT_EINVAL, "N must be even and >= 2");
   double nb = 1.0;
-  for (int r = 0; r < p->d1; ++r) nb *= (double)p->N;
+  for (int r = 0; r < dmax; ++r) nb *= (double)p->N;
   if (nb > 1099511627776.0) return fail(SFFT_ERANGE, "N^d1 exceeds 2^40");
   if (p->k_max < 1) return fail(SFFT_EINVAL, "k_max must be >= 1");
   if (!(p->c > 1.0) || !std::isfinite(p->c)) return fail(SFFT_EINVAL, "c must be > 1");
@@ -129,12 +170,14 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   if (st != SFFT_OK) return st;
   if (max_batch < 1) return fail(SFFT_EINVAL, "max_batch must be >= 1");
   const sfft_params& P = *params;
+  std::vector<int32_t> blocks, order;
+  resolve_partition(params, &blocks, &order);  // checked by validate_params
 
   KParams kp;
   memset(&kp, 0, sizeof(kp));
   kp.d = P.d;
-  kp.d1 = P.d1;
-  kp.d2 = P.d / P.d1;
+  kp.d1 = *std::max_element(blocks.begin(), blocks.end());
+  kp.d2 = (int)blocks.size();
   kp.S = (P.ladder_K > 1) ? 2 * kp.d2 : kp.d2;
   kp.S1 = kp.S + 1;
   kp.RT = (2 * kp.S1 + 15) / 16;
@@ -143,7 +186,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
                 kMaxRT);
   kp.N = P.N;
   kp.NB = 1;
-  for (int r = 0; r < P.d1; ++r) kp.NB *= P.N;
+  for (int r = 0; r < kp.d1; ++r) kp.NB *= P.N;
   kp.k_max = P.k_max;
   // registry capacity: k_max, plus the repair slack of the verification round
   kp.cap = P.k_max + (P.verify ? std::max(16, (P.k_max + 7) / 8) : 0);
@@ -289,11 +332,34 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   sfft_plan plan = new (std::nothrow) sfft_plan_s();
   if (!plan) return fail(SFFT_ENOMEM, "host allocation failed");
   plan->prm = P;
+  plan->prm.blocks = nullptr;  // the caller's arrays are not kept
+  plan->prm.order = nullptr;
   plan->device = dev;
   plan->max_batch = max_batch;
 
   const size_t ws_bytes = (size_t)kp.n_slots * kp.ws_slot;
+  // partition tables: block starts [d2 + 1], coordinate order [d], band sums [d2]
+  std::vector<int32_t> blk(kp.d2 + 1, 0);
+  std::vector<int64_t> band_s(kp.d2, 0);
+  bool natural = true;
+  for (int q = 0; q < kp.d2; ++q) {
+    blk[q + 1] = blk[q] + blocks[q];
+    int64_t s = 0, pw = 1;
+    for (int r = 0; r < blocks[q]; ++r) {
+      s += pw;
+      pw *= P.N;
+    }
+    band_s[q] = s;
+    if (blocks[q] != 1) natural = false;
+  }
+  for (int l = 0; l < P.d; ++l)
+    if (order[l] != l) natural = false;
+  kp.wrap_rank = natural ? 0 : 1;
+  const size_t part_blk = 0, part_perm = al256(4 * (size_t)(kp.d2 + 1));
+  const size_t part_band = part_perm + al256(4 * (size_t)P.d);
+  const size_t part_bytes = part_band + 8 * (size_t)kp.d2;
   if ((e = hipMalloc((void**)&plan->d_primes, primes.size() * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc((void**)&plan->d_part, part_bytes)) != hipSuccess ||
       (e = hipMalloc((void**)&plan->d_ws, ws_bytes)) != hipSuccess ||
       (e = hipMalloc((void**)&plan->d_queue, 256)) != hipSuccess) {
     sfft_plan_destroy(plan);
@@ -301,6 +367,12 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
                 hipGetErrorString(e));
   }
   if ((e = hipMemcpy(plan->d_primes, primes.data(), primes.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(plan->d_part + part_blk, blk.data(), blk.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(plan->d_part + part_perm, order.data(), order.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(plan->d_part + part_band, band_s.data(), band_s.size() * sizeof(int64_t),
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(plan->d_ws, 0, ws_bytes)) != hipSuccess ||
       (e = hipMemset(plan->d_queue, 0, 256)) != hipSuccess) {
@@ -314,6 +386,9 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   }
   kp.primes = plan->d_primes;
   kp.n_primes = (int)primes.size();
+  kp.blk = reinterpret_cast<const int32_t*>(plan->d_part + part_blk);
+  kp.perm = reinterpret_cast<const int32_t*>(plan->d_part + part_perm);
+  kp.band_s = reinterpret_cast<const int64_t*>(plan->d_part + part_band);
   kp.ws = plan->d_ws;
   kp.queue = plan->d_queue;
   plan->kp = kp;
@@ -325,6 +400,7 @@ sfft_status sfft_plan_destroy(sfft_plan plan) {
   if (!plan) return SFFT_OK;
   (void)hipDeviceSynchronize();
   if (plan->d_primes) (void)hipFree(plan->d_primes);
+  if (plan->d_part) (void)hipFree(plan->d_part);
   if (plan->d_ws) (void)hipFree(plan->d_ws);
   if (plan->d_queue) (void)hipFree(plan->d_queue);
   delete plan;

@@ -79,7 +79,7 @@ struct WsLayout {
 // Everything a kernel needs about a plan (passed by value).
 struct KParams {
   int d, d1, d2, S, S1, RT;
-  int64_t N, NB;          // NB = N^d1
+  int64_t N, NB;          // NB = N^d1 (d1: the largest block)
   int k_max, cap, m_max, pairs_max;
   int max_rounds, prime_rule, p_min, ladder_K, robust, precision;
   double c, tau, tau_noise, eta;
@@ -103,6 +103,13 @@ struct KParams {
   int sched_nt[kNtBands]; // sampler column tiles per wave per p band (0: built-in choice)
   int sched_fft;          // kFftRadix24Head or kFftRadix8Head
   int sched_dft_batch;    // FP32: most sets per batched Bluestein pass (0: all that fit)
+  // Partition of the d coordinates into d2 blocks (device tables): block q holds
+  // coordinates perm[blk[q]] .. perm[blk[q+1] - 1], the first the least
+  // significant base-N digit; band_s[q] = sum_{r < d_q} N^r bounds its band.
+  const int32_t* blk;     // [d2 + 1] block starts
+  const int32_t* perm;    // [d] coordinate order
+  const int64_t* band_s;  // [d2]
+  int wrap_rank;          // lexicographic order of w differs from that of y
 };
 
 struct KBatch {

@@ -126,19 +126,21 @@ struct WgState {
 };
 
 // --------------------------------------------------- per-signal set-up -----
-// Planted modes: y = U^T w (eq. (35)) and the coefficient rows
+// Planted modes: y = U^T w (eq. (35); block q of a general partition holds the
+// coordinates perm[blk[q]] .. perm[blk[q+1] - 1], the first the least
+// significant base-N digit) and the coefficient rows
 // C[j][0] = a_j, C[j][s] = a_j exp(2 pi i eps K_s y_{j,n_s}).
 template <typename T>
 __device__ void planted_setup(const KParams& kp, const KBatch& kb, char* slot, WgState& st) {
   int64_t* ypl = reinterpret_cast<int64_t*>(slot + kp.lay.ypl);
   cpx<T>* cc = ws_cpx<T>(slot, kp.lay.ccomp);
-  const int d = kp.d, d1 = kp.d1, d2 = kp.d2, S1 = kp.S1;
+  const int d = kp.d, d2 = kp.d2, S1 = kp.S1;
   for (int j = threadIdx.x; j < st.M_pl; j += kWG) {
     const int64_t* w = kb.freqs + (st.off + j) * d;
     for (int q = 0; q < d2; ++q) {
       int64_t y = 0, pw = 1;
-      for (int r = 0; r < d1; ++r) {
-        y += w[d1 * q + r] * pw;
+      for (int l = kp.blk[q]; l < kp.blk[q + 1]; ++l) {
+        y += w[kp.perm[l]] * pw;
         pw *= kp.N;
       }
       ypl[(size_t)j * d2 + q] = y;
@@ -762,16 +764,8 @@ __device__ void decode_round(const KParams& kp, const KOut& ko, char* slot, WgSt
   const int p = st.p, d2 = kp.d2, S = kp.S;
   const int64_t NB = kp.NB;
   const double NBd = (double)NB;
-  int64_t lo = 0, hi = 0;
-  {
-    int64_t Ssum = 0, pw = 1;
-    for (int r = 0; r < kp.d1; ++r) {
-      Ssum += pw;
-      pw *= kp.N;
-    }
-    lo = -(kp.N / 2) * Ssum;
-    hi = (kp.N / 2 - 1) * Ssum;
-  }
+  // band of coordinate n: [-(N/2) S_n, (N/2 - 1) S_n], S_n = band_s[n]
+  const int64_t nlo = -(kp.N / 2), nhi = kp.N / 2 - 1;
   for (int c = threadIdx.x; c < st.ncand; c += kWG) {
     const int h = cand[c];
     const double f0x = (double)V[h].x, f0y = (double)V[h].y;
@@ -797,7 +791,8 @@ __device__ void decode_round(const KParams& kp, const KOut& ko, char* slot, WgSt
         yn = yn + llround(delta * NBd / (M_PI * (double)K));
         if (kp.robust && fabs(yc_real - (double)yn) > NBd / (4.0 * (double)K)) valid = false;
       }
-      if (yn < lo || yn > hi) valid = false;
+      const int64_t Sn = kp.band_s[n];
+      if (yn < nlo * Sn || yn > nhi * Sn) valid = false;
       y[n] = yn;
     }
     if (kp.robust && pmod64(y[st.m0], p) != h) valid = false;
@@ -1177,11 +1172,12 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
 }
 
 // ------------------------------------------------------------- output ------
-// Wrap y back to w with balanced base-N digits (inverse of eq. (35)) and
-// write the registry in lexicographic order of w.
+// Wrap y back to w with balanced base-N digits (inverse of eq. (35), over the
+// blocks and coordinate order of the partition) and write the registry in
+// lexicographic order of w.
 __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgState& st,
                                     char* lds) {
-  const int d = kp.d, d1 = kp.d1, d2 = kp.d2, nR = st.nR;
+  const int d = kp.d, d2 = kp.d2, nR = st.nR;
   const int64_t* ry = reg_y(kp, slot, st.sb);
   const double2* ra = reg_a(kp, slot, st.sb);
   const int* ord = reg_ord(kp, slot, st.cur);
@@ -1193,15 +1189,15 @@ __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgSt
   for (int e = threadIdx.x; e < nOut; e += kWG) {
     for (int q = 0; q < d2; ++q) {
       int64_t rest = ry[(size_t)ord[e] * d2 + q];
-      for (int r = 0; r < d1; ++r) {
+      for (int l = kp.blk[q]; l < kp.blk[q + 1]; ++l) {
         const int64_t digit = pmod64(rest + half, kp.N) - half;
-        fo[(size_t)e * d + d1 * q + r] = digit;
+        fo[(size_t)e * d + kp.perm[l]] = digit;
         rest = (rest - digit) / kp.N;
       }
     }
   }
   __syncthreads();
-  if (d1 > 1 && nOut > 1) {
+  if (kp.wrap_rank && nOut > 1) {
     // lexicographic order of w differs from that of y: rank and permute
     int* rank = reinterpret_cast<int*>(lds);
     for (int e = threadIdx.x; e < nOut; e += kWG) {

@@ -112,7 +112,9 @@ int count_exact(Work& w) {
 void fill_entry(const sfft_params& p, sfft_tune_entry* e) {
   e->c = p.c;
   for (int b = 0; b < kNtBands; ++b) e->sched_nt[b] = p.sched_nt[b];
-  e->sched_fft = p.sched_fft;
+  // the schedule as run: sched_fft 0 is the radix-2/4 head, which is what the
+  // winner written back to the caller says as well
+  e->sched_fft = p.sched_fft == 0 ? sfft::kFftRadix24Head : p.sched_fft;
   e->sched_dft_batch = p.sched_dft_batch;
   e->status = SFFT_OK;
   e->exact = 0;

@@ -51,6 +51,9 @@ class sfft_params(ctypes.Structure):
         ("sched_nt", ctypes.c_int32 * 4),
         ("sched_fft", ctypes.c_int32),
         ("sched_dft_batch", ctypes.c_int32),
+        ("blocks", ctypes.POINTER(ctypes.c_int32)),
+        ("n_blocks", ctypes.c_int32),
+        ("order", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -181,15 +184,26 @@ class Params:
     sched_nt: tuple = (0, 0, 0, 0)  # kernel schedules; 0 = built-in choice
     sched_fft: int = 0
     sched_dft_batch: int = 0
+    blocks: tuple | None = None     # general partition: block sizes (sum d); None = d1
+    order: tuple | None = None      # coordinate order (a permutation of 0..d-1)
 
     def to_c(self) -> sfft_params:
-        return sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
-                           self.p_min, self.ladder_K, self.tau, self.tau_noise, self.eta,
-                           self.max_rounds, self.precision, self.robust, self.classifier,
-                           _ptr(self.mlp_weights), self.mlp_threshold, self.feature_scale,
-                           self.verify, self.verify_eta, self.residual,
-                           (ctypes.c_int32 * 4)(*[int(v) for v in self.sched_nt]),
-                           self.sched_fft, self.sched_dft_batch)
+        c = sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
+                        self.p_min, self.ladder_K, self.tau, self.tau_noise, self.eta,
+                        self.max_rounds, self.precision, self.robust, self.classifier,
+                        _ptr(self.mlp_weights), self.mlp_threshold, self.feature_scale,
+                        self.verify, self.verify_eta, self.residual,
+                        (ctypes.c_int32 * 4)(*[int(v) for v in self.sched_nt]),
+                        self.sched_fft, self.sched_dft_batch)
+        # the arrays live as long as the returned structure (sfft_plan_create copies them)
+        if self.blocks is not None:
+            c._blocks = (ctypes.c_int32 * len(self.blocks))(*[int(v) for v in self.blocks])
+            c.blocks = ctypes.cast(c._blocks, ctypes.POINTER(ctypes.c_int32))
+            c.n_blocks = len(self.blocks)
+        if self.order is not None:
+            c._order = (ctypes.c_int32 * len(self.order))(*[int(v) for v in self.order])
+            c.order = ctypes.cast(c._order, ctypes.POINTER(ctypes.c_int32))
+        return c
 
 
 class Plan:

@@ -77,6 +77,13 @@ BAD = [
     (dict(k_max=1700, c=5.0), -2),                   # first round needs p >= 8500 > 8192
     (dict(k_max=900, c=5.0, precision=0), -2),       # FP64: p >= 4500 > 4096
     (dict(d=40, d1=1, ladder_K=4), -2),              # 2 (S+1) rows beyond 8 MFMA tiles
+    # general partitions
+    (dict(blocks=(2, 1)), -1),                       # sizes sum to 3, not d = 4
+    (dict(blocks=(4, 0)), -1),                       # an empty block
+    (dict(blocks=(1, 1, 1, 1), order=(0, 1, 1, 3)), -1),  # order repeats a coordinate
+    (dict(order=(0, 1, 2, 4)), -1),                  # order leaves 0..d-1
+    (dict(blocks=(1,) * 300, d=300, precision=0), -2),  # more than 256 blocks
+    (dict(blocks=(5, 1), d=6, N=1024), -2),          # N^(largest block) = 2^50 > 2^40
 ]
 
 

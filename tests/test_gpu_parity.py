@@ -48,15 +48,16 @@ def _params(cfg, k_max, precision=None):
                        tau=(cfg["tau"] or 0.0), eta=cfg["eta"], max_rounds=cfg.get("max_rounds", 64),
                        precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64,
                        robust=int(cfg["robust"]), verify=int(cfg["verify"]),
-                       verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]))
+                       verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]),
+                       blocks=cfg["blocks"], order=cfg["order"])
 
 
 def _oracle_params(cfg, k):
     return oracle.Params(d=cfg["d"], N=cfg["N"], k=int(k), d1=cfg["d1"], c=cfg["c"],
                          ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
                          p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
-                         verify_eta=cfg["verify_eta"],
-                         max_rounds=cfg.get("max_rounds", 64))
+                         verify_eta=cfg["verify_eta"], blocks=cfg["blocks"],
+                         order=cfg["order"], max_rounds=cfg.get("max_rounds", 64))
 
 
 # ------------------------------------------------------------ sampler -------
@@ -78,6 +79,10 @@ SAMPLER_CASES = [
     ("e1_fp64_d100", "e1", {}, 64, 331, 7, 16, 2),
     # d = 1000: 200 unwrapped coordinates, 201 sets, sampled on the last axis
     ("e2_fp64_d1000", "e2", {}, 32, 163, 200, 8, 2),
+    # general partitions: blocks of 3 and 4 over a shuffled order (FP64), blocks
+    # (2, 1, 1) over a shuffled order (FP32)
+    ("e3_fp64_uneven", "e3", {}, 100, 503, 5, 20, 2),
+    ("c2_fp32_uneven", "c2", {"blocks": (2, 1, 1), "order_seed": 2001}, 128, 641, 1, 20, 2),
 ]
 
 
@@ -98,10 +103,10 @@ def test_sampler_matches_oracle(name, cname, over, k, p, m, nres, B):
     res_y, res_a, res_off = [], [], [0]
     for b in range(B):
         w, a = pb.signal(b)
-        y = oracle.unwrap(w, P.d1, P.N)
+        y = oracle.unwrap(w, P.d1, P.N, P.blocks, P.order)
         sel = rng.choice(k, size=min(nres, k), replace=False)
         ys = y[sel].copy()
-        ys[::2, 0] = np.clip(ys[::2, 0] + 1, *oracle.y_range(P.N, P.d1))
+        ys[::2, 0] = np.clip(ys[::2, 0] + 1, *oracle.y_range(P.N, P.block_sizes[0]))
         res_y.append(ys)
         res_a.append(a[sel] * 0.9)
         res_off.append(res_off[-1] + len(sel))
@@ -214,6 +219,15 @@ RECOVER_CASES = [
     # and at d = 1000 (200 unwrapped coordinates, 201 sets per round)
     ("e2_fp64_d1000", "e2", {}, 2, 16, 1e-8),
     ("e2_fp64_d1000_k64", "e2", {}, 2, 64, 1e-8),
+    # general partitions (uneven blocks, shuffled coordinate order)
+    ("e3_fp64_uneven_order", "e3", {}, 2, 100, 1e-9),
+    ("c1_fp64_order", "c1", {"order_seed": 1001}, 8, 8, 1e-9),
+    # (N = 64: with the largest block at N^2 = 4096, tau = eps = 1.2e-4 is within FP32's
+    # reach; at N = 1024 eps = 4.8e-7 is below the FP32 spectra's rounding and the
+    # ratio test sends buckets the FP64 oracle accepts to later rounds)
+    ("c2_fp32_uneven_order", "c2", {"N": 64, "blocks": (2, 1, 1), "order_seed": 2001},
+     2, 256, 1e-5),
+    ("c3_fp32_order", "c3b", {"order_seed": 3101}, 3, 150, 1e-5),
     ("c2_fp32", "c2", {}, 2, 256, 1e-5),
     ("c2_fp32_single_mode", "c2", {}, 3, 1, 1e-5),
     ("c3_fp32_noisy_small", "c3b", {}, 3, 150, 1e-5),
@@ -375,6 +389,7 @@ def test_autotune_log_and_winner():
     assert [e["c"] for e in log[:3]] == [2.5, 3.0, 40.0]
     assert log[2]["status"] == sfft.SFFT_ERANGE       # 40 * 300 > the largest prime
     assert len(log) >= 3 + 1 + 4 + 2 + 2 + 3 + 3
+    assert all(e["sched_fft"] in (1, 2) for e in log)  # the schedule as run
     ok = [e for e in log if e["status"] == 0]
     best_exact = max(e["exact"] for e in ok)
     assert best_exact == B
