@@ -32,7 +32,8 @@ from .philox import sample_noise
 from .primes import ith_prime_at_least
 from .signal import evaluate, sample_points
 from .classifier import bf16_round, bucket_features, bucket_label, prob_single
-from .unwrapping import partition, unwrap, unwrap_matrix, wrap, y_range
+from .unwrapping import (partition, pythagorean_tilt, tilt_back, tilt_forward, tilt_range,
+                         unwrap, unwrap_matrix, wrap, y_range)
 
 READINGS = {
     "R1": "Phaseshift listing labels the shifted and unshifted sample vectors the other "
@@ -86,6 +87,14 @@ READINGS = {
            "block's first position; one shift eps = 1/(2 N^max d_q) on every axis, below the "
            "inverse of the largest block bandwidth as the paper chooses (not one eps per "
            "block); the band check of R16 uses each coordinate's own block size.",
+    "R23": "2D tilting (Section 3.3, Theorem 1): for d = 2 the whole recovery runs on lines "
+           "t = U t~, U = [[b, a], [-a, b]] (eq. (27): rotation by sin = a/c, cos = b/c scaled "
+           "by c), y = U^T w, and w = U y / c^2 at the end (the listing's rotation back, "
+           "exact in integers).  (a, b, c) is a Pythagorean triple with b > 2N and "
+           "gcd(a, b) = 1; unless given, the one with the smallest bandwidth a + b.  "
+           "eps = 1/(2 NB), NB = (a + b) N / 2 bounds every rotated coordinate.  A decoded "
+           "y is no mode unless U y is divisible by c^2 with the quotient in [-N/2, N/2)^2 "
+           "(the rotated form of R16).",
 }
 
 STATUS_OK = 0
@@ -101,6 +110,7 @@ class Params:
     d1: int = 1
     blocks: tuple | None = None        # R22: block sizes (sum d); None = uniform d1
     order: tuple | None = None         # R22: coordinate order; None = natural
+    tilt: object = None                # R23 (d = 2): None, True (triple of Theorem 1) or (a, b, c)
     c: float = 5.0
     ladder_K: int = 1
     tau: float | None = None
@@ -123,13 +133,62 @@ class Params:
         return partition(self.d, self.d1, self.blocks, self.order)[0]
 
     @property
+    def tilt_abc(self):
+        """(a, b, c) of the rotation (R23), or None."""
+        if self.tilt is None or self.tilt is False:
+            return None
+        if self.tilt is True:
+            return pythagorean_tilt(int(self.N))
+        return tuple(int(v) for v in self.tilt)
+
+    @property
     def d2(self) -> int:
-        return len(self.block_sizes)
+        return 2 if self.tilt_abc else len(self.block_sizes)
 
     @property
     def NB(self) -> int:
-        """Largest bandwidth of an unwrapped coordinate, N^d1 (R22: N^max d_q)."""
+        """Largest bandwidth of an unwrapped coordinate, N^d1 (R22: N^max d_q; R23:
+        (a + b) N / 2, which bounds every rotated coordinate)."""
+        t = self.tilt_abc
+        if t:
+            return (t[0] + t[1]) * int(self.N) // 2
         return int(self.N) ** max(self.block_sizes)
+
+    def line_matrix(self) -> np.ndarray:
+        """U of the sampling lines, t = U t~ (eq. (36); eq. (27) when tilted)."""
+        return unwrap_matrix(self.d, self.d1, self.N, self.blocks, self.order, self.tilt_abc)
+
+    def to_lines(self, w) -> np.ndarray:
+        """y = U^T w."""
+        t = self.tilt_abc
+        if t:
+            return tilt_forward(w, t[0], t[1])
+        return unwrap(w, self.d1, self.N, self.blocks, self.order)
+
+    def from_lines(self, y) -> np.ndarray:
+        """w from y (the inverse of to_lines on its image)."""
+        t = self.tilt_abc
+        if t:
+            w, ok = tilt_back(y, t[0], t[1], t[2], int(self.N))
+            if not np.all(ok):
+                raise ValueError("value outside the rotated image")
+            return w
+        return wrap(y, self.d1, self.N, self.blocks, self.order)
+
+    def bands(self) -> list:
+        """Inclusive range of each unwrapped coordinate (R16)."""
+        t = self.tilt_abc
+        if t:
+            return tilt_range(int(self.N), t[0], t[1])
+        return [y_range(self.N, dn) for dn in self.block_sizes]
+
+    def in_image(self, y) -> bool:
+        """Whether y = U^T w for some w in [-N/2, N/2)^d (R16, R23)."""
+        t = self.tilt_abc
+        if t:
+            return bool(tilt_back(np.asarray(y, np.int64)[None, :], t[0], t[1], t[2],
+                                  int(self.N))[1][0])
+        return all(lo <= int(v) <= hi for v, (lo, hi) in zip(y, self.bands()))
 
     @property
     def eps(self) -> float:
@@ -144,6 +203,14 @@ class Params:
         if self.d < 1:
             raise ValueError("d must be positive")
         partition(self.d, self.d1, self.blocks, self.order)  # raises on a bad partition
+        t = self.tilt_abc
+        if t:
+            a, b, c = t
+            if self.d != 2 or self.blocks is not None or self.order is not None or self.d1 != 1:
+                raise ValueError("tilting is defined for d = 2 without unwrapping")
+            if not (1 <= a < b < c and a * a + b * b == c * c and math.gcd(a, b) == 1
+                    and b > 2 * self.N):
+                raise ValueError("the tilt must be a Pythagorean triple with b > 2N, gcd(a, b) = 1")
         if self.N < 2 or self.N % 2:
             raise ValueError("N must be even and >= 2")
         if self.k < 1 or self.c <= 1.0 or self.ladder_K < 1:
@@ -199,8 +266,7 @@ def verify_samples(freqs, coeffs, P: Params, p: int, q: int, i: int, yR, aR,
     """R14: residual samples f(t_h) + noise - g(t_h) on the tilted line
     t_h = (h/p) U v, v_n = q^(n-1) mod p, h = 0..p-1 (noise of set 0, round i)."""
     v = np.array([pow(int(q), n, int(p)) for n in range(P.d2)], dtype=np.int64)
-    direction = (unwrap_matrix(P.d, P.d1, P.N, P.blocks, P.order).astype(np.float64)
-                 @ v.astype(np.float64))
+    direction = P.line_matrix().astype(np.float64) @ v.astype(np.float64)
     h = np.arange(p)
     t = (h.astype(np.float64) / p)[:, None] * direction[None, :]
     out = evaluate(freqs, coeffs, t) + sample_noise(seed, signal, i, 0, h, sigma)
@@ -243,10 +309,8 @@ def _decode(F, h, p, m, P: Params):
             if P.robust and abs(yc_real - yn) > NB / (4.0 * K):
                 valid = False
         y[n - 1] = yn
-    for n, dn in enumerate(P.block_sizes):     # R16: out-of-band decodes are no mode
-        lo, hi = y_range(P.N, dn)
-        if y[n] < lo or y[n] > hi:
-            valid = False
+    if not P.in_image(y):                      # R16 (R23: and the rotated lattice)
+        valid = False
     if P.robust and (int(y[m - 1]) % p) != h:  # R17
         valid = False
     return y, valid
@@ -278,7 +342,7 @@ def round_samples(freqs, coeffs, P: Params, p: int, m: int, i: int, yR, aR,
     V = []
     for s, (n, K) in enumerate([(1, 0)] + tab):
         shift = P.eps * K
-        t = sample_points(d, d1, N, p, m, n, shift, P.blocks, P.order)[h]
+        t = sample_points(d, d1, N, p, m, n, shift, P.blocks, P.order, P.tilt_abc)[h]
         v = evaluate(freqs, coeffs, t)
         v = v + sample_noise(seed, signal, i, s, h, sigma)
         if len(aR):                                        # adaptive subtraction of g
@@ -299,7 +363,7 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
     freqs = np.asarray(freqs, dtype=np.int64)
     coeffs = np.asarray(coeffs, dtype=np.complex128)
     d, d1, d2, N = P.d, P.d1, P.d2, P.N
-    y_planted = unwrap(freqs, d1, N, P.blocks, P.order) if collect is not None else None
+    y_planted = P.to_lines(freqs) if collect is not None else None
     tab = shift_table(d2, P.ladder_K)
     R: dict = {}
     trace, spectra, registry = [], [], []
@@ -380,7 +444,7 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
     if R:
         ys = np.array(list(R.keys()), dtype=np.int64).reshape(-1, d2)
         a = np.array(list(R.values()), dtype=np.complex128)
-        w = wrap(ys, d1, N, P.blocks, P.order)
+        w = P.from_lines(ys)
         order = np.lexsort(w.T[::-1])
         w, a, ys = w[order], a[order], ys[order]
     else:

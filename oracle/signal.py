@@ -26,16 +26,17 @@ def evaluate(freqs: np.ndarray, coeffs: np.ndarray, t: np.ndarray,
 
 
 def sample_points(d: int, d1: int, N: int, p: int, m: int, shift_axis: int,
-                  shift: float, blocks=None, order=None) -> np.ndarray:
+                  shift: float, blocks=None, order=None, tilt=None) -> np.ndarray:
     """Points of one sampling line, float64 [p, d].
 
     t_h = (h/p) U e_m + shift U e_n  for h = 0..p-1 (eq. (41) with the partial
     unwrapping of eq. (36)); m and n = shift_axis are 1-based unwrapped axes,
     shift = 0 gives the unshifted line.  0-based h with h/p is the reading of
     eq. (2); the listings' (h-1)/p for h = 1..p is the same set of points.
-    blocks / order: a general partition (see unwrap_matrix).
+    blocks / order: a general partition; tilt: the rotation of Section 3.3 (see
+    unwrap_matrix).
     """
-    U = unwrap_matrix(d, d1, N, blocks, order).astype(np.float64)
+    U = unwrap_matrix(d, d1, N, blocks, order, tilt).astype(np.float64)
     h = np.arange(p, dtype=np.float64)[:, None]
     t = (h / p) * U[:, m - 1][None, :]
     if shift != 0.0:

@@ -26,6 +26,8 @@ the bound |y| < 1/(2 eps).  The oracle follows eq. (35).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -47,8 +49,12 @@ def partition(d: int, d1: int, blocks=None, order=None):
     return blocks, order, tuple(starts)
 
 
-def unwrap_matrix(d: int, d1: int, N: int, blocks=None, order=None) -> np.ndarray:
-    """U in Z^{d x d2} with U[pi(s_q + r), q] = N^r, so that y = U^T w."""
+def unwrap_matrix(d: int, d1: int, N: int, blocks=None, order=None,
+                  tilt=None) -> np.ndarray:
+    """U in Z^{d x d2} with U[pi(s_q + r), q] = N^r, so that y = U^T w; with
+    tilt = (a, b, c) (d = 2) the scaled rotation of eq. (27)."""
+    if tilt is not None:
+        return tilt_matrix(tilt[0], tilt[1])
     blocks, order, starts = partition(d, d1, blocks, order)
     U = np.zeros((d, len(blocks)), dtype=object)
     for q, dq in enumerate(blocks):
@@ -95,3 +101,65 @@ def y_range(N: int, d1: int) -> tuple[int, int]:
     [-(N/2) S, (N/2 - 1) S], S = sum N^r."""
     S = sum(int(N) ** r for r in range(d1))
     return -(N // 2) * S, (N // 2 - 1) * S
+
+
+# ---- 2D tilting (Section 3.3, eqs. (21), (25), (27), Theorem 1) -------------------------
+#
+# The frequency plane is rotated by theta with sin theta = a/c, cos theta = b/c, (a, b, c)
+# a Pythagorean triple, and scaled by c so that the rotated frequencies stay integers:
+# the sampling lines run in coordinates t = U t~ with U = [[b, a], [-a, b]] (eq. (27)),
+# so that y = U^T w = (b w_1 - a w_2, a w_1 + b w_2).  U U^T = c^2 I, hence
+# w = U y / c^2 exactly (the listing's rotation back).  By Theorem 1, with b > 2N and
+# gcd(a, b) = 1, no two frequencies of [-N/2, N/2)^2 share either rotated coordinate.
+
+
+def pythagorean_tilt(N: int) -> tuple[int, int, int]:
+    """The triple (a, b, c) with a^2 + b^2 = c^2, c > b > a >= 1, gcd(a, b) = 1 and
+    b > 2N (Theorem 1) whose bandwidth a + b is smallest (ties: smaller b).
+
+    Primitive triples are (m^2 - n^2, 2 m n, m^2 + n^2) with m > n >= 1 coprime and of
+    opposite parity (Euclid); a + b >= m^2 > 8N beyond m = sqrt(8N) + 1, while the
+    triple of n = ceil(sqrt(N)), m = n + 1 already has a + b <= 8N, so the search stops
+    there."""
+    best = None
+    m_max = int(math.isqrt(8 * int(N))) + 2
+    for m in range(2, m_max + 1):
+        for n in range(1, m):
+            if (m - n) % 2 == 0 or math.gcd(m, n) != 1:
+                continue
+            u, v, c = m * m - n * n, 2 * m * n, m * m + n * n
+            for a, b in ((u, v), (v, u)):
+                if b > 2 * N and a < b:
+                    key = (a + b, b)
+                    if best is None or key < best[0]:
+                        best = (key, (a, b, c))
+    return best[1]
+
+
+def tilt_matrix(a: int, b: int) -> np.ndarray:
+    """U of eq. (27) (scaled rotation), t = U t~: U = [[b, a], [-a, b]]."""
+    return np.array([[b, a], [-a, b]], dtype=object)
+
+
+def tilt_forward(w: np.ndarray, a: int, b: int) -> np.ndarray:
+    """y = U^T w = (b w_1 - a w_2, a w_1 + b w_2) (eq. (21) times c)."""
+    w = np.asarray(w, dtype=np.int64)
+    return np.stack([b * w[:, 0] - a * w[:, 1], a * w[:, 0] + b * w[:, 1]], axis=1)
+
+
+def tilt_back(y: np.ndarray, a: int, b: int, c: int, N: int):
+    """w = U y / c^2, and whether each row is an image of [-N/2, N/2)^2 (divisible by
+    c^2, inside the box)."""
+    y = np.asarray(y, dtype=np.int64)
+    u = np.stack([b * y[:, 0] + a * y[:, 1], -a * y[:, 0] + b * y[:, 1]], axis=1)
+    c2 = int(c) * int(c)
+    ok = np.all(u % c2 == 0, axis=1)
+    w = u // c2
+    ok &= np.all((w >= -(N // 2)) & (w < N // 2), axis=1)
+    return w, ok
+
+
+def tilt_range(N: int, a: int, b: int) -> list[tuple[int, int]]:
+    """Inclusive range of each rotated coordinate over w in [-N/2, N/2)^2."""
+    lo_w, hi_w = -(N // 2), N // 2 - 1
+    return [(b * lo_w - a * hi_w, b * hi_w - a * lo_w), ((a + b) * lo_w, (a + b) * hi_w)]

@@ -84,6 +84,58 @@ def test_unwrap_general_by_hand():
             oracle.Params(d=20, N=20, k=1, **bad).validate()
 
 
+@pytest.mark.parametrize("N", [4, 8, 16, 20, 64])
+def test_pythagorean_tilt_is_smallest(N):
+    # brute force over all integer legs: the plan's triple satisfies Theorem 1 (b > 2N,
+    # gcd(a, b) = 1, c > b > a) with the smallest bandwidth a + b
+    best = None
+    for b in range(2 * N + 1, 8 * N + 1):
+        for a in range(1, b):
+            c2 = a * a + b * b
+            c = math.isqrt(c2)
+            if c * c == c2 and math.gcd(a, b) == 1:
+                key = (a + b, b)
+                if best is None or key < best[0]:
+                    best = (key, (a, b, c))
+    assert uw.pythagorean_tilt(N) == best[1]
+
+
+def test_tilt_theorem_no_collisions():
+    # Theorem 1, exhaustively at N = 16: no two frequencies share a rotated coordinate,
+    # the rotation back is exact, and the bands are the extremes of the image
+    N = 16
+    a, b, c = uw.pythagorean_tilt(N)
+    g = np.arange(-N // 2, N // 2)
+    w = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2).astype(np.int64)
+    y = uw.tilt_forward(w, a, b)
+    assert len(np.unique(y[:, 0])) == N * N and len(np.unique(y[:, 1])) == N * N
+    back, ok = uw.tilt_back(y, a, b, c, N)
+    assert ok.all() and np.array_equal(back, w)
+    for shift in ((1, 0), (0, 1), (c, 0)):
+        assert not uw.tilt_back(y + np.array(shift), a, b, c, N)[1].any()
+    for q, (lo, hi) in enumerate(uw.tilt_range(N, a, b)):
+        assert y[:, q].min() == lo and y[:, q].max() == hi
+    # the condition b > 2N matters: the (3, 4, 5) rotation leaves collisions at N = 16
+    y345 = uw.tilt_forward(w, 3, 4)
+    assert len(np.unique(y345[:, 0])) < N * N
+    # y = U^T w with U of eq. (27): (b w_1 - a w_2, a w_1 + b w_2), by hand for one point
+    assert uw.tilt_forward(np.array([[2, -3]]), a, b).tolist() == [[2 * b + 3 * a, 2 * a - 3 * b]]
+
+
+def test_tilt_phase_identity():
+    # f on the lines t = U t~ equals the signal with frequencies y = U^T w in t~ (eq. (27))
+    rng = np.random.default_rng(5)
+    N = 64
+    a, b, c = uw.pythagorean_tilt(N)
+    w = rng.integers(-N // 2, N // 2, size=(6, 2))
+    amp = rng.normal(size=6) + 1j * rng.normal(size=6)
+    tt = rng.uniform(-1, 1, size=(10, 2))
+    U = uw.tilt_matrix(a, b).astype(float)
+    lhs = oracle.evaluate(w, amp, tt @ U.T)
+    rhs = oracle.evaluate(uw.tilt_forward(w, a, b), amp, tt)
+    assert np.abs(lhs - rhs).max() < 1e-9
+
+
 def test_unwrap_paper_example():
     ex = GOLD["worked_example"]
     lo, hi = uw.y_range(ex["N"], ex["d1"])

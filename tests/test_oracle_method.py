@@ -128,6 +128,35 @@ def test_bruteforce_full_grid_uneven(d, N, blocks, order, k, seed):
     assert np.abs(r.coeffs - fa).max() < 1e-9
 
 
+@pytest.mark.parametrize("N,k,seed", [(16, 6, 31), (8, 5, 33)])
+def test_bruteforce_full_grid_tilted(N, k, seed):
+    # the tilted recovery (R23) finds what the 2-dim DFT of the full grid finds
+    w, a = workloads.planted_signal(seed, 0, 2, N, k)
+    fw, fa = _bruteforce_spectrum(w, a, 2, N)
+    r = oracle.multiphaseshift(w, a, oracle.Params(d=2, N=N, k=k, tilt=True))
+    assert r.status == 0
+    assert np.array_equal(r.freqs, fw)
+    assert np.abs(r.coeffs - fa).max() < 1e-9
+
+
+@pytest.mark.parametrize("N,r", [(64, 4), (64, 6), (1024, 5)])
+def test_worst_case_rectangles_need_tilting(N, r):
+    # Section 3.3: frequencies on the vertices of axis-aligned rectangles collide on every
+    # parallel projection, so the untilted method recovers nothing; tilted with the
+    # triple of Theorem 1 it recovers all of them
+    pb = workloads.rectangle_batch(7000 + N + r, 3, N, r)
+    for b in range(pb.B):
+        w, a = pb.signal(b)
+        o = np.lexsort(w.T[::-1])
+        plain = oracle.multiphaseshift(w, a, oracle.Params(d=2, N=N, k=r * r, max_rounds=8))
+        assert plain.status == 1 and plain.freqs.shape[0] == 0
+        P = oracle.Params(d=2, N=N, k=r * r, tilt=True)
+        res = oracle.multiphaseshift(w, a, P)
+        assert res.status == 0
+        assert np.array_equal(res.freqs, w[o])
+        assert np.abs(res.coeffs - a[o]).max() < 1e-9
+
+
 # coefficient tolerance: 1e-9, and 1e-8 for the d = 100 and 1000 recipes, where the oracle
 # evaluates exp(2 pi i w . t) at arguments of up to N^d1 / 2 = 1.6e6 cycles in FP64
 # (a phase error of about 1e-9 rad per term)
@@ -214,6 +243,7 @@ def _pins_hold(monkeypatch=None):
         test_single_mode_round_one(2, 64, 1)
         test_bruteforce_full_grid(2, 64, 2, 8, 1001)
         test_bruteforce_full_grid_uneven(3, 16, (2, 1), (2, 0, 1), 6, 21)
+        test_bruteforce_full_grid_tilted(16, 6, 31)
     except AssertionError:
         return False
     return True
@@ -225,7 +255,8 @@ def test_pins_hold_unmutated():
 
 @pytest.mark.parametrize("mutation", ["dft_sign", "unwrap_power", "no_residual",
                                       "shift_axis", "coef_scale", "arg_sign", "round_floor",
-                                      "wrap_natural_order", "block_digits_reversed"])
+                                      "wrap_natural_order", "block_digits_reversed",
+                                      "tilt_back_transposed", "tilt_sample_unrotated"])
 def test_planted_mistakes_are_caught(monkeypatch, mutation):
     if mutation == "dft_sign":
         monkeypatch.setattr(mps_mod, "dft", lambda v: np.fft.ifft(v) * v.shape[-1])
@@ -256,11 +287,21 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         # R22 misread: the last coordinate of a block is the least significant digit
         orig = sig_mod.unwrap_matrix
 
-        def rev(d, d1, N, blocks=None, order=None):
+        def rev(d, d1, N, blocks=None, order=None, tilt=None):
             b, o, s = uw.partition(d, d1, blocks, order)
             o2 = sum((tuple(reversed(o[s[q]:s[q + 1]])) for q in range(len(b))), ())
-            return orig(d, d1, N, blocks, o2)
+            return orig(d, d1, N, blocks, o2, tilt)
         monkeypatch.setattr(sig_mod, "unwrap_matrix", rev)
+    elif mutation == "tilt_back_transposed":
+        # R23 misread: rotated back with U^T instead of U
+        monkeypatch.setattr(mps_mod, "tilt_back",
+                            lambda y, a, b, c, N: uw.tilt_back(y, -a, b, c, N))
+    elif mutation == "tilt_sample_unrotated":
+        # R23 misread: the samples taken on the unrotated axes
+        orig = sig_mod.unwrap_matrix
+        monkeypatch.setattr(sig_mod, "unwrap_matrix",
+                            lambda d, d1, N, blocks=None, order=None, tilt=None:
+                            orig(d, d1, N, blocks, order, None))
     assert not _pins_hold()
 
 

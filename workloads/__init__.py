@@ -6,7 +6,8 @@ experiments and of the measured configurations.  It holds none of the sparse
 Fourier method's arithmetic, so both the CPU oracle and the HIP path may take
 their inputs from it.
 """
-from .planted import PlantedBatch, planted_batch, planted_signal
+from .planted import PlantedBatch, planted_batch, planted_signal, rectangle_batch
 from .configs import CONFIGS, config
 
-__all__ = ["PlantedBatch", "planted_batch", "planted_signal", "CONFIGS", "config"]
+__all__ = ["PlantedBatch", "planted_batch", "planted_signal", "rectangle_batch", "CONFIGS",
+           "config"]

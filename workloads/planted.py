@@ -108,3 +108,31 @@ def uneven_k(seed: int, B: int, lo: int, hi: int) -> np.ndarray:
 def uniform_sigma(seed: int, B: int, lo: float, hi: float) -> np.ndarray:
     rng = np.random.default_rng([int(seed), 0x5D])
     return rng.uniform(lo, hi, size=B)
+
+
+def rectangle_batch(seed: int, B: int, N: int, r: int, mag=(1.0, 2.0),
+                    sigma=0.0) -> PlantedBatch:
+    """B two-dimensional signals whose k = r^2 frequencies are the grid X x Y of r
+    distinct first and r distinct second coordinates (Section 3.3's worst case:
+    every frequency is a vertex of axis-aligned rectangles, so each one shares its
+    projection onto either axis with r - 1 others)."""
+    if r < 1 or r > N:
+        raise ValueError("bad grid size")
+    sig = np.broadcast_to(np.asarray(sigma, dtype=np.float64), (B,)).copy()
+    fs, cs = [], []
+    off = np.zeros(B + 1, dtype=np.int64)
+    half = N // 2
+    for b in range(B):
+        rng = np.random.default_rng([int(seed), int(b), 0x7E])
+        xs = rng.choice(np.arange(-half, half), size=r, replace=False)
+        ys = rng.choice(np.arange(-half, half), size=r, replace=False)
+        w = np.stack(np.meshgrid(xs, ys, indexing="ij"), axis=-1).reshape(-1, 2).astype(np.int64)
+        lo, hi = mag
+        rad = rng.uniform(lo, hi, size=r * r) if hi > lo else np.full(r * r, float(lo))
+        a = rad * np.exp(2j * np.pi * rng.uniform(0.0, 1.0, size=r * r))
+        fs.append(w)
+        cs.append(a.astype(np.complex128))
+        off[b + 1] = off[b] + r * r
+    return PlantedBatch(freqs=np.ascontiguousarray(np.concatenate(fs)),
+                        coeffs=np.concatenate(cs), mode_off=off,
+                        k=np.full(B, r * r, np.int32), sigma=sig, seed=int(seed), d=2, N=N)
