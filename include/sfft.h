@@ -136,6 +136,18 @@ typedef struct {
                               blocks of d1                                           */
   int32_t n_blocks;        /* 1..256 with `blocks` (this is d2); 0 without           */
   const int32_t* order;    /* a permutation of 0..d-1; NULL: 0, 1, ..., d-1          */
+  /* 2D tilting (Section 3.3, eq. (27), Theorem 1), for d = 2 with d1 = 1 and no
+   * blocks or order: the recovery runs on lines t = U t~, U = [[b, a], [-a, b]]
+   * (the rotation by sin = a/c, cos = b/c, scaled by c), so y = U^T w, and each
+   * answer is rotated back exactly, w = U y / c^2.  A decoded y is no mode unless
+   * U y is divisible by c^2 with the quotient in [-N/2, N/2)^2.  One shift
+   * eps = 1 / ((a + b) N) serves both axes.  With b > 2N and gcd(a, b) = 1 no two
+   * frequencies share a rotated coordinate, which recovers frequencies on the
+   * vertices of axis-aligned rectangles (every parallel projection collides). */
+  int32_t tilt;            /* 0: off.  1: on                                         */
+  int32_t tilt_a, tilt_b, tilt_c; /* the triple: a^2 + b^2 = c^2, 1 <= a < b, b > 2N,
+                              gcd(a, b) = 1; all 0: the plan takes the triple with
+                              the smallest a + b (then the smallest b)               */
 } sfft_params;
 
 /* A batch of synthetic black-box signals with planted spectra.  All pointers

@@ -106,6 +106,53 @@ static sfft_status resolve_partition(const sfft_params* p, std::vector<int32_t>*
   return SFFT_OK;
 }
 
+static int64_t gcd64(int64_t x, int64_t y) {
+  while (y) {
+    const int64_t t = x % y;
+    x = y;
+    y = t;
+  }
+  return x < 0 ? -x : x;
+}
+
+// The rotation of 2D tilting: the caller's triple, or the Pythagorean triple
+// (a, b, c) with b > 2N and gcd(a, b) = 1 of least a + b (then least b).  Every
+// primitive triple is {m^2 - n^2, 2mn} with hypotenuse m^2 + n^2 (m > n >= 1
+// coprime, m - n odd).  A triple with m > sqrt(8N) + 1 has a + b >= m^2 > 8N,
+// more than that of n = ceil(sqrt N), m = n + 1, so the search stops there.
+static sfft_status resolve_tilt(const sfft_params* p, int64_t* a, int64_t* b, int64_t* c) {
+  if (p->tilt_a || p->tilt_b || p->tilt_c) {
+    *a = p->tilt_a;
+    *b = p->tilt_b;
+    *c = p->tilt_c;
+    if (!(*a >= 1 && *a < *b && *b < *c && (*a) * (*a) + (*b) * (*b) == (*c) * (*c)))
+      return fail(SFFT_EINVAL, "tilt (%lld, %lld, %lld) is not a triple with 1 <= a < b < c",
+                  (long long)*a, (long long)*b, (long long)*c);
+    if (gcd64(*a, *b) != 1 || *b <= 2 * p->N)
+      return fail(SFFT_EINVAL, "tilt needs gcd(a, b) = 1 and b > 2N");
+    return SFFT_OK;
+  }
+  int64_t best_sum = -1;
+  const int64_t m_max = (int64_t)std::sqrt(8.0 * (double)p->N) + 2;
+  for (int64_t m = 2; m <= m_max; ++m)
+    for (int64_t n = 1; n < m; ++n) {
+      if ((m - n) % 2 == 0 || gcd64(m, n) != 1) continue;
+      const int64_t legs[2] = {m * m - n * n, 2 * m * n};
+      for (int o = 0; o < 2; ++o) {
+        const int64_t x = legs[o], y = legs[1 - o];  // candidate a = x, b = y
+        if (y > 2 * p->N && x < y &&
+            (best_sum < 0 || x + y < best_sum || (x + y == best_sum && y < *b))) {
+          best_sum = x + y;
+          *a = x;
+          *b = y;
+          *c = m * m + n * n;
+        }
+      }
+    }
+  if (best_sum < 0) return fail(SFFT_ERANGE, "no tilt found");
+  return SFFT_OK;
+}
+
 static sfft_status validate_params(const sfft_params* p) {
   if (!p) return fail(SFFT_EINVAL, "params is NULL");
   std::vector<int32_t> blocks, order;
@@ -115,6 +162,18 @@ static sfft_status validate_params(const sfft_params* p) {
   if (p->N < 2 || p->N % 2 != 0) return fail(SFFT_EINVAL, "N must be even and >= 2");
   double nb = 1.0;
   for (int r = 0; r < dmax; ++r) nb *= (double)p->N;
+  if (p->tilt != 0 && p->tilt != 1) return fail(SFFT_EINVAL, "tilt must be 0 or 1");
+  if (p->tilt) {
+    if (p->d != 2 || p->d1 != 1 || p->blocks || p->order)
+      return fail(SFFT_EINVAL, "tilting needs d = 2, d1 = 1 and no blocks or order");
+    if (p->N > (1 << 24)) return fail(SFFT_ERANGE, "N too large for tilting");
+    int64_t ta = 0, tb = 0, tc = 0;
+    const sfft_status ts = resolve_tilt(p, &ta, &tb, &tc);
+    if (ts != SFFT_OK) return ts;
+    nb = (double)(ta + tb) * (double)p->N / 2.0;
+  } else if (p->tilt_a || p->tilt_b || p->tilt_c) {
+    return fail(SFFT_EINVAL, "tilt_a/b/c without tilt");
+  }
   if (nb > 1099511627776.0) return fail(SFFT_ERANGE, "N^d1 exceeds 2^40");
   if (p->k_max < 1) return fail(SFFT_EINVAL, "k_max must be >= 1");
   if (!(p->c > 1.0) || !std::isfinite(p->c)) return fail(SFFT_EINVAL, "c must be > 1");
@@ -187,6 +246,15 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.N = P.N;
   kp.NB = 1;
   for (int r = 0; r < kp.d1; ++r) kp.NB *= P.N;
+  int64_t ta = 0, tb = 0, tc = 0;
+  if (P.tilt) {
+    resolve_tilt(params, &ta, &tb, &tc);  // checked by validate_params
+    kp.tilt = 1;
+    kp.ta = ta;
+    kp.tb = tb;
+    kp.tc2 = tc * tc;
+    kp.NB = (ta + tb) * P.N / 2;  // every |y| <= NB, the top one below it
+  }
   kp.k_max = P.k_max;
   // registry capacity: k_max, plus the repair slack of the verification round
   kp.cap = P.k_max + (P.verify ? std::max(16, (P.k_max + 7) / 8) : 0);
@@ -338,10 +406,11 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   plan->max_batch = max_batch;
 
   const size_t ws_bytes = (size_t)kp.n_slots * kp.ws_slot;
-  // partition tables: block starts [d2 + 1], coordinate order [d], band sums [d2]
+  // partition tables: block starts [d2 + 1], coordinate order [d], bands [d2][2]
   std::vector<int32_t> blk(kp.d2 + 1, 0);
-  std::vector<int64_t> band_s(kp.d2, 0);
+  std::vector<int64_t> band(2 * (size_t)kp.d2, 0);
   bool natural = true;
+  const int64_t wlo = -(P.N / 2), whi = P.N / 2 - 1;
   for (int q = 0; q < kp.d2; ++q) {
     blk[q + 1] = blk[q] + blocks[q];
     int64_t s = 0, pw = 1;
@@ -349,15 +418,24 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
       s += pw;
       pw *= P.N;
     }
-    band_s[q] = s;
+    band[2 * q] = wlo * s;
+    band[2 * q + 1] = whi * s;
     if (blocks[q] != 1) natural = false;
   }
   for (int l = 0; l < P.d; ++l)
     if (order[l] != l) natural = false;
+  if (kp.tilt) {
+    // y0 = b w0 - a w1, y1 = a w0 + b w1 over w in [wlo, whi]^2
+    band[0] = tb * wlo - ta * whi;
+    band[1] = tb * whi - ta * wlo;
+    band[2] = (ta + tb) * wlo;
+    band[3] = (ta + tb) * whi;
+    natural = false;
+  }
   kp.wrap_rank = natural ? 0 : 1;
   const size_t part_blk = 0, part_perm = al256(4 * (size_t)(kp.d2 + 1));
   const size_t part_band = part_perm + al256(4 * (size_t)P.d);
-  const size_t part_bytes = part_band + 8 * (size_t)kp.d2;
+  const size_t part_bytes = part_band + 16 * (size_t)kp.d2;
   if ((e = hipMalloc((void**)&plan->d_primes, primes.size() * sizeof(int32_t))) != hipSuccess ||
       (e = hipMalloc((void**)&plan->d_part, part_bytes)) != hipSuccess ||
       (e = hipMalloc((void**)&plan->d_ws, ws_bytes)) != hipSuccess ||
@@ -372,7 +450,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(plan->d_part + part_perm, order.data(), order.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(plan->d_part + part_band, band_s.data(), band_s.size() * sizeof(int64_t),
+      (e = hipMemcpy(plan->d_part + part_band, band.data(), band.size() * sizeof(int64_t),
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(plan->d_ws, 0, ws_bytes)) != hipSuccess ||
       (e = hipMemset(plan->d_queue, 0, 256)) != hipSuccess) {
@@ -388,7 +466,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.n_primes = (int)primes.size();
   kp.blk = reinterpret_cast<const int32_t*>(plan->d_part + part_blk);
   kp.perm = reinterpret_cast<const int32_t*>(plan->d_part + part_perm);
-  kp.band_s = reinterpret_cast<const int64_t*>(plan->d_part + part_band);
+  kp.band = reinterpret_cast<const int64_t*>(plan->d_part + part_band);
   kp.ws = plan->d_ws;
   kp.queue = plan->d_queue;
   plan->kp = kp;

@@ -105,11 +105,15 @@ struct KParams {
   int sched_dft_batch;    // FP32: most sets per batched Bluestein pass (0: all that fit)
   // Partition of the d coordinates into d2 blocks (device tables): block q holds
   // coordinates perm[blk[q]] .. perm[blk[q+1] - 1], the first the least
-  // significant base-N digit; band_s[q] = sum_{r < d_q} N^r bounds its band.
+  // significant base-N digit; y_q lies in [band[2q], band[2q+1]].
   const int32_t* blk;     // [d2 + 1] block starts
   const int32_t* perm;    // [d] coordinate order
-  const int64_t* band_s;  // [d2]
+  const int64_t* band;    // [d2][2] inclusive band of each coordinate
   int wrap_rank;          // lexicographic order of w differs from that of y
+  // 2D tilting: y = (tb w0 - ta w1, ta w0 + tb w1), w = (tb y0 + ta y1,
+  // -ta y0 + tb y1) / tc2 (tilt = 0: the partition above)
+  int tilt;
+  int64_t ta, tb, tc2;
 };
 
 struct KBatch {

@@ -128,7 +128,8 @@ struct WgState {
 // --------------------------------------------------- per-signal set-up -----
 // Planted modes: y = U^T w (eq. (35); block q of a general partition holds the
 // coordinates perm[blk[q]] .. perm[blk[q+1] - 1], the first the least
-// significant base-N digit) and the coefficient rows
+// significant base-N digit; tilted: the rotation of eq. (27), y = U^T w with
+// U = [[b, a], [-a, b]]) and the coefficient rows
 // C[j][0] = a_j, C[j][s] = a_j exp(2 pi i eps K_s y_{j,n_s}).
 template <typename T>
 __device__ void planted_setup(const KParams& kp, const KBatch& kb, char* slot, WgState& st) {
@@ -137,13 +138,18 @@ __device__ void planted_setup(const KParams& kp, const KBatch& kb, char* slot, W
   const int d = kp.d, d2 = kp.d2, S1 = kp.S1;
   for (int j = threadIdx.x; j < st.M_pl; j += kWG) {
     const int64_t* w = kb.freqs + (st.off + j) * d;
-    for (int q = 0; q < d2; ++q) {
-      int64_t y = 0, pw = 1;
-      for (int l = kp.blk[q]; l < kp.blk[q + 1]; ++l) {
-        y += w[kp.perm[l]] * pw;
-        pw *= kp.N;
+    if (kp.tilt) {
+      ypl[(size_t)j * 2] = kp.tb * w[0] - kp.ta * w[1];
+      ypl[(size_t)j * 2 + 1] = kp.ta * w[0] + kp.tb * w[1];
+    } else {
+      for (int q = 0; q < d2; ++q) {
+        int64_t y = 0, pw = 1;
+        for (int l = kp.blk[q]; l < kp.blk[q + 1]; ++l) {
+          y += w[kp.perm[l]] * pw;
+          pw *= kp.N;
+        }
+        ypl[(size_t)j * d2 + q] = y;
       }
-      ypl[(size_t)j * d2 + q] = y;
     }
     const cpx<double> a = cmk<double>(kb.coeffs[2 * (st.off + j)], kb.coeffs[2 * (st.off + j) + 1]);
     cc[(size_t)j * S1] = cmk<T>((T)a.x, (T)a.y);
@@ -764,8 +770,7 @@ __device__ void decode_round(const KParams& kp, const KOut& ko, char* slot, WgSt
   const int p = st.p, d2 = kp.d2, S = kp.S;
   const int64_t NB = kp.NB;
   const double NBd = (double)NB;
-  // band of coordinate n: [-(N/2) S_n, (N/2 - 1) S_n], S_n = band_s[n]
-  const int64_t nlo = -(kp.N / 2), nhi = kp.N / 2 - 1;
+  // coordinate n lies in [band[2n], band[2n+1]]
   for (int c = threadIdx.x; c < st.ncand; c += kWG) {
     const int h = cand[c];
     const double f0x = (double)V[h].x, f0y = (double)V[h].y;
@@ -791,9 +796,18 @@ __device__ void decode_round(const KParams& kp, const KOut& ko, char* slot, WgSt
         yn = yn + llround(delta * NBd / (M_PI * (double)K));
         if (kp.robust && fabs(yc_real - (double)yn) > NBd / (4.0 * (double)K)) valid = false;
       }
-      const int64_t Sn = kp.band_s[n];
-      if (yn < nlo * Sn || yn > nhi * Sn) valid = false;
+      if (yn < kp.band[2 * n] || yn > kp.band[2 * n + 1]) valid = false;
       y[n] = yn;
+    }
+    if (kp.tilt && valid) {
+      // tilted: y must be U^T w for an integer w in the box (U y divisible by c^2)
+      const int64_t u0 = kp.tb * y[0] + kp.ta * y[1], u1 = kp.tb * y[1] - kp.ta * y[0];
+      if (u0 % kp.tc2 != 0 || u1 % kp.tc2 != 0) {
+        valid = false;
+      } else {
+        const int64_t w0 = u0 / kp.tc2, w1 = u1 / kp.tc2;
+        if (w0 < -(kp.N / 2) || w0 >= kp.N / 2 || w1 < -(kp.N / 2) || w1 >= kp.N / 2) valid = false;
+      }
     }
     if (kp.robust && pmod64(y[st.m0], p) != h) valid = false;
     bool ok;
@@ -1186,7 +1200,13 @@ __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgSt
   const int nOut = min(nR, kp.k_max);
   const int64_t half = kp.N / 2;
   // entries in registry order first (lexicographic in y)
-  for (int e = threadIdx.x; e < nOut; e += kWG) {
+  for (int e = threadIdx.x; e < nOut && kp.tilt; e += kWG) {
+    // rotation back, w = U y / c^2 (exact: decode admits only such y)
+    const int64_t y0 = ry[(size_t)ord[e] * 2], y1 = ry[(size_t)ord[e] * 2 + 1];
+    fo[(size_t)e * 2] = (kp.tb * y0 + kp.ta * y1) / kp.tc2;
+    fo[(size_t)e * 2 + 1] = (kp.tb * y1 - kp.ta * y0) / kp.tc2;
+  }
+  for (int e = threadIdx.x; e < nOut && !kp.tilt; e += kWG) {
     for (int q = 0; q < d2; ++q) {
       int64_t rest = ry[(size_t)ord[e] * d2 + q];
       for (int l = kp.blk[q]; l < kp.blk[q + 1]; ++l) {

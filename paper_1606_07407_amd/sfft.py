@@ -54,6 +54,8 @@ class sfft_params(ctypes.Structure):
         ("blocks", ctypes.POINTER(ctypes.c_int32)),
         ("n_blocks", ctypes.c_int32),
         ("order", ctypes.POINTER(ctypes.c_int32)),
+        ("tilt", ctypes.c_int32),
+        ("tilt_a", ctypes.c_int32), ("tilt_b", ctypes.c_int32), ("tilt_c", ctypes.c_int32),
     ]
 
 
@@ -186,6 +188,8 @@ class Params:
     sched_dft_batch: int = 0
     blocks: tuple | None = None     # general partition: block sizes (sum d); None = d1
     order: tuple | None = None      # coordinate order (a permutation of 0..d-1)
+    tilt: int = 0                   # 1: 2D tilting (d = 2); tilt_abc (0, 0, 0) = plan's triple
+    tilt_abc: tuple = (0, 0, 0)
 
     def to_c(self) -> sfft_params:
         c = sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
@@ -203,6 +207,8 @@ class Params:
         if self.order is not None:
             c._order = (ctypes.c_int32 * len(self.order))(*[int(v) for v in self.order])
             c.order = ctypes.cast(c._order, ctypes.POINTER(ctypes.c_int32))
+        c.tilt = int(self.tilt)
+        c.tilt_a, c.tilt_b, c.tilt_c = (int(v) for v in self.tilt_abc)
         return c
 
 

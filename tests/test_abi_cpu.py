@@ -84,6 +84,14 @@ BAD = [
     (dict(order=(0, 1, 2, 4)), -1),                  # order leaves 0..d-1
     (dict(blocks=(1,) * 300, d=300, precision=0), -2),  # more than 256 blocks
     (dict(blocks=(5, 1), d=6, N=1024), -2),          # N^(largest block) = 2^50 > 2^40
+    # 2D tilting
+    (dict(d=2, N=64, tilt=1, d1=2), -1),             # tilting needs d1 = 1
+    (dict(d=3, N=64, tilt=1), -1),                   # and d = 2
+    (dict(d=2, N=64, tilt=1, tilt_abc=(3, 4, 5)), -1),      # b = 4 is not > 2N
+    (dict(d=2, N=64, tilt=1, tilt_abc=(20, 129, 131)), -1), # not a triple
+    (dict(d=2, N=64, tilt=1, tilt_abc=(34, 288, 290)), -1), # gcd(a, b) = 2
+    (dict(d=2, N=64, tilt_abc=(17, 144, 145)), -1),  # a triple without tilt
+    (dict(d=2, N=64, tilt=2), -1),
 ]
 
 

@@ -49,7 +49,9 @@ def _params(cfg, k_max, precision=None):
                        precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64,
                        robust=int(cfg["robust"]), verify=int(cfg["verify"]),
                        verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]),
-                       blocks=cfg["blocks"], order=cfg["order"])
+                       blocks=cfg["blocks"], order=cfg["order"], tilt=1 if cfg["tilt"] else 0,
+                       tilt_abc=(tuple(cfg["tilt"]) if isinstance(cfg["tilt"], tuple)
+                                 else (0, 0, 0)))
 
 
 def _oracle_params(cfg, k):
@@ -57,7 +59,8 @@ def _oracle_params(cfg, k):
                          ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
                          p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
                          verify_eta=cfg["verify_eta"], blocks=cfg["blocks"],
-                         order=cfg["order"], max_rounds=cfg.get("max_rounds", 64))
+                         order=cfg["order"], tilt=cfg["tilt"],
+                         max_rounds=cfg.get("max_rounds", 64))
 
 
 # ------------------------------------------------------------ sampler -------
@@ -83,6 +86,9 @@ SAMPLER_CASES = [
     # (2, 1, 1) over a shuffled order (FP32)
     ("e3_fp64_uneven", "e3", {}, 100, 503, 5, 20, 2),
     ("c2_fp32_uneven", "c2", {"blocks": (2, 1, 1), "order_seed": 2001}, 128, 641, 1, 20, 2),
+    # 2D tilting: the rotated lines of Section 3.3
+    ("c1_fp64_tilt", "c1", {"tilt": True}, 8, 41, 2, 3, 2),
+    ("c1_fp32_tilt", "c1", {"tilt": True, "precision": "fp32"}, 8, 41, 1, 3, 2),
 ]
 
 
@@ -103,10 +109,10 @@ def test_sampler_matches_oracle(name, cname, over, k, p, m, nres, B):
     res_y, res_a, res_off = [], [], [0]
     for b in range(B):
         w, a = pb.signal(b)
-        y = oracle.unwrap(w, P.d1, P.N, P.blocks, P.order)
+        y = P.to_lines(w)
         sel = rng.choice(k, size=min(nres, k), replace=False)
         ys = y[sel].copy()
-        ys[::2, 0] = np.clip(ys[::2, 0] + 1, *oracle.y_range(P.N, P.block_sizes[0]))
+        ys[::2, 0] = np.clip(ys[::2, 0] + 1, *P.bands()[0])
         res_y.append(ys)
         res_a.append(a[sel] * 0.9)
         res_off.append(res_off[-1] + len(sel))
@@ -228,6 +234,10 @@ RECOVER_CASES = [
     ("c2_fp32_uneven_order", "c2", {"N": 64, "blocks": (2, 1, 1), "order_seed": 2001},
      2, 256, 1e-5),
     ("c3_fp32_order", "c3b", {"order_seed": 3101}, 3, 150, 1e-5),
+    # 2D tilting (Theorem 1's triple; and a caller's triple); FP32 at tau = eps = 1/((a+b) N)
+    ("c1_fp64_tilt", "c1", {"tilt": True}, 8, 8, 1e-9),
+    ("c1_fp64_tilt_given", "c1", {"tilt": (33, 544, 545)}, 4, 8, 1e-9),
+    ("c1_fp32_tilt", "c1", {"tilt": True, "precision": "fp32", "tau": None}, 8, 8, 1e-5),
     ("c2_fp32", "c2", {}, 2, 256, 1e-5),
     ("c2_fp32_single_mode", "c2", {}, 3, 1, 1e-5),
     ("c3_fp32_noisy_small", "c3b", {}, 3, 150, 1e-5),
@@ -269,6 +279,31 @@ def test_recover_matches_oracle(name, cname, over, B, k, tol):
     rel = _compare(cfg, pb, h, tol)
     _say(f"    statuses {h['status'].tolist()} rounds {h['rounds'].tolist()} max rel {rel:.2e}")
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_worst_case_rectangles(prec):
+    """Section 3.3's worst case: frequencies on the vertices of axis-aligned rectangles
+    (a 5 x 5 grid per signal).  Untilted, every parallel projection collides and, as in
+    the oracle, nothing is recovered; tilted with Theorem 1's triple, every signal
+    matches the oracle, round by round."""
+    sfft = _sfft()
+    N, r, B = 64, 5, 6
+    pb = workloads.rectangle_batch(7100, B, N, r)
+    tol = 1e-9 if prec == "fp64" else 1e-5
+    for tilt in (None, True):
+        cfg = workloads.config("c1", k=r * r, precision=prec, max_rounds=8, tilt=tilt,
+                               tau=1e-6 if prec == "fp64" else None)
+        _say(f"[worst case] {prec} tilt={tilt} B={B} k={r * r}")
+        plan = sfft.sfft_plan_create(_params(cfg, r * r), max_batch=B)
+        h = sfft.outputs_to_host(sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb)))
+        _compare(cfg, pb, h, tol)
+        if tilt:
+            assert np.all(h["status"] == sfft.SFFT_OK)
+        else:
+            assert np.all(h["status"] == sfft.SFFT_NOT_CONVERGED) and not np.any(h["k_found"])
+        _say(f"    statuses {h['status'].tolist()} rounds {h['rounds'].tolist()}")
+        plan.close()
 
 
 @pytest.mark.parametrize("cname,k,prec", [("c3b", 60, "fp32"), ("c1", 8, "fp64")])

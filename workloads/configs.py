@@ -22,7 +22,8 @@ measured single-GPU configurations:
 
 blocks / order_seed describe a general partition: block sizes (sum d; None:
 uniform blocks of d1) and the seed of a random coordinate order (None: the
-natural order), drawn here as a permutation of 0..d-1.
+natural order), drawn here as a permutation of 0..d-1.  tilt (d = 2): True for
+the rotated lines of Section 3.3 with the plan's triple, or a triple (a, b, c).
 """
 from __future__ import annotations
 
@@ -72,7 +73,8 @@ CONFIGS = {
 
 def config(name: str, **over):
     """A copy of the named recipe with fields overridden by keyword."""
-    cfg = dict(verify=False, verify_eta=None, residual=0, blocks=None, order_seed=None)
+    cfg = dict(verify=False, verify_eta=None, residual=0, blocks=None, order_seed=None,
+               tilt=None)
     cfg.update(copy.deepcopy(CONFIGS[name]))
     cfg.update(over)
     cfg["name"] = name
