@@ -238,6 +238,48 @@ sfft_status sfft_sample_lines(sfft_plan plan, const sfft_signal_batch* batch, in
  * plan's precision, device), in place.  Any p in [2, plan's largest prime]. */
 sfft_status sfft_dft(sfft_plan plan, void* data, int32_t count, int32_t p, void* stream);
 
+/* Caller-supplied samples (signals the library cannot evaluate: the paper's
+ * black-box f of eq. (32)).  A session runs the rounds of Section 5.0 one at a
+ * time: sfft_session_request names the line each signal needs next, the caller
+ * evaluates f on it, sfft_session_feed runs the rest of the round (DFT, registry
+ * subtraction in the spectra, selection, decode and merge), and
+ * sfft_session_finish writes the answers as sfft_recover does.  Every call is
+ * asynchronous on `stream`.  The plan must have verify = 0 and
+ * residual = SFFT_RESIDUAL_SPECTRUM (else SFFT_EINVAL) and must outlive the
+ * session; one session is used on one stream at a time.  The session allocates
+ * B workspace slots of the plan's size (hipMalloc in create, freed in destroy). */
+typedef struct sfft_session_s* sfft_session;
+
+/* k: [B] sparsities (device int32, 1..k_max; others end with SFFT_EINVAL). */
+sfft_status sfft_session_create(sfft_plan plan, int32_t B, const int32_t* k, void* stream,
+                                sfft_session* out);
+sfft_status sfft_session_destroy(sfft_session session);
+
+/* The lines of the next round (device int32 [B] each): p[b] the prime (0 once
+ * signal b is finished), m[b] the unwrapped axis (1..d2).  The samples are
+ * f(t) at t_h = (h/p) U e_m + eps K_s U e_{n_s}, h = 0..p-1, for the sets
+ * s = 0..S (eqs. (36), (41)): set 0 unshifted, s = 1..d2 shifted by eps along
+ * n_s = s, and with ladder_K > 1 also s = d2+1..2 d2 shifted by K eps along
+ * n_s = s - d2; U is the plan's unwrapping (eq. (35), its partition, or the
+ * rotation of 2D tilting), eps = 1 / (2 NB) with NB the largest bandwidth of an
+ * unwrapped coordinate. */
+sfft_status sfft_session_request(sfft_session session, int32_t* p, int32_t* m, void* stream);
+
+/* Convenience: the points of the requested lines, t[b][s][h][0..d) doubles
+ * (device, [B][S+1][max_prime][d]; rows h >= p[b] and finished signals are not
+ * written). */
+sfft_status sfft_session_points(sfft_session session, double* t, void* stream);
+
+/* The samples of the requested lines, complex of the plan's precision (float2
+ * or double2), device, [B][S+1][max_prime] (h < p[b] read; finished signals
+ * ignored).  Runs one round of every unfinished signal. */
+sfft_status sfft_session_feed(sfft_session session, const void* samples, void* stream);
+
+/* Outputs as for sfft_recover (feature export and phase timestamps are not
+ * offered: those fields must be NULL).  rounds and samples count the fed
+ * rounds; a signal still unfinished ends with SFFT_NOT_CONVERGED. */
+sfft_status sfft_session_finish(sfft_session session, const sfft_outputs* out, void* stream);
+
 /* Learned classifier kernels.  `w` points to SFFT_MLP_PARAMS BF16 values
  * (device); x holds n feature rows of SFFT_MLP_FEATURES floats (device), which
  * are rounded to BF16 on input; y holds n labels in {0, 1}.

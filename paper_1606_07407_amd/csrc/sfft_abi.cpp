@@ -568,6 +568,125 @@ sfft_status sfft_sample_lines(sfft_plan plan, const sfft_signal_batch* batch, in
   return SFFT_OK;
 }
 
+struct sfft_session_s {
+  KParams kp;     // the plan's, with ws = the session's workspace
+  KSess ss;
+  char* d_ws = nullptr;
+  char* d_state = nullptr;
+  int32_t* d_req = nullptr;    // p [B] then m [B]
+  int32_t* d_trace = nullptr;
+};
+
+sfft_status sfft_session_destroy(sfft_session s) {
+  if (!s) return SFFT_OK;
+  (void)hipDeviceSynchronize();
+  if (s->d_ws) (void)hipFree(s->d_ws);
+  if (s->d_state) (void)hipFree(s->d_state);
+  if (s->d_req) (void)hipFree(s->d_req);
+  if (s->d_trace) (void)hipFree(s->d_trace);
+  delete s;
+  return SFFT_OK;
+}
+
+sfft_status sfft_session_create(sfft_plan plan, int32_t B, const int32_t* k, void* stream,
+                                sfft_session* out) {
+  g_err[0] = 0;
+  if (!out) return fail(SFFT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!plan) return fail(SFFT_EINVAL, "plan is NULL");
+  if (B < 1) return fail(SFFT_EINVAL, "B must be >= 1");
+  if (!k) return fail(SFFT_EINVAL, "k is NULL");
+  if (plan->kp.verify || plan->kp.residual != SFFT_RESIDUAL_SPECTRUM)
+    return fail(SFFT_EINVAL, "sessions need verify = 0 and the residual subtracted in the spectra");
+  sfft_session s = new (std::nothrow) sfft_session_s();
+  if (!s) return fail(SFFT_ENOMEM, "host allocation failed");
+  s->kp = plan->kp;
+  const size_t ws = (size_t)B * s->kp.ws_slot;
+  const size_t state = (size_t)B * session_state_bytes();
+  const size_t trace = (size_t)B * s->kp.max_rounds * 8 * sizeof(int32_t);
+  hipError_t e;
+  if ((e = hipMalloc((void**)&s->d_ws, ws)) != hipSuccess ||
+      (e = hipMalloc((void**)&s->d_state, state)) != hipSuccess ||
+      (e = hipMalloc((void**)&s->d_req, 2 * (size_t)B * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc((void**)&s->d_trace, trace)) != hipSuccess) {
+    sfft_session_destroy(s);
+    return fail(SFFT_ENOMEM, "session allocation of %zu bytes failed: %s", ws + state + trace,
+                hipGetErrorString(e));
+  }
+  if ((e = hipMemset(s->d_ws, 0, ws)) != hipSuccess ||
+      (e = hipMemset(s->d_trace, 0, trace)) != hipSuccess) {
+    sfft_session_destroy(s);
+    return hip_fail(e, "session set-up");
+  }
+  s->kp.ws = s->d_ws;
+  s->ss.B = B;
+  s->ss.k = k;
+  s->ss.state = reinterpret_cast<WgState*>(s->d_state);
+  s->ss.req_p = s->d_req;
+  s->ss.req_m = s->d_req + B;
+  s->ss.trace = s->d_trace;
+  const int le = launch_session(s->kp, s->ss, 0, nullptr, nullptr, nullptr, stream);
+  if (le) {
+    sfft_session_destroy(s);
+    return hip_fail((hipError_t)le, "session init launch");
+  }
+  *out = s;
+  return SFFT_OK;
+}
+
+sfft_status sfft_session_request(sfft_session s, int32_t* p, int32_t* m, void* stream) {
+  g_err[0] = 0;
+  if (!s) return fail(SFFT_EINVAL, "session is NULL");
+  if (!p || !m) return fail(SFFT_EINVAL, "p and m are needed");
+  const size_t n = (size_t)s->ss.B * sizeof(int32_t);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(p, s->ss.req_p, n, hipMemcpyDeviceToDevice, (hipStream_t)stream)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(m, s->ss.req_m, n, hipMemcpyDeviceToDevice, (hipStream_t)stream)) !=
+          hipSuccess)
+    return hip_fail(e, "session request copy");
+  return SFFT_OK;
+}
+
+sfft_status sfft_session_points(sfft_session s, double* t, void* stream) {
+  g_err[0] = 0;
+  if (!s) return fail(SFFT_EINVAL, "session is NULL");
+  if (!t) return fail(SFFT_EINVAL, "t is NULL");
+  const int e = launch_session(s->kp, s->ss, 2, nullptr, t, nullptr, stream);
+  if (e) return hip_fail((hipError_t)e, "session points launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_session_feed(sfft_session s, const void* samples, void* stream) {
+  g_err[0] = 0;
+  if (!s) return fail(SFFT_EINVAL, "session is NULL");
+  if (!samples) return fail(SFFT_EINVAL, "samples is NULL");
+  const int e = launch_session(s->kp, s->ss, 1, samples, nullptr, nullptr, stream);
+  if (e) return hip_fail((hipError_t)e, "session feed launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_session_finish(sfft_session s, const sfft_outputs* out, void* stream) {
+  g_err[0] = 0;
+  if (!s) return fail(SFFT_EINVAL, "session is NULL");
+  if (!out || !out->freqs || !out->coeffs || !out->k_found || !out->status)
+    return fail(SFFT_EINVAL, "outputs need freqs, coeffs, k_found and status");
+  if (out->feat || out->label || out->feat_meta || out->feat_count || out->phase)
+    return fail(SFFT_EINVAL, "sessions offer no feature export or phase timestamps");
+  KOut ko;
+  memset(&ko, 0, sizeof(ko));
+  ko.freqs = out->freqs;
+  ko.coeffs = out->coeffs;
+  ko.k_found = out->k_found;
+  ko.status = out->status;
+  ko.rounds = out->rounds;
+  ko.samples = out->samples;
+  ko.trace = out->trace;
+  const int e = launch_session(s->kp, s->ss, 3, nullptr, nullptr, &ko, stream);
+  if (e) return hip_fail((hipError_t)e, "session finish launch");
+  return SFFT_OK;
+}
+
 sfft_status sfft_dft(sfft_plan plan, void* data, int32_t count, int32_t p, void* stream) {
   g_err[0] = 0;
   if (!plan) return fail(SFFT_EINVAL, "plan is NULL");

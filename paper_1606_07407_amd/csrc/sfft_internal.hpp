@@ -142,6 +142,17 @@ struct KOut {
   int64_t* phase;         // [B][max_rounds][8] wall-clock ticks per phase (NULL: off)
 };
 
+// A session of caller-supplied samples (device arrays owned by the session).
+struct WgState;
+struct KSess {
+  int B;
+  const int32_t* k;   // [B] sparsities
+  WgState* state;     // [B] round state between launches
+  int32_t* req_p;     // [B] prime of the requested round, 0 once finished
+  int32_t* req_m;     // [B] its unwrapped axis, 1-based
+  int32_t* trace;     // [B][max_rounds][8]
+};
+
 // Launchers (defined in the .hip file).  Return a hipError_t as int.
 int launch_zero_queue(const KParams& kp, int64_t* count, void* stream);
 int launch_mlp_forward(const void* w, const float* x, int64_t n, float* prob, void* stream);
@@ -160,5 +171,9 @@ int launch_sample_lines(const KParams& kp, const KBatch& kb, int round, int p, i
                         void* V, void* stream);
 int launch_dft(const KParams& kp, void* data, int count, int p, void* stream);
 int set_kernel_lds_limits(int lds_bytes);
+size_t session_state_bytes();
+// what: 0 init, 1 feed (samples), 2 points (t), 3 finish (ko)
+int launch_session(const KParams& kp, const KSess& ss, int what, const void* samples, double* t,
+                   const KOut* ko, void* stream);
 
 }  // namespace sfft

@@ -1422,6 +1422,179 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
   }
 }
 
+// ------------------------------------------ caller-supplied samples ------
+// A session recovers signals the library cannot evaluate itself: every round
+// is one launch, the caller samples f on the lines the session asks for, and
+// each signal's round state lives in global memory between launches.  The
+// steps after sampling are the recovery kernel's (DFT, registry subtraction in
+// the spectra, selection, decode, merge); the verification round is not
+// offered (it samples a different line).  One work-group per signal, slot b of
+// the session's workspace for signal b.
+
+// The next round of a signal (thread 0): st.p = 0 once it is finished.
+__device__ void session_next(const KParams& kp, WgState& st) {
+  st.p = 0;
+  if (st.flag) return;
+  if (st.nR >= st.k || st.i > kp.max_rounds) {
+    st.flag = 3;
+    return;
+  }
+  st.kstar = st.k - st.nR;
+  const int p = prime_for_round(kp, st.kstar, st.i);
+  st.m0 = st.i % kp.d2;
+  if (p < 2 || p > kp.p_max) {
+    st.status = -2;  // SFFT_ERANGE
+    st.flag = 3;
+    return;
+  }
+  int L = 1, lg = 0;
+  while (L < 2 * p - 1) {
+    L <<= 1;
+    ++lg;
+  }
+  st.p = p;
+  st.L = L;
+  st.log2L = lg;
+}
+
+__device__ __forceinline__ void session_publish(const KSess& ss, const WgState& st, int b) {
+  ss.req_p[b] = st.p;
+  ss.req_m[b] = st.m0 + 1;
+  ss.state[b] = st;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) session_init_kernel(KParams kp, KSess ss) {
+  __shared__ WgState st;
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) {
+    WgState z;
+    memset(&z, 0, sizeof(z));
+    z.sig = b;
+    z.k = ss.k[b];
+    z.i = 1;
+    if (z.k < 1 || z.k > kp.k_max) {
+      z.status = -1;  // SFFT_EINVAL
+      z.flag = 3;
+    }
+    st = z;
+    session_next(kp, st);
+    session_publish(ss, st, b);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+session_feed_kernel(KParams kp, KSess ss, const void* samples) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  __shared__ int sh_part[kWG];
+  const int b = blockIdx.x;
+  char* slot = kp.ws + (size_t)b * kp.ws_slot;
+  cpx<T>* V = ws_cpx<T>(slot, kp.lay.V);
+  const int vstride = kp.vstride;
+  if (threadIdx.x == 0) st = ss.state[b];
+  __syncthreads();
+  if (st.p == 0) return;  // finished (uniform over the work-group)
+  const int p = st.p;
+  const cpx<T>* src = reinterpret_cast<const cpx<T>*>(samples) + (size_t)b * kp.S1 * kp.p_max;
+  for (int q = threadIdx.x; q < kp.S1 * p; q += kWG) {
+    const int sidx = q / p, h = q - sidx * p;
+    V[(size_t)sidx * vstride + h] = src[(size_t)sidx * kp.p_max + h];
+  }
+  __syncthreads();
+  KOut ko;
+  memset(&ko, 0, sizeof(ko));
+  dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
+  subtract_registry<T>(kp, slot, st, lds, V, vstride, kp.S1, sh_part);
+  select_round<T>(kp, slot, st, lds, V, sh_part);
+  decode_round<T>(kp, ko, slot, st, V, vstride, lds, sh_part);
+  decode_finish(kp, st, lds, sh_part);
+  merge_round<T>(kp, slot, st, lds, sh_part, 0);
+  if (threadIdx.x == 0) {
+    st.samples += (int64_t)kp.S1 * st.p;
+    int32_t* tr = ss.trace + ((size_t)b * kp.max_rounds + (st.i - 1)) * 8;
+    tr[0] = st.i;
+    tr[1] = st.kstar;
+    tr[2] = st.p;
+    tr[3] = st.m0 + 1;
+    tr[4] = st.ncand;
+    tr[5] = st.nacc;
+    tr[6] = st.nR;
+    tr[7] = 0;
+    st.i += 1;
+    session_next(kp, st);
+    session_publish(ss, st, b);
+  }
+}
+
+// Points of the requested lines: t[b][s][h][l] = (h/p) U[l][m] + eps K_s U[l][n_s]
+// (eqs. (36), (41); U of the plan's partition, or of the tilt), h < p.
+__global__ void __launch_bounds__(kWG) session_points_kernel(KParams kp, KSess ss, double* t) {
+  // products and sums rounded one by one (no fused multiply-add), so that a
+  // point is the same double however the caller forms it from the formula
+#pragma clang fp contract(off)
+  const int b = blockIdx.x;
+  const int p = ss.req_p[b];
+  if (p == 0) return;
+  const int m0 = ss.req_m[b] - 1;
+  const int d = kp.d;
+  const double eps = 1.0 / (2.0 * (double)kp.NB);
+  for (int q = threadIdx.x; q < kp.S1 * p; q += kWG) {
+    const int sidx = q / p, h = q - sidx * p;
+    int n0 = 0;
+    int64_t K = 0;
+    if (sidx > 0) shift_of(kp, sidx, &n0, &K);
+    const double x = (double)h / (double)p, sh = eps * (double)K;
+    double* out = t + (((size_t)b * kp.S1 + sidx) * kp.p_max + h) * d;
+    for (int l = 0; l < d; ++l) out[l] = 0.0;
+    if (kp.tilt) {
+      // columns of U = [[b, a], [-a, b]]: (b, -a) and (a, b)
+      const double c0[2] = {(double)kp.tb, -(double)kp.ta}, c1[2] = {(double)kp.ta, (double)kp.tb};
+      const double* cm = m0 == 0 ? c0 : c1;
+      out[0] = x * cm[0];
+      out[1] = x * cm[1];
+      if (sidx > 0) {
+        const double* cn = n0 == 0 ? c0 : c1;
+        out[0] += sh * cn[0];
+        out[1] += sh * cn[1];
+      }
+    } else {
+      double pw = 1.0;
+      for (int l = kp.blk[m0]; l < kp.blk[m0 + 1]; ++l) {
+        out[kp.perm[l]] += x * pw;
+        pw *= (double)kp.N;
+      }
+      if (sidx > 0) {
+        pw = 1.0;
+        for (int l = kp.blk[n0]; l < kp.blk[n0 + 1]; ++l) {
+          out[kp.perm[l]] += sh * pw;
+          pw *= (double)kp.N;
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kWG) session_finish_kernel(KParams kp, KSess ss, KOut ko) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  const int b = blockIdx.x;
+  char* slot = kp.ws + (size_t)b * kp.ws_slot;
+  if (threadIdx.x == 0) {
+    st = ss.state[b];
+    if (st.status == 0) st.status = (st.nR < st.k) ? 1 : (st.nR > st.k) ? 2 : 0;
+  }
+  __syncthreads();
+  if (ko.trace) {
+    const int32_t* tr = ss.trace + (size_t)b * kp.max_rounds * 8;
+    int32_t* to = ko.trace + (size_t)b * kp.max_rounds * 8;
+    for (int e = threadIdx.x; e < (st.i - 1) * 8; e += kWG) to[e] = tr[e];
+  }
+  write_output(kp, ko, slot, st, lds);
+}
+
 // ----------------------------------------------- component: line sampler ----
 template <typename T, int RT>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) sample_kernel(KParams kp, KBatch kb, int round, int p,
@@ -1581,6 +1754,36 @@ int launch_dft(const KParams& kp, void* data, int count, int p, void* stream) {
   return (int)hipGetLastError();
 }
 
+size_t session_state_bytes() { return sizeof(WgState); }
+
+int launch_session(const KParams& kp, const KSess& ss, int what, const void* samples, double* t,
+                   const KOut* ko, void* stream) {
+  const dim3 grid(ss.B), block(kWG);
+  hipStream_t hs = (hipStream_t)stream;
+  const bool f32 = kp.precision == 1;
+  switch (what) {
+    case 0:
+      if (f32) hipLaunchKernelGGL(session_init_kernel<float>, grid, block, 0, hs, kp, ss);
+      else hipLaunchKernelGGL(session_init_kernel<double>, grid, block, 0, hs, kp, ss);
+      break;
+    case 1:
+      if (f32)
+        hipLaunchKernelGGL(session_feed_kernel<float>, grid, block, kp.lds_bytes, hs, kp, ss, samples);
+      else
+        hipLaunchKernelGGL(session_feed_kernel<double>, grid, block, kp.lds_bytes, hs, kp, ss, samples);
+      break;
+    case 2:
+      hipLaunchKernelGGL(session_points_kernel, grid, block, 0, hs, kp, ss, t);
+      break;
+    default:
+      if (f32)
+        hipLaunchKernelGGL(session_finish_kernel<float>, grid, block, kp.lds_bytes, hs, kp, ss, *ko);
+      else
+        hipLaunchKernelGGL(session_finish_kernel<double>, grid, block, kp.lds_bytes, hs, kp, ss, *ko);
+  }
+  return (int)hipGetLastError();
+}
+
 int set_kernel_lds_limits(int lds_bytes) {
   hipError_t e = hipSuccess;
   const void* fns[] = {
@@ -1593,7 +1796,9 @@ int set_kernel_lds_limits(int lds_bytes) {
       (const void*)sample_kernel<float, 4>,  (const void*)sample_kernel<float, 5>,
       (const void*)sample_kernel<float, 6>,  (const void*)sample_kernel<float, 7>,
       (const void*)sample_kernel<float, 8>,  (const void*)sample_kernel<double, 0>,
-      (const void*)dft_kernel<float>,        (const void*)dft_kernel<double>};
+      (const void*)dft_kernel<float>,        (const void*)dft_kernel<double>,
+      (const void*)session_feed_kernel<float>, (const void*)session_feed_kernel<double>,
+      (const void*)session_finish_kernel<float>, (const void*)session_finish_kernel<double>};
   for (const void* f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (r != hipSuccess) e = r;

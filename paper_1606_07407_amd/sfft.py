@@ -135,6 +135,18 @@ def lib() -> ctypes.CDLL:
                                     ctypes.POINTER(sfft_tune_entry), i32,
                                     ctypes.POINTER(i32), vp]
         L.sfft_autotune.restype = i32
+        L.sfft_session_create.argtypes = [vp, i32, vp, vp, ctypes.POINTER(vp)]
+        L.sfft_session_create.restype = i32
+        L.sfft_session_destroy.argtypes = [vp]
+        L.sfft_session_destroy.restype = i32
+        L.sfft_session_request.argtypes = [vp, vp, vp, vp]
+        L.sfft_session_request.restype = i32
+        L.sfft_session_points.argtypes = [vp, vp, vp]
+        L.sfft_session_points.restype = i32
+        L.sfft_session_feed.argtypes = [vp, vp, vp]
+        L.sfft_session_feed.restype = i32
+        L.sfft_session_finish.argtypes = [vp, ctypes.POINTER(sfft_outputs), vp]
+        L.sfft_session_finish.restype = i32
         _lib = L
     return _lib
 
@@ -342,6 +354,78 @@ def sfft_recover(plan: Plan, batch: DeviceBatch, out: dict | None = None, stream
     _check(lib().sfft_recover(plan.handle, ctypes.byref(b), ctypes.byref(o), _stream(stream)),
            "sfft_recover")
     return out
+
+
+class Session:
+    """Caller-supplied samples (the sfft_session_* calls of the C ABI): the caller
+    evaluates its signal on the lines each round asks for.
+
+        s = Session(plan, k)              # k: sparsity per signal
+        while True:
+            p, m = s.request()            # host arrays; p[b] == 0: signal b is done
+            if not p.any(): break
+            t = s.points()                # [B, S+1, max_prime, d] float64 on the device
+            s.feed(f(t))                  # complex [B, S+1, max_prime], the plan's precision
+        out = s.finish()                  # as sfft_recover
+    """
+
+    def __init__(self, plan: Plan, k, stream=None):
+        torch = _torch()
+        self.plan = plan
+        self.k = torch.as_tensor(k, dtype=torch.int32, device="cuda").reshape(-1).contiguous()
+        self.B = int(self.k.shape[0])
+        self.stream = stream
+        self._req = torch.zeros((2, self.B), dtype=torch.int32, device="cuda")
+        h = ctypes.c_void_p()
+        _check(lib().sfft_session_create(plan.handle, self.B, _ptr(self.k), _stream(stream),
+                                         ctypes.byref(h)), "sfft_session_create")
+        self.handle = h
+
+    def request(self):
+        _check(lib().sfft_session_request(self.handle, _ptr(self._req[0]), _ptr(self._req[1]),
+                                          _stream(self.stream)), "sfft_session_request")
+        r = self._req.cpu().numpy()
+        return r[0].copy(), r[1].copy()
+
+    def points(self, t=None):
+        torch = _torch()
+        P = self.plan.params
+        if t is None:
+            t = torch.zeros((self.B, self.plan.num_sets, self.plan.max_prime, P.d),
+                            dtype=torch.float64, device="cuda")
+        _check(lib().sfft_session_points(self.handle, _ptr(t), _stream(self.stream)),
+               "sfft_session_points")
+        return t
+
+    def feed(self, samples):
+        torch = _torch()
+        dt = torch.complex64 if self.plan.params.precision == SFFT_FP32 else torch.complex128
+        want = (self.B, self.plan.num_sets, self.plan.max_prime)
+        if tuple(samples.shape) != want or samples.dtype != dt or not samples.is_contiguous():
+            raise ValueError(f"samples must be a contiguous {dt} tensor of shape {want}")
+        _check(lib().sfft_session_feed(self.handle, _ptr(samples), _stream(self.stream)),
+               "sfft_session_feed")
+
+    def finish(self, out: dict | None = None) -> dict:
+        if out is None:
+            out = alloc_outputs(self.plan, self.B)
+        o = sfft_outputs(_ptr(out["freqs"]), _ptr(out["coeffs"]), _ptr(out["k_found"]),
+                         _ptr(out["status"]), _ptr(out.get("rounds")), _ptr(out.get("samples")),
+                         _ptr(out.get("trace")), None, None, None, None, 0, None)
+        _check(lib().sfft_session_finish(self.handle, ctypes.byref(o), _stream(self.stream)),
+               "sfft_session_finish")
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().sfft_session_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sfft_sample_lines(plan: Plan, batch: DeviceBatch, round_i: int, p: int, m: int,

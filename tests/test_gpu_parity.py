@@ -281,6 +281,92 @@ def test_recover_matches_oracle(name, cname, over, B, k, tol):
     plan.close()
 
 
+# ------------------------------------------------- caller-supplied samples -----
+
+def _black_box(pb, t, dtype):
+    """The caller's side: f(t) = sum_j a_j exp(2 pi i w_j . t) of each planted signal at
+    the points t [B, S+1, P, d] (float64), evaluated in FP64 on the device."""
+    import math
+    import torch
+    B, S1, P, d = t.shape
+    out = torch.zeros((B, S1, P), dtype=torch.complex128, device=t.device)
+    for b in range(B):
+        w, a = pb.signal(b)
+        W = torch.as_tensor(np.ascontiguousarray(w, np.float64), device=t.device)
+        A = torch.as_tensor(np.ascontiguousarray(a, np.complex128), device=t.device)
+        ph = t[b].reshape(-1, d) @ W.T.contiguous()
+        out[b] = (torch.exp((2j * math.pi) * ph) @ A).reshape(S1, P)
+    return out.to(dtype).contiguous()
+
+
+SESSION_CASES = [
+    # name, config, overrides, B, k, coefficient tolerance
+    ("c1_fp64", "c1", {}, 4, 8, 1e-9),
+    ("c1_fp64_round_cap", "c1", {"max_rounds": 1}, 4, 8, 1e-9),
+    ("e4_fp64", "e4", {}, 2, 100, 1e-8),
+    ("e3_fp64_uneven_order", "e3", {}, 2, 100, 1e-9),
+    ("c1_fp64_tilt", "c1", {"tilt": True}, 4, 8, 1e-9),
+    ("c2_fp32", "c2", {}, 2, 256, 1e-5),
+]
+
+
+@pytest.mark.parametrize("name,cname,over,B,k,tol", SESSION_CASES)
+def test_session_matches_oracle(name, cname, over, B, k, tol):
+    """Caller-supplied samples: the session asks for lines, the caller samples its own
+    black box on the points the session lays out, and the recovery equals the oracle's
+    (which samples the same signal itself), round by round."""
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config(cname, **over)
+    _say(f"[session] {name} B={B} k={k}")
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], k, cfg["mag"], 0.0)
+    plan = sfft.sfft_plan_create(_params(cfg, k), max_batch=B)
+    sess = sfft.Session(plan, np.full(B, k))
+    dt = torch.complex64 if cfg["precision"] == "fp32" else torch.complex128
+    fed = 0
+    while True:
+        p, m = sess.request()
+        if not p.any():
+            break
+        sess.feed(_black_box(pb, sess.points(), dt))
+        fed += 1
+        assert fed <= cfg.get("max_rounds", 64)
+    h = sfft.outputs_to_host(sess.finish())
+    torch.cuda.synchronize()
+    _compare(cfg, pb, h, tol)
+    _say(f"    fed {fed} rounds; statuses {h['status'].tolist()}")
+    sess.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("cname,over", [("e3", {}), ("c1", {"tilt": True}),
+                                        ("c3b", {"order_seed": 3101})])
+def test_session_points_match_oracle(cname, over):
+    """The points of the requested lines equal the oracle's sampling points bit for bit
+    (eqs. (36), (41): the same products and sums in the same order)."""
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config(cname, **over)
+    cfg.update(verify=False, residual=0)
+    k = 40
+    plan = sfft.sfft_plan_create(_params(cfg, k), max_batch=2)
+    sess = sfft.Session(plan, [k, k // 2])
+    p, m = sess.request()
+    t = sess.points().cpu().numpy()
+    P = _oracle_params(cfg, k)
+    tab = [(1, 0)] + oracle.shift_table(P.d2, P.ladder_K)
+    for b in range(2):
+        assert p[b] == oracle.ith_prime_at_least(max(math.ceil(P.c * (k if b == 0 else k // 2)),
+                                                     P.p_min), 1)
+        assert m[b] == (1 % P.d2) + 1
+        for s_i, (n, K) in enumerate(tab):
+            ref = oracle.sample_points(P.d, P.d1, P.N, int(p[b]), int(m[b]), n, P.eps * K,
+                                       P.blocks, P.order, P.tilt_abc)
+            assert np.array_equal(t[b, s_i, :p[b]], ref), (b, s_i)
+    sess.close()
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_worst_case_rectangles(prec):
     """Section 3.3's worst case: frequencies on the vertices of axis-aligned rectangles
