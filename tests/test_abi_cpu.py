@@ -106,6 +106,20 @@ def test_plan_create_rejects(over, status):
     assert len(sfft.sfft_last_error()) > 0
 
 
+def test_session_null_arguments():
+    sfft = _lib()
+    L = sfft.lib()
+    h = ctypes.c_void_p()
+    p = ctypes.c_void_p(0)
+    assert L.sfft_session_create(None, 1, p, None, ctypes.byref(h)) == sfft.SFFT_EINVAL
+    assert L.sfft_session_create(None, 1, p, None, None) == sfft.SFFT_EINVAL
+    assert L.sfft_session_request(None, p, p, None) == sfft.SFFT_EINVAL
+    assert L.sfft_session_points(None, p, None) == sfft.SFFT_EINVAL
+    assert L.sfft_session_feed(None, p, None) == sfft.SFFT_EINVAL
+    assert L.sfft_session_finish(None, None, None) == sfft.SFFT_EINVAL
+    assert L.sfft_session_destroy(None) == sfft.SFFT_OK
+
+
 def test_null_arguments():
     sfft = _lib()
     L = sfft.lib()
