@@ -12,7 +12,9 @@ per length-p DFT and the registry subtraction's terms, counted from the per-roun
 trace) against the FP32 matrix peak.  The plain classifier's entry also times
 the launch replayed from a captured HIP graph.  The CPU baseline is the FP64
 oracle on a bounded sample of the same signals.  --paper-sweep prints the
-paper's experiment over k (d = 100 and d = 1000) instead of the headline line.
+paper's experiment over k (d = 100 and d = 1000) instead of the headline line;
+--next measures 2D tilting, a general partition and a session of caller-supplied
+samples.
 """
 from __future__ import annotations
 
@@ -279,6 +281,106 @@ def paper_sweep(sfft, steps: int, warmup: int, name: str = "e1") -> list:
     return rows
 
 
+def params_of(sfft, cfg, k_max):
+    """Plan parameters of a workload recipe (every field the recipes set)."""
+    tilt = cfg.get("tilt")
+    return sfft.Params(d=cfg["d"], N=cfg["N"], k_max=k_max, d1=cfg["d1"], c=cfg["c"],
+                       p_min=cfg["p_min"], ladder_K=cfg["ladder_K"], tau=cfg["tau"] or 0.0,
+                       eta=cfg["eta"],
+                       precision=sfft.SFFT_FP32 if cfg["precision"] == "fp32" else sfft.SFFT_FP64,
+                       robust=int(cfg["robust"]), verify=int(cfg["verify"]),
+                       verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]),
+                       blocks=cfg.get("blocks"), order=cfg.get("order"),
+                       tilt=1 if tilt else 0,
+                       tilt_abc=tuple(tilt) if isinstance(tilt, tuple) else (0, 0, 0))
+
+
+def next_rows(sfft, steps: int, warmup: int) -> list:
+    """The widened paths, measured: 2D tilting on Section 3.3's worst case (512 signals,
+    each the 36 vertices of a 6 x 6 grid of axis-aligned rectangles, N = 64), the uneven
+    split of the worked example over a shuffled coordinate order (e3, 512 signals), and a
+    session of caller-supplied samples (e4-shaped, 64 signals; a torch FP64 black box
+    evaluates f, and the library's share -- points, feed and finish launches -- is timed
+    apart from it).  Recoveries/s count exact supports; HIP events on the launch stream."""
+    import math
+    import torch
+    rows = []
+    B = 512
+    for prec in ("fp64", "fp32"):
+        N, r = 64, 6
+        pb = workloads.rectangle_batch(7200, B, N, r)
+        cfg = workloads.config("c1", k=r * r, precision=prec, tilt=True,
+                               tau=1e-6 if prec == "fp64" else None)
+        plan = sfft.sfft_plan_create(params_of(sfft, cfg, r * r), max_batch=B)
+        db = sfft.DeviceBatch.from_planted(pb)
+        out, step_s, gpu_ms, per = time_recover(sfft, plan, db, B, steps, warmup)
+        ok = exact_support(pb, sfft.outputs_to_host(out))
+        rows.append(dict(path="2D tilting, worst-case rectangles", precision=prec, signals=B,
+                         k=r * r, N=N, success_rate=float(ok.mean()),
+                         value=int(ok.sum()) / (gpu_ms * 1e-3), unit="recoveries/s",
+                         launch_ms=gpu_ms))
+        plan.close()
+        print(f"[next] tilting {prec}: {rows[-1]['value']:.0f}/s", file=sys.stderr, flush=True)
+    cfg = workloads.config("e3")
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], cfg["k"], cfg["mag"], 0.0)
+    plan = sfft.sfft_plan_create(params_of(sfft, cfg, cfg["k"]), max_batch=B)
+    db = sfft.DeviceBatch.from_planted(pb)
+    out, step_s, gpu_ms, per = time_recover(sfft, plan, db, B, steps, warmup)
+    ok = exact_support(pb, sfft.outputs_to_host(out))
+    rows.append(dict(path="general partition (blocks 3,3,3,3,4,4, shuffled order)",
+                     precision="fp64", signals=B, k=cfg["k"], d=cfg["d"],
+                     success_rate=float(ok.mean()), value=int(ok.sum()) / (gpu_ms * 1e-3),
+                     unit="recoveries/s", launch_ms=gpu_ms))
+    plan.close()
+    print(f"[next] partition: {rows[-1]['value']:.0f}/s", file=sys.stderr, flush=True)
+    # session: the library's launches timed apart from the caller's evaluation of f
+    cfg = workloads.config("e4")
+    Bs = 64
+    pb = workloads.planted_batch(cfg["seed"], Bs, cfg["d"], cfg["N"], cfg["k"], cfg["mag"], 0.0)
+    plan = sfft.sfft_plan_create(params_of(sfft, cfg, cfg["k"]), max_batch=Bs)
+    stream = torch.cuda.current_stream()
+    W = [torch.as_tensor(np.ascontiguousarray(pb.signal(b)[0], np.float64), device="cuda")
+         for b in range(Bs)]
+    A = [torch.as_tensor(np.ascontiguousarray(pb.signal(b)[1], np.complex128), device="cuda")
+         for b in range(Bs)]
+    lib_ms, box_ms, fed = 0.0, 0.0, 0
+    sess = sfft.Session(plan, np.full(Bs, cfg["k"]), stream=stream)
+    while True:
+        p, m = sess.request()
+        if not p.any():
+            break
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
+        t = sess.points()
+        e[1].record(stream)
+        S1, P, d = t.shape[1], t.shape[2], t.shape[3]
+        f = torch.stack([(torch.exp((2j * math.pi) * (t[b].reshape(-1, d) @ W[b].T.contiguous()))
+                          @ A[b]).reshape(S1, P) for b in range(Bs)]).contiguous()
+        e[2].record(stream)
+        sess.feed(f)
+        e[3].record(stream)
+        torch.cuda.synchronize()
+        lib_ms += e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3])
+        box_ms += e[1].elapsed_time(e[2])
+        fed += 1
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    out = sess.finish()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lib_ms += e0.elapsed_time(e1)
+    ok = exact_support(pb, sfft.outputs_to_host(out))
+    rows.append(dict(path="session of caller-supplied samples (e4 shape)", precision="fp64",
+                     signals=Bs, k=cfg["k"], d=cfg["d"], rounds_fed=fed,
+                     success_rate=float(ok.mean()), library_ms=lib_ms, black_box_ms=box_ms,
+                     value=int(ok.sum()) / (lib_ms * 1e-3),
+                     unit="recoveries/s of library time (the caller's f excluded)"))
+    sess.close()
+    plan.close()
+    print(f"[next] session: {rows[-1]['value']:.0f}/s", file=sys.stderr, flush=True)
+    return rows
+
+
 def tolerance_curve(sfft, base, extra, kind, db, pb, B):
     """Success rate and recoveries/s over the decision threshold: tau for the plain
     ratio test, the probability threshold for the learned classifier."""
@@ -372,6 +474,9 @@ def main():
     ap.add_argument("--paper-sweep", action="store_true",
                     help="instead of the headline: the paper's d = 100 and 1000 sweeps "
                          "over k (FP64)")
+    ap.add_argument("--next", action="store_true",
+                    help="instead of the headline: tilting, a general partition and a session "
+                         "of caller-supplied samples")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuner (use --c / --sched or the recipe's values)")
     ap.add_argument("--c", type=float, default=None, help="c instead of the recipe's")
@@ -387,6 +492,15 @@ def main():
     import torch
     from paper_1606_07407_amd import classifier as cls
     from paper_1606_07407_amd import sfft
+
+    if args.next:
+        torch.cuda.set_device(0)
+        rows = next_rows(sfft, args.steps, args.warmup)
+        print(json.dumps({"metric": "recoveries/s of the widened paths", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "data": "synthetic planted spectra (seeded)", "rows": rows}),
+              flush=True)
+        return
 
     if args.paper_sweep:
         torch.cuda.set_device(0)
