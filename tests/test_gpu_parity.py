@@ -307,6 +307,8 @@ SESSION_CASES = [
     ("e3_fp64_uneven_order", "e3", {}, 2, 100, 1e-9),
     ("c1_fp64_tilt", "c1", {"tilt": True}, 4, 8, 1e-9),
     ("c2_fp32", "c2", {}, 2, 256, 1e-5),
+    # FP32 with the K eps ladder and the robust checks (noiseless, no verification round)
+    ("c3_fp32_ladder", "c3b", {"verify": False}, 2, 120, 1e-5),
 ]
 
 
