@@ -381,9 +381,16 @@ class Session:
                                          ctypes.byref(h)), "sfft_session_create")
         self.handle = h
 
+    def _after_current(self):
+        """Order the session's stream after torch's current one (tensors made there)."""
+        if self.stream is not None and hasattr(self.stream, "wait_stream"):
+            self.stream.wait_stream(_torch().cuda.current_stream())
+
     def request(self):
+        self._after_current()
         _check(lib().sfft_session_request(self.handle, _ptr(self._req[0]), _ptr(self._req[1]),
                                           _stream(self.stream)), "sfft_session_request")
+        (self.stream if self.stream is not None else _torch().cuda.current_stream()).synchronize()
         r = self._req.cpu().numpy()
         return r[0].copy(), r[1].copy()
 
@@ -393,6 +400,7 @@ class Session:
         if t is None:
             t = torch.zeros((self.B, self.plan.num_sets, self.plan.max_prime, P.d),
                             dtype=torch.float64, device="cuda")
+        self._after_current()
         _check(lib().sfft_session_points(self.handle, _ptr(t), _stream(self.stream)),
                "sfft_session_points")
         return t
@@ -403,6 +411,7 @@ class Session:
         want = (self.B, self.plan.num_sets, self.plan.max_prime)
         if tuple(samples.shape) != want or samples.dtype != dt or not samples.is_contiguous():
             raise ValueError(f"samples must be a contiguous {dt} tensor of shape {want}")
+        self._after_current()
         _check(lib().sfft_session_feed(self.handle, _ptr(samples), _stream(self.stream)),
                "sfft_session_feed")
 
@@ -412,6 +421,7 @@ class Session:
         o = sfft_outputs(_ptr(out["freqs"]), _ptr(out["coeffs"]), _ptr(out["k_found"]),
                          _ptr(out["status"]), _ptr(out.get("rounds")), _ptr(out.get("samples")),
                          _ptr(out.get("trace")), None, None, None, None, 0, None)
+        self._after_current()
         _check(lib().sfft_session_finish(self.handle, ctypes.byref(o), _stream(self.stream)),
                "sfft_session_finish")
         return out
