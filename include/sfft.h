@@ -244,9 +244,10 @@ sfft_status sfft_dft(sfft_plan plan, void* data, int32_t count, int32_t p, void*
  * evaluates f on it, sfft_session_feed runs the rest of the round (DFT, registry
  * subtraction in the spectra, selection, decode and merge), and
  * sfft_session_finish writes the answers as sfft_recover does.  Every call is
- * asynchronous on `stream`.  The plan must have verify = 0 and
- * residual = SFFT_RESIDUAL_SPECTRUM (else SFFT_EINVAL) and must outlive the
- * session; one session is used on one stream at a time.  The session allocates
+ * asynchronous on `stream`.  The plan must have residual =
+ * SFFT_RESIDUAL_SPECTRUM (else SFFT_EINVAL) and must outlive the session; one
+ * session is used on one stream at a time.  With verify = 1 the verification
+ * round asks for the tilted line of the plan's verification (m < 0 below).  The session allocates
  * B workspace slots of the plan's size (hipMalloc in create, freed in destroy). */
 typedef struct sfft_session_s* sfft_session;
 
@@ -256,7 +257,9 @@ sfft_status sfft_session_create(sfft_plan plan, int32_t B, const int32_t* k, voi
 sfft_status sfft_session_destroy(sfft_session session);
 
 /* The lines of the next round (device int32 [B] each): p[b] the prime (0 once
- * signal b is finished), m[b] the unwrapped axis (1..d2).  The samples are
+ * signal b is finished), m[b] the unwrapped axis (1..d2), or m[b] = -q for a
+ * verification round, whose one line is t_h = (h/p) U v with v_n = q^(n-1)
+ * mod p (n = 1..d2; only set 0 of the samples is read).  Otherwise the samples are
  * f(t) at t_h = (h/p) U e_m + eps K_s U e_{n_s}, h = 0..p-1, for the sets
  * s = 0..S (eqs. (36), (41)): set 0 unshifted, s = 1..d2 shifted by eps along
  * n_s = s, and with ladder_K > 1 also s = d2+1..2 d2 shifted by K eps along

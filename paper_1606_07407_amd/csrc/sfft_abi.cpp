@@ -596,8 +596,8 @@ sfft_status sfft_session_create(sfft_plan plan, int32_t B, const int32_t* k, voi
   if (!plan) return fail(SFFT_EINVAL, "plan is NULL");
   if (B < 1) return fail(SFFT_EINVAL, "B must be >= 1");
   if (!k) return fail(SFFT_EINVAL, "k is NULL");
-  if (plan->kp.verify || plan->kp.residual != SFFT_RESIDUAL_SPECTRUM)
-    return fail(SFFT_EINVAL, "sessions need verify = 0 and the residual subtracted in the spectra");
+  if (plan->kp.residual != SFFT_RESIDUAL_SPECTRUM)
+    return fail(SFFT_EINVAL, "sessions need the residual subtracted in the spectra");
   sfft_session s = new (std::nothrow) sfft_session_s();
   if (!s) return fail(SFFT_ENOMEM, "host allocation failed");
   s->kp = plan->kp;

@@ -306,10 +306,12 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
 // the bucket of a mode is (y . v) mod p, exact in integers:
 //   V[h] = sum_j C[j][0] omega_p^{(h r_j) mod p} - sum_e a_e omega_p^{(h r_e) mod p},
 // then noise (set 0 of round st.i) and the DFT of that one sequence.  Writes
-// the number of buckets with |F[h]| >= verify_eta p to st.ncand.
+// the number of buckets with |F[h]| >= verify_eta p to st.ncand.  `extra`
+// (NULL in the recovery kernel): samples added before the DFT -- the caller's
+// f(t_h) in a session, where there are no planted modes.
 template <typename T>
 __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, WgState& st,
-                            char* lds, cpx<T>* V, int* sh_part) {
+                            char* lds, cpx<T>* V, int* sh_part, const cpx<T>* extra) {
   const int p = st.p, d2 = kp.d2;
   const int M = st.M_pl + st.nslots;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
@@ -408,6 +410,10 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
       for (int g = 1; g < G; ++g) acc = cadd(acc, part[g * p + h]);
       V[h] = acc;
     }
+    __syncthreads();
+  }
+  if (extra) {
+    for (int h = threadIdx.x; h < p; h += kWG) V[h] = cadd(V[h], extra[h]);
     __syncthreads();
   }
   add_noise<T>(V, kp.vstride, p, 1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
@@ -1352,7 +1358,7 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
       }
       phase_mark(kp, ko, st, 0);
       if (at_k) {
-        verify_round<T>(kp, kb, slot, st, lds, V, sh_part);
+        verify_round<T>(kp, kb, slot, st, lds, V, sh_part, nullptr);
         phase_mark(kp, ko, st, 6);
         if (threadIdx.x == 0) {
           st.samples += st.p;
@@ -1427,20 +1433,27 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
 // is one launch, the caller samples f on the lines the session asks for, and
 // each signal's round state lives in global memory between launches.  The
 // steps after sampling are the recovery kernel's (DFT, registry subtraction in
-// the spectra, selection, decode, merge); the verification round is not
-// offered (it samples a different line).  One work-group per signal, slot b of
-// the session's workspace for signal b.
+// the spectra, selection, decode, merge; in a verification round the registry's
+// sum on the tilted line, the DFT and the bucket count).  One work-group per
+// signal, slot b of the session's workspace for signal b.
+
+// A verification round is due (the recovery kernel's test, the state after a
+// round): the registry holds k entries and no repair round is pending.
+__device__ __forceinline__ bool session_at_k(const WgState& st) {
+  return st.nR >= st.k && st.kv == 0;
+}
 
 // The next round of a signal (thread 0): st.p = 0 once it is finished.
 __device__ void session_next(const KParams& kp, WgState& st) {
   st.p = 0;
   if (st.flag) return;
-  if (st.nR >= st.k || st.i > kp.max_rounds) {
+  const bool at_k = session_at_k(st);
+  if ((at_k && (!kp.verify || st.verified)) || st.i > kp.max_rounds) {
     st.flag = 3;
     return;
   }
-  st.kstar = st.k - st.nR;
-  const int p = prime_for_round(kp, st.kstar, st.i);
+  st.kstar = at_k ? 0 : (st.nR < st.k ? st.k - st.nR : st.kv);
+  const int p = prime_for_round(kp, at_k ? 1 : st.kstar, st.i);
   st.m0 = st.i % kp.d2;
   if (p < 2 || p > kp.p_max) {
     st.status = -2;  // SFFT_ERANGE
@@ -1457,9 +1470,11 @@ __device__ void session_next(const KParams& kp, WgState& st) {
   st.log2L = lg;
 }
 
+// The request: m >= 1 names the axis of an ordinary round; m = -q a verification
+// line, v_n = q^(n-1) mod p.
 __device__ __forceinline__ void session_publish(const KSess& ss, const WgState& st, int b) {
   ss.req_p[b] = st.p;
-  ss.req_m[b] = st.m0 + 1;
+  ss.req_m[b] = (st.p > 1 && session_at_k(st)) ? -(1 + (st.i % (st.p - 1))) : st.m0 + 1;
   ss.state[b] = st;
 }
 
@@ -1498,6 +1513,42 @@ session_feed_kernel(KParams kp, KSess ss, const void* samples) {
   if (st.p == 0) return;  // finished (uniform over the work-group)
   const int p = st.p;
   const cpx<T>* src = reinterpret_cast<const cpx<T>*>(samples) + (size_t)b * kp.S1 * kp.p_max;
+  if (session_at_k(st)) {
+    // verification round: f on the tilted line (set 0 of the samples) enters the
+    // residual sum through the set-1 area of V
+    cpx<T>* f = V + vstride;
+    for (int h = threadIdx.x; h < p; h += kWG) f[h] = src[h];
+    __syncthreads();
+    KBatch kb;
+    memset(&kb, 0, sizeof(kb));
+    verify_round<T>(kp, kb, slot, st, lds, V, sh_part, f);
+    if (threadIdx.x == 0) {
+      st.samples += st.p;
+      int32_t* tr = ss.trace + ((size_t)b * kp.max_rounds + (st.i - 1)) * 8;
+      tr[0] = st.i;
+      tr[1] = 0;
+      tr[2] = st.p;
+      tr[3] = 0;
+      tr[4] = st.ncand;
+      tr[5] = 0;
+      tr[6] = st.nR;
+      tr[7] = 1;
+      st.i += 1;
+      if (st.ncand == 0) {
+        st.verified = 1;
+      } else {
+        const int room = st.k + max(16, (st.k + 7) / 8) - st.nR;
+        st.kv = min(min(st.ncand, st.k), room);
+        if (st.kv <= 0) {
+          st.kv = 0;
+          st.flag = 2;  // no room: RESIDUAL_NONZERO
+        }
+      }
+      session_next(kp, st);
+      session_publish(ss, st, b);
+    }
+    return;
+  }
   for (int q = threadIdx.x; q < kp.S1 * p; q += kWG) {
     const int sidx = q / p, h = q - sidx * p;
     V[(size_t)sidx * vstride + h] = src[(size_t)sidx * kp.p_max + h];
@@ -1513,6 +1564,7 @@ session_feed_kernel(KParams kp, KSess ss, const void* samples) {
   merge_round<T>(kp, slot, st, lds, sh_part, 0);
   if (threadIdx.x == 0) {
     st.samples += (int64_t)kp.S1 * st.p;
+    st.kv = 0;
     int32_t* tr = ss.trace + ((size_t)b * kp.max_rounds + (st.i - 1)) * 8;
     tr[0] = st.i;
     tr[1] = st.kstar;
@@ -1537,8 +1589,34 @@ __global__ void __launch_bounds__(kWG) session_points_kernel(KParams kp, KSess s
   const int b = blockIdx.x;
   const int p = ss.req_p[b];
   if (p == 0) return;
-  const int m0 = ss.req_m[b] - 1;
   const int d = kp.d;
+  if (ss.req_m[b] < 0) {
+    // verification line t_h = (h/p) U v, v_n = q^(n-1) mod p (set 0 only)
+    const int64_t q = -ss.req_m[b];
+    double* out0 = t + (size_t)b * kp.S1 * kp.p_max * d;
+    for (int h = threadIdx.x; h < p; h += kWG) {
+      const double x = (double)h / (double)p;
+      double* out = out0 + (size_t)h * d;
+      for (int l = 0; l < d; ++l) out[l] = 0.0;
+      int64_t v = 1;
+      if (kp.tilt) {
+        // U v with U = [[b, a], [-a, b]], v = (1, q)
+        out[0] = x * (double)(kp.tb + kp.ta * q);
+        out[1] = x * (double)(kp.tb * q - kp.ta);
+      } else {
+        for (int n = 0; n < kp.d2; ++n) {
+          double pw = 1.0;
+          for (int l = kp.blk[n]; l < kp.blk[n + 1]; ++l) {
+            out[kp.perm[l]] = x * ((double)v * pw);
+            pw *= (double)kp.N;
+          }
+          v = (v * q) % p;
+        }
+      }
+    }
+    return;
+  }
+  const int m0 = ss.req_m[b] - 1;
   const double eps = 1.0 / (2.0 * (double)kp.NB);
   for (int q = threadIdx.x; q < kp.S1 * p; q += kWG) {
     const int sidx = q / p, h = q - sidx * p;
@@ -1584,7 +1662,8 @@ __global__ void __launch_bounds__(kWG) session_finish_kernel(KParams kp, KSess s
   char* slot = kp.ws + (size_t)b * kp.ws_slot;
   if (threadIdx.x == 0) {
     st = ss.state[b];
-    if (st.status == 0) st.status = (st.nR < st.k) ? 1 : (st.nR > st.k) ? 2 : 0;
+    if (st.status == 0)
+      st.status = (st.nR < st.k) ? 1 : (st.nR > st.k || (kp.verify && !st.verified)) ? 2 : 0;
   }
   __syncthreads();
   if (ko.trace) {

@@ -307,8 +307,12 @@ SESSION_CASES = [
     ("e3_fp64_uneven_order", "e3", {}, 2, 100, 1e-9),
     ("c1_fp64_tilt", "c1", {"tilt": True}, 4, 8, 1e-9),
     ("c2_fp32", "c2", {}, 2, 256, 1e-5),
-    # FP32 with the K eps ladder and the robust checks (noiseless, no verification round)
+    # FP32 with the K eps ladder and the robust checks, without and with the
+    # verification round (the caller samples the tilted line too)
     ("c3_fp32_ladder", "c3b", {"verify": False}, 2, 120, 1e-5),
+    ("c3_fp32_ladder_verify", "c3b", {}, 3, 120, 1e-5),
+    ("c1_fp64_verify", "c1", {"verify": True}, 4, 8, 1e-9),
+    ("e3_fp64_uneven_verify", "e3", {"verify": True}, 2, 100, 1e-9),
 ]
 
 
@@ -325,12 +329,20 @@ def test_session_matches_oracle(name, cname, over, B, k, tol):
     plan = sfft.sfft_plan_create(_params(cfg, k), max_batch=B)
     sess = sfft.Session(plan, np.full(B, k))
     dt = torch.complex64 if cfg["precision"] == "fp32" else torch.complex128
+    P = _oracle_params(cfg, k)
     fed = 0
     while True:
         p, m = sess.request()
         if not p.any():
             break
-        sess.feed(_black_box(pb, sess.points(), dt))
+        t = sess.points()
+        for b in np.nonzero((m < 0) & (p > 0))[0]:
+            # a verification line: t_h = (h/p) U v, v_n = q^(n-1) mod p, q = -m
+            v = np.array([pow(int(-m[b]), n, int(p[b])) for n in range(P.d2)], np.int64)
+            direction = P.line_matrix().astype(np.float64) @ v.astype(np.float64)
+            ref = (np.arange(p[b]).astype(np.float64) / p[b])[:, None] * direction[None, :]
+            assert np.array_equal(t[b, 0, :p[b]].cpu().numpy(), ref), b
+        sess.feed(_black_box(pb, t, dt))
         fed += 1
         assert fed <= cfg.get("max_rounds", 64)
     h = sfft.outputs_to_host(sess.finish())
