@@ -367,6 +367,10 @@ class Session:
             t = s.points()                # [B, S+1, max_prime, d] float64 on the device
             s.feed(f(t))                  # complex [B, S+1, max_prime], the plan's precision
         out = s.finish()                  # as sfft_recover
+
+    m[b] >= 1 is the unwrapped axis of an ordinary round; m[b] = -q marks a
+    verification round, whose one line (set 0 of t and of the samples) is
+    t_h = (h/p) U v with v_n = q^(n-1) mod p.
     """
 
     def __init__(self, plan: Plan, k, stream=None):
