@@ -281,6 +281,11 @@ def paper_sweep(sfft, steps: int, warmup: int, name: str = "e1") -> list:
     return rows
 
 
+def progress(msg: str):
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def params_of(sfft, cfg, k_max):
     """Plan parameters of a workload recipe (every field the recipes set)."""
     tilt = cfg.get("tilt")
@@ -542,6 +547,7 @@ def main():
         tuned, log = autotune(sfft, sfft.Params(**base), db)
         base.update(c=tuned.c, sched_nt=tuned.sched_nt, sched_fft=tuned.sched_fft,
                     sched_dft_batch=tuned.sched_dft_batch)
+        progress(f"autotuned: {plan_key(tuned)} ({len(log)} candidates)")
         tune_info = {"chosen": plan_key(tuned), "seconds": time.perf_counter() - t0,
                      "candidates": [[e["c"], "-".join(map(str, e["sched_nt"])), e["sched_fft"],
                                      e["sched_dft_batch"], e["status"], e["exact"],
@@ -568,6 +574,7 @@ def main():
         out, step_s, gpu_ms, per = time_recover(sfft, plan, db, B, args.steps, args.warmup)
         h = sfft.outputs_to_host(out)
         ok = exact_support(pb, h)
+        progress(f"{kind}: {gpu_ms:.3f} ms per launch, {int(ok.sum())}/{B} exact")
         flops = algorithmic_flops(h["trace"], pb.k, plan.num_sets, int(cfg["residual"]))
         results[kind] = dict(value=int(ok.sum()) / step_s, success_rate=float(ok.mean()),
                              ms_per_step=step_s * 1e3, kernel_ms=gpu_ms,
@@ -585,6 +592,7 @@ def main():
             results[kind]["graph_value"] = int(okg.sum()) / (g_ms * 1e-3)
         if not args.no_curves:
             curves[kind] = tolerance_curve(sfft, base, extra, kind, db, pb, B)
+            progress(f"{kind}: threshold curve done")
         if kind == kinds[0] and not args.no_components:
             tr0 = h["trace"][0, 0]
             comp = components(sfft, plan, pb, db, plan.num_sets, int(tr0[2]), int(tr0[3]),
@@ -658,6 +666,8 @@ def main():
         line["components"] = comp
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        progress(f"cpu baseline: the oracle on {min(max(args.cpu_sample, workers), B)} "
+                 f"signals, {workers} processes")
         line["cpu_baseline"] = cpu_baseline(cfg, pb, min(max(args.cpu_sample, workers), B),
                                             workers)
     print(json.dumps(line), flush=True)
