@@ -36,7 +36,7 @@ METRIC = "signal recoveries/sec at exact support, d=10 k=1000; learned vs plain"
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X FP32 vector
 TUNE_C_OFFSETS = (-1.0, -0.5, 0.0, 0.5)  # c values the autotuner measures around the recipe's c
-TUNE_WARMUP, TUNE_STEPS = 1, 5
+TUNE_WARMUP, TUNE_STEPS = 3, 10
 
 
 def algorithmic_flops(trace: np.ndarray, k: np.ndarray, S1: int, residual: int = 0) -> float:
