@@ -825,6 +825,17 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
             for (int t = 0; t < RT; ++t)
               acc[t][u] =
                   __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[t], b_cur[u], acc[t][u], 0, 0, 0);
+          if constexpr (RT <= 2) {
+            // one or two row tiles: interleaving LDS reads and index arithmetic
+            // between the MFMAs measured faster than the compiler's own order;
+            // from three row tiles on the compiler's order is faster
+#pragma unroll
+            for (int g = 0; g < RT * NT; ++g) {
+              __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+              __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+              __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);   // three VALU
+            }
+          }
 #pragma unroll
           for (int t = 0; t < RT; ++t) a_cur[t] = a_nxt[t];
 #pragma unroll
