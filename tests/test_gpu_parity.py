@@ -353,6 +353,40 @@ def test_session_matches_oracle(name, cname, over, B, k, tol):
     plan.close()
 
 
+def test_session_large_k_against_planted():
+    """A session at k = 500 (FP32, K eps ladder, robust checks, verification rounds): every
+    support equals the planted one and every coefficient is within 1e-5 relative of the
+    planted value (noiseless; the oracle takes minutes per signal at this size)."""
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config("c3b", k=500)
+    B, k = 4, 500
+    _say(f"[session] c3b FP32 B={B} k={k} against planted")
+    pb = workloads.planted_batch(cfg["seed"] + 7, B, cfg["d"], cfg["N"], k, cfg["mag"], 0.0)
+    plan = sfft.sfft_plan_create(_params(cfg, k), max_batch=B)
+    sess = sfft.Session(plan, np.full(B, k))
+    fed = 0
+    while True:
+        p, m = sess.request()
+        if not p.any():
+            break
+        sess.feed(_black_box(pb, sess.points(), torch.complex64))
+        fed += 1
+        assert fed <= 64
+    h = sfft.outputs_to_host(sess.finish())
+    torch.cuda.synchronize()
+    for b in range(B):
+        w, a = pb.signal(b)
+        o = np.lexsort(w.T[::-1])
+        assert int(h["status"][b]) == 0 and int(h["k_found"][b]) == k, b
+        assert np.array_equal(h["freqs"][b, :k], w[o]), b
+        rel = np.abs(h["coeffs"][b, :k] - a[o]) / np.abs(a[o])
+        assert rel.max() <= 1e-5, (b, rel.max())
+    _say(f"    fed {fed} rounds; all {B} exact")
+    sess.close()
+    plan.close()
+
+
 @pytest.mark.parametrize("cname,over", [("e3", {}), ("c1", {"tilt": True}),
                                         ("c3b", {"order_seed": 3101})])
 def test_session_points_match_oracle(cname, over):
