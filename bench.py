@@ -92,9 +92,10 @@ def _oracle_one(args):
                       p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
                       verify_eta=cfg["verify_eta"])
     r = oracle.multiphaseshift(w, a, P, sigma=float(sigma), seed=seed, signal=b)
+    dt = time.perf_counter() - t0
     o = np.lexsort(w.T[::-1])
     ok = int(r.status == 0 and r.freqs.shape == w.shape and np.array_equal(r.freqs, w[o]))
-    return ok, time.perf_counter() - t0
+    return ok, dt, b, int(r.status), r.freqs, r.coeffs
 
 
 def _oracle_warm(_):
@@ -105,11 +106,44 @@ def _oracle_warm(_):
     return 0
 
 
-def cpu_baseline(cfg, pb, n_sig: int, workers: int, budget_s: float = 120.0) -> dict:
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform's description."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def oracle_parity(h, results) -> dict:
+    """The GPU launch against the oracle on the signals the CPU baseline finished:
+    support equal bit for bit, status equal, and the largest relative coefficient error
+    |a_gpu - a_oracle| / |a_oracle| per signal (eq. (41), a = F_0[h] / p)."""
+    per, n_eq = [], 0
+    for _ok, _dt, b, status, freqs, coeffs in sorted(results, key=lambda r: r[2]):
+        kf = int(h["k_found"][b])
+        same = (int(h["status"][b]) == status and kf == freqs.shape[0]
+                and np.array_equal(h["freqs"][b, :kf], freqs))
+        rel = None
+        if same and kf:
+            rel = float((np.abs(h["coeffs"][b, :kf] - coeffs) / np.abs(coeffs)).max())
+        n_eq += int(same)
+        per.append({"signal": int(b), "support_equal": bool(same), "max_rel": rel})
+    rels = [e["max_rel"] for e in per if e["max_rel"] is not None]
+    return {"signals": len(per), "support_equal": n_eq,
+            "max_rel": max(rels) if rels else None, "per_signal": per}
+
+
+def cpu_baseline(cfg, pb, n_sig: int, workers: int, budget_s: float = 120.0,
+                 h=None) -> dict:
     """The oracle on the host: one signal per worker process (spawned, one thread each),
     for at most budget_s seconds of wall time (large workloads need minutes per signal;
     the rate then covers the signals finished within the budget, and is None if none
-    finished)."""
+    finished).  cfg carries the launch's own method parameters (the tuned c), so that
+    with the GPU outputs h the same signals are also compared with the oracle."""
     import multiprocessing as mp
     jobs = []
     for b in range(n_sig):
@@ -141,12 +175,17 @@ def cpu_baseline(cfg, pb, n_sig: int, workers: int, budget_s: float = 120.0) -> 
     busy = sum(r[1] for r in res)
     cut = "" if done == len(jobs) else (f" (cut at the {budget_s:.0f} s budget: {done} of "
                                         f"{len(jobs)} signals finished)")
-    return {"value": (n_ok / dt) if done else None, "unit": "recoveries/s", "cores": workers,
-            "kind": "oracle", "value_one_core": (n_ok / busy) if done else None,
-            "sample": f"first {n_sig} of the {pb.B} signals, FP64 NumPy oracle, one process "
-                      f"per signal on {workers} host cores, {dt:.1f} s wall, "
-                      f"{n_ok}/{done} exact{cut}; value_one_core = exact signals per second "
-                      f"of single-thread oracle time ({busy:.1f} s)"}
+    out = {"value": (n_ok / dt) if done else None, "unit": "recoveries/s", "cores": workers,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "value_one_core": (n_ok / busy) if done else None,
+           "sample": f"first {n_sig} of the {pb.B} signals at the launch's c = {cfg['c']:g}, "
+                     f"FP64 NumPy oracle, one process per signal on {workers} host cores "
+                     f"({cpu_model()}), {dt:.1f} s wall, {n_ok}/{done} exact{cut}; "
+                     f"value_one_core = exact signals per second of single-thread oracle "
+                     f"time ({busy:.1f} s)"}
+    if h is not None:
+        out["parity"] = oracle_parity(h, res)
+    return out
 
 
 def sources_sha256() -> str:
@@ -586,7 +625,7 @@ def main():
                      "columns": ["c", "sched_nt", "sched_fft", "sched_dft_batch", "status",
                                  "exact", "median_ms"]}
     kinds = ["plain", "mlp"] if args.classifier == "both" else [args.classifier]
-    results, train_info, comp, curves = {}, None, None, {}
+    results, train_info, comp, curves, hosts = {}, None, None, {}, {}
     for kind in kinds:
         extra = {}
         if kind == "mlp":
@@ -607,6 +646,7 @@ def main():
         ok = exact_support(pb, h)
         progress(f"{kind}: {gpu_ms:.3f} ms per launch, {int(ok.sum())}/{B} exact")
         flops = algorithmic_flops(h["trace"], pb.k, plan.num_sets, int(cfg["residual"]))
+        hosts[kind] = h
         results[kind] = dict(value=int(ok.sum()) / step_s, success_rate=float(ok.mean()),
                              ms_per_step=step_s * 1e3, kernel_ms=gpu_ms,
                              launch_ms_median=float(np.median(per)),
@@ -699,8 +739,10 @@ def main():
         workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
         progress(f"cpu baseline: the oracle on {min(max(args.cpu_sample, workers), B)} "
                  f"signals, {workers} processes")
-        line["cpu_baseline"] = cpu_baseline(cfg, pb, min(max(args.cpu_sample, workers), B),
-                                            workers, args.cpu_budget)
+        cpu = cpu_baseline(dict(cfg, c=base["c"]), pb, min(max(args.cpu_sample, workers), B),
+                           workers, args.cpu_budget, h=hosts[best])
+        line["coeff_err_vs_oracle"] = cpu.pop("parity")
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

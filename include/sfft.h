@@ -216,6 +216,24 @@ sfft_status sfft_plan_destroy(sfft_plan plan);
 sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch,
                          const sfft_outputs* out, void* stream);
 
+/* Bucket features for training the learned classifier (not in the paper; the
+ * inputs are the spectra of Algorithm MultiPhaseshift's rounds): runs the same
+ * recovery as sfft_recover on `batch` and writes, for every candidate bucket
+ * of every round, one record of the export described in sfft_outputs -- the
+ * SFFT_MLP_FEATURES features (device float [feat_cap][8], before BF16
+ * rounding), the label (device uint8 [feat_cap]: 1 iff the residual holds
+ * exactly one mode in the bucket), and (signal, round, bucket, accepted)
+ * (device int32 [feat_cap][4]) -- at an atomically claimed index, so the
+ * order across signals is not deterministic.  *feat_count (device int64) is
+ * zeroed by the call and ends as the number of records produced; records past
+ * feat_cap are counted but dropped.  No recovery outputs are written.  The
+ * plan's classifier decides which buckets are accepted (the plain test for
+ * the training data).  SFFT_EINVAL for a NULL array or feat_cap < 0.
+ * Allocates nothing. */
+sfft_status sfft_export_bucket_features(sfft_plan plan, const sfft_signal_batch* batch,
+                                        float* feat, uint8_t* label, int32_t* feat_meta,
+                                        int64_t feat_cap, int64_t* feat_count, void* stream);
+
 /* The line sampler on its own (eqs. (36), (41), adaptive residual of
  * Section 5.0): for each signal b writes the S+1 sample sets of round `round`
  * (1-based; keys the noise counter) along unwrapped axis m (1-based) with

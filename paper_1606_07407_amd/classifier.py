@@ -1,9 +1,9 @@
 """Training data and training of the learned bucket classifier, on the GPU.
 
-Bucket features come from the method itself: sfft_recover runs the plain
-ratio test on synthetic signals (d = 6, N = 4096, k = 2000, |a| ~ U[1, 2],
-noise sigma ~ U[0, 1e-2] per signal) with the feature export switched on, and
-every candidate bucket of every round becomes one (features, label) row.
+Bucket features come from the method itself: sfft_export_bucket_features runs
+the recovery with the plain ratio test on synthetic signals (d = 6, N = 4096,
+k = 2000, |a| ~ U[1, 2], noise sigma ~ U[0, 1e-2] per signal), and every
+candidate bucket of every round becomes one (features, label) row.
 Training runs the project's forward/backward and Adam kernels
 (sfft_mlp_train).  Only device memory and the stream come from PyTorch.
 """
@@ -36,8 +36,8 @@ def export_features(n_rows: int, seed: int = 4000, batch: int = 256, recipe=None
         sg = workloads.planted.uniform_sigma(s, batch, *r["sigma"])
         pb = workloads.planted_batch(s, batch, r["d"], r["N"], r["k"], r["mag"], sg)
         cap = batch * 4 * r["k"]
-        out = sfft.alloc_outputs(plan, batch, trace=False, device=device, export_cap=cap)
-        sfft.sfft_recover(plan, sfft.DeviceBatch.from_planted(pb, device), out)
+        out = sfft.sfft_export_bucket_features(plan, sfft.DeviceBatch.from_planted(pb, device),
+                                               cap)
         n = int(out["feat_count"].item())
         n = min(n, cap)
         feats.append(out["feat"][:n].clone())

@@ -549,6 +549,30 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
   return SFFT_OK;
 }
 
+sfft_status sfft_export_bucket_features(sfft_plan plan, const sfft_signal_batch* batch,
+                                        float* feat, uint8_t* label, int32_t* feat_meta,
+                                        int64_t feat_cap, int64_t* feat_count, void* stream) {
+  g_err[0] = 0;
+  sfft_status st = check_batch(plan, batch);
+  if (st != SFFT_OK) return st;
+  if (!feat || !label || !feat_meta || !feat_count)
+    return fail(SFFT_EINVAL, "feat, label, feat_meta and feat_count are required");
+  if (feat_cap < 0) return fail(SFFT_EINVAL, "feat_cap must be >= 0");
+  KOut ko;
+  memset(&ko, 0, sizeof(ko));  // no recovery outputs: the kernel writes only the export
+  ko.feat = feat;
+  ko.label = label;
+  ko.meta = feat_meta;
+  ko.count = feat_count;
+  ko.cap = feat_cap;
+  int e = launch_zero_queue(plan->kp, feat_count, stream);
+  if (e) return hip_fail((hipError_t)e, "queue reset launch");
+  const int grid = std::min(batch->B, plan->kp.n_slots);
+  e = launch_recover(plan->kp, to_kbatch(batch), ko, grid, stream);
+  if (e) return hip_fail((hipError_t)e, "recover launch");
+  return SFFT_OK;
+}
+
 sfft_status sfft_sample_lines(sfft_plan plan, const sfft_signal_batch* batch, int32_t round,
                               int32_t p, int32_t m, const int64_t* res_off, const int64_t* res_y,
                               const double* res_coeffs, void* V, void* stream) {

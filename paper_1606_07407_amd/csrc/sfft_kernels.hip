@@ -301,6 +301,11 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   __syncthreads();
 }
 
+// The S+1 (or `nsets`) prime-length DFTs of a round (defined with the DFT step below).
+template <typename T>
+__device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds, cpx<T>* V,
+                          int vstride, int nsets);
+
 // Verification samples (the check at |R| = k): the residual, planted modes
 // minus registry, on the tilted line t_h = (h/p) U v, v_n = q^(n-1) mod p, so
 // the bucket of a mode is (y . v) mod p, exact in integers:
@@ -1197,6 +1202,10 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
 // lexicographic order of w.
 __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgState& st,
                                     char* lds) {
+  if (ko.freqs == nullptr) {  // feature export only: no recovery outputs
+    __syncthreads();
+    return;
+  }
   const int d = kp.d, d2 = kp.d2, nR = st.nR;
   const int64_t* ry = reg_y(kp, slot, st.sb);
   const double2* ra = reg_a(kp, slot, st.sb);
@@ -1309,7 +1318,7 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
     }
     __syncthreads();
     if (st.flag) {
-      if (threadIdx.x == 0) {
+      if (threadIdx.x == 0 && ko.k_found) {
         ko.k_found[st.sig] = 0;
         ko.status[st.sig] = -1;  // SFFT_EINVAL
         if (ko.rounds) ko.rounds[st.sig] = 0;

@@ -1,7 +1,7 @@
 """Python binding of libsfft (ctypes).  Argument marshalling only.
 
 The names mirror the C ABI of include/sfft.h: sfft_plan_create,
-sfft_plan_destroy, sfft_recover, sfft_sample_lines, sfft_dft,
+sfft_plan_destroy, sfft_recover, sfft_export_bucket_features, sfft_sample_lines, sfft_dft,
 sfft_plan_max_prime, sfft_plan_num_sets, sfft_autotune, sfft_last_error,
 sfft_version (and the classifier kernels sfft_mlp_forward / _grad / _train).
 PyTorch provides device memory and the current stream; every step of the
@@ -110,6 +110,9 @@ def lib() -> ctypes.CDLL:
         L.sfft_recover.argtypes = [vp, ctypes.POINTER(sfft_signal_batch),
                                    ctypes.POINTER(sfft_outputs), vp]
         L.sfft_recover.restype = i32
+        L.sfft_export_bucket_features.argtypes = [vp, ctypes.POINTER(sfft_signal_batch), vp, vp,
+                                                  vp, i64, vp, vp]
+        L.sfft_export_bucket_features.restype = i32
         L.sfft_sample_lines.argtypes = [vp, ctypes.POINTER(sfft_signal_batch), i32, i32, i32,
                                         vp, vp, vp, vp, vp]
         L.sfft_sample_lines.restype = i32
@@ -353,6 +356,26 @@ def sfft_recover(plan: Plan, batch: DeviceBatch, out: dict | None = None, stream
     b = batch.to_c()
     _check(lib().sfft_recover(plan.handle, ctypes.byref(b), ctypes.byref(o), _stream(stream)),
            "sfft_recover")
+    return out
+
+
+def sfft_export_bucket_features(plan: Plan, batch: DeviceBatch, cap: int, out: dict | None = None,
+                                stream=None) -> dict:
+    """Bucket features of every candidate of every round (the classifier's training
+    data): dict of feat [cap, 8] float32, label [cap] uint8, feat_meta [cap, 4] int32 and
+    feat_count [1] int64 device tensors; records past cap are counted, not written."""
+    torch = _torch()
+    if out is None:
+        dev = batch.k.device
+        out = dict(feat=torch.zeros((cap, SFFT_MLP_FEATURES), dtype=torch.float32, device=dev),
+                   label=torch.zeros(cap, dtype=torch.uint8, device=dev),
+                   feat_meta=torch.zeros((cap, 4), dtype=torch.int32, device=dev),
+                   feat_count=torch.zeros(1, dtype=torch.int64, device=dev))
+    b = batch.to_c()
+    _check(lib().sfft_export_bucket_features(plan.handle, ctypes.byref(b), _ptr(out["feat"]),
+                                             _ptr(out["label"]), _ptr(out["feat_meta"]),
+                                             int(out["feat"].shape[0]), _ptr(out["feat_count"]),
+                                             _stream(stream)), "sfft_export_bucket_features")
     return out
 
 

@@ -110,6 +110,35 @@ def test_export_matches_oracle():
     assert n_ref == len(gpu)
 
 
+def test_export_entry_point_equals_recover_export():
+    """sfft_export_bucket_features writes the same records as sfft_recover's optional
+    export on the same batch (bit for bit; the order across signals may differ)."""
+    import torch
+    sfft = _sfft()
+    cfg, pb = _c4_batch(4, 150)
+    g = _export(cfg, pb)
+    plan = _plan(cfg, int(pb.k.max()), pb.B)
+    out = sfft.sfft_export_bucket_features(plan, sfft.DeviceBatch.from_planted(pb), 200000)
+    torch.cuda.synchronize()
+    n = int(out["feat_count"].item())
+    plan.close()
+    assert n == len(g["label"]) and n > 0
+    f, lab, meta = (out["feat"][:n].cpu().numpy(), out["label"][:n].cpu().numpy(),
+                    out["feat_meta"][:n].cpu().numpy())
+    o1 = np.lexsort(meta[:, :3].T[::-1])
+    o2 = np.lexsort(g["meta"][:, :3].T[::-1])
+    assert np.array_equal(meta[o1], g["meta"][o2])
+    assert np.array_equal(lab[o1], g["label"][o2])
+    assert np.array_equal(f[o1], g["feat"][o2])
+    # a too-small cap counts every record and writes only the first cap
+    plan = _plan(cfg, int(pb.k.max()), pb.B)
+    small = sfft.sfft_export_bucket_features(plan, sfft.DeviceBatch.from_planted(pb), 7)
+    torch.cuda.synchronize()
+    plan.close()
+    assert int(small["feat_count"].item()) == n
+    _say(f"[export entry] {n} records equal the recovery's export")
+
+
 def _rand_params(seed):
     rng = np.random.default_rng(seed)
     th = C.init_params(seed) + rng.normal(scale=0.05, size=C.N_PARAMS)

@@ -45,7 +45,8 @@ def _params(cfg, k_max, precision=None):
     prec = cfg["precision"] if precision is None else precision
     return sfft.Params(d=cfg["d"], N=cfg["N"], k_max=k_max, d1=cfg["d1"], c=cfg["c"],
                        p_min=cfg["p_min"], ladder_K=cfg["ladder_K"],
-                       tau=(cfg["tau"] or 0.0), eta=cfg["eta"], max_rounds=cfg.get("max_rounds", 64),
+                       tau=(cfg["tau"] or 0.0), tau_noise=cfg.get("tau_noise", 0.0),
+                       eta=cfg["eta"], max_rounds=cfg.get("max_rounds", 64),
                        precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64,
                        robust=int(cfg["robust"]), verify=int(cfg["verify"]),
                        verify_eta=cfg["verify_eta"] or 0.0, residual=int(cfg["residual"]),
@@ -56,7 +57,8 @@ def _params(cfg, k_max, precision=None):
 
 def _oracle_params(cfg, k):
     return oracle.Params(d=cfg["d"], N=cfg["N"], k=int(k), d1=cfg["d1"], c=cfg["c"],
-                         ladder_K=cfg["ladder_K"], tau=cfg["tau"], eta=cfg["eta"],
+                         ladder_K=cfg["ladder_K"], tau=cfg["tau"],
+                         tau_noise=cfg.get("tau_noise", 0.0), eta=cfg["eta"],
                          p_min=cfg["p_min"], robust=cfg["robust"], verify=cfg["verify"],
                          verify_eta=cfg["verify_eta"], blocks=cfg["blocks"],
                          order=cfg["order"], tilt=cfg["tilt"],
@@ -241,6 +243,8 @@ RECOVER_CASES = [
     ("c2_fp32", "c2", {}, 2, 256, 1e-5),
     ("c2_fp32_single_mode", "c2", {}, 3, 1, 1e-5),
     ("c3_fp32_noisy_small", "c3b", {}, 3, 150, 1e-5),
+    # the noise-widened ratio test (R6): tau = 1e-4 alone rejects most noisy singletons
+    ("c3_fp32_tau_noise", "c3b", {"tau": 1e-4, "tau_noise": 3e-3}, 3, 150, 1e-5),
     ("c3_fp32_uneven_k", "c3b", {}, 5, (20, 260), 1e-5),
     ("c2_fp32_round_cap", "c2", {"max_rounds": 1}, 2, 256, 1e-5),
     ("c1_fp64_round_cap", "c1", {"max_rounds": 1}, 4, 8, 1e-9),
