@@ -193,7 +193,7 @@ typedef struct {
   int64_t feat_cap;
   /* Phase timestamps (optional, NULL = off): [B][max_rounds][SFFT_TRACE_W] device
    * wall-clock ticks (100 MHz) taken by each work-group at the start of round i
-   * (0) and after its sampler (1), DFTs (2), registry subtraction and selection
+   * (0) and after its sampler (1), DFTs (2), registry subtraction (7), selection
    * (3), test and decode (4) and merge (5); a verification round writes 0 and 6.
    * Unused entries are left as they were. */
   int64_t* phase;

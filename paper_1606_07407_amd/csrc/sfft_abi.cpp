@@ -321,7 +321,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   // LDS: the largest of the per-step carve-ups.  The merge/sort arrays stay in
   // LDS unless they would be the largest; then they live in the slot.
   size_t lds = 0;
-  lds = std::max(lds, (size_t)L * cs + (size_t)kTwiddleEntries * cs);     // DFT buffer + twiddles
+  lds = std::max(lds, (size_t)lds_padded(L) * cs + (size_t)kTwiddleEntries * cs);  // DFT buffer + twiddles
   lds = std::max(lds, align16((size_t)kp.p_max * cs) + 2 * align16(2 * (size_t)(kp.m_max + 4)) +
                           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0));  // sampler
   lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection

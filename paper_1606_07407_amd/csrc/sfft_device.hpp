@@ -163,6 +163,11 @@ __device__ inline int block_sum(int v, int* part) {
 }
 
 // ----------------------------------------------------- LDS Stockham FFT ----
+// The DFT buffer in LDS holds element i at i + i / 16 (one complex of padding
+// after every 16): the strided writes of the first Stockham passes (16 or 256
+// elements apart) then spread over the LDS banks instead of hitting one.
+__device__ __forceinline__ int lp(int i) { return i + (i >> 4); }
+
 // One radix-R pass of the Stockham autosort FFT over L points in LDS:
 // item j (k = j mod Ns) reads x_r = buf[j + r L/R], multiplies by
 // w^{r k} with w = exp(-+2 pi i / (Ns R)), applies the R-point DFT and writes
@@ -275,7 +280,7 @@ __device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* T1, cons
       const int k = j & (Ns - 1);
       cpx<T> x[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[r] = buf[j + r * nitems];
+      for (int r = 0; r < R; ++r) x[r] = buf[lp(j + r * nitems)];
       if (Ns > 1) {
         if (R == 16) {
           // w^r = w^{4a} w^b with w^{4a} from the table (a = 1, 2) or one product,
@@ -323,7 +328,7 @@ __device__ void stockham_pass(cpx<T>* buf, int L, int Ns, const cpx<T>* T1, cons
       const int k = j & (Ns - 1);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q * R + r];
+      for (int r = 0; r < R; ++r) buf[lp(base + r * Ns)] = v[q * R + r];
     }
   }
   __syncthreads();
@@ -372,11 +377,13 @@ __device__ __forceinline__ void fft_lds_v(cpx<T>* buf, int L, int log2L, const c
   }
 }
 
-// The largest lengths, kept out of line: their register-held pass needs twice
-// the registers, and inlining it would raise the register pressure (and the
-// spills) of every caller for all lengths.
+// The largest lengths: their register-held pass needs twice the registers.
+// Inlined like every device function the persistent kernels call: out-of-line
+// calls from those 256-VGPR kernels gave wrong results on the GPU in some
+// register-allocation states (the same source with these helpers inlined
+// passed, out of line failed), so the kernels make no calls.
 template <typename T>
-__device__ __noinline__ void fft_lds_large(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
+__device__ __forceinline__ void fft_lds_large(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
                                            const cpx<T>* T2, bool inv, int fs) {
   fft_lds_v<T, MaxL<T>::value / kWG>(buf, L, log2L, T1, T2, inv, fs);
 }
@@ -417,7 +424,7 @@ __device__ __forceinline__ void bs_chirp_in(cpx<T>* buf, const cpx<T>* x0, int v
 #pragma unroll
     for (int u = 0; u < kLoadBlock; ++u) {
       const int n = n0 + u * kWG;
-      if (n < n_all) buf[n] = cmul(xv[u], cv[u]);
+      if (n < n_all) buf[lp(n)] = cmul(xv[u], cv[u]);
     }
   }
 }
@@ -434,7 +441,7 @@ __device__ __forceinline__ void bs_filter(cpx<T>* buf, int n_all, int L, const c
 #pragma unroll
     for (int u = 0; u < kLoadBlock; ++u) {
       const int n = n0 + u * kWG;
-      if (n < n_all) buf[n] = cmul(buf[n], hv[u]);
+      if (n < n_all) buf[lp(n)] = cmul(buf[lp(n)], hv[u]);
     }
   }
 }
@@ -456,7 +463,7 @@ __device__ __forceinline__ void bs_chirp_out(cpx<T>* x0, int vstride, int G, int
       const int n = n0 + u * kWG;
       if (n < n_out) {
         const int g = n / p, m = n - g * p;
-        x0[(size_t)g * vstride + m] = cscale(cmul(buf[(size_t)g * L + m], cv[u]), invL);
+        x0[(size_t)g * vstride + m] = cscale(cmul(buf[lp(g * L + m)], cv[u]), invL);
       }
     }
   }
@@ -470,7 +477,7 @@ template <typename T>
 __device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
                                 cpx<T>* buf, int fs) {
   const int tid = threadIdx.x;
-  cpx<T>* T1 = buf + L;
+  cpx<T>* T1 = buf + lp(L);
   cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
   twiddle_tables<T>(L, T1, T2);
   for (int n = tid; n < p; n += kWG) {
@@ -488,11 +495,11 @@ __device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* 
       v = chirp[L - n];
     }
     v.y = -v.y;
-    buf[n] = v;
+    buf[lp(n)] = v;
   }
   __syncthreads();
   fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
-  for (int n = tid; n < L; n += kWG) bhat[n] = buf[n];
+  for (int n = tid; n < L; n += kWG) bhat[n] = buf[lp(n)];
   __syncthreads();
 }
 
@@ -503,7 +510,7 @@ template <typename T>
 __device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* chirp,
                               const cpx<T>* bhat, cpx<T>* buf, int fs) {
   const int tid = threadIdx.x;
-  const cpx<T>* T1 = buf + L;
+  const cpx<T>* T1 = buf + lp(L);
   const cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
   if constexpr (sizeof(T) == 4) {
     bs_chirp_in<T>(buf, x, 0, L, p, L, log2L, chirp);
@@ -516,14 +523,14 @@ __device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* 
     __syncthreads();
     return;
   }
-  for (int n = tid; n < L; n += kWG) buf[n] = (n < p) ? cmul(x[n], chirp[n]) : cmk<T>(0, 0);
+  for (int n = tid; n < L; n += kWG) buf[lp(n)] = (n < p) ? cmul(x[n], chirp[n]) : cmk<T>(0, 0);
   __syncthreads();
   fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
-  for (int n = tid; n < L; n += kWG) buf[n] = cmul(buf[n], bhat[n]);
+  for (int n = tid; n < L; n += kWG) buf[lp(n)] = cmul(buf[lp(n)], bhat[n]);
   __syncthreads();
   fft_lds<T>(buf, L, log2L, T1, T2, true, fs);
   const T invL = (T)1 / (T)L;
-  for (int n = tid; n < p; n += kWG) x[n] = cscale(cmul(buf[n], chirp[n]), invL);
+  for (int n = tid; n < p; n += kWG) x[n] = cscale(cmul(buf[lp(n)], chirp[n]), invL);
   __syncthreads();
 }
 
@@ -545,11 +552,11 @@ __device__ void stockham_pass_b(cpx<T>* buf, int L, int lgn, int G, int Ns, cons
     const int jj = tid + q * kWG;
     if (jj < total) {
       const int j = jj & (nitems - 1);
-      const cpx<T>* b = buf + (size_t)(jj >> lgn) * L;
+      const int b = (jj >> lgn) * L;  // first element of this sequence
       const int k = j & (Ns - 1);
       cpx<T> x[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[r] = b[j + r * nitems];
+      for (int r = 0; r < R; ++r) x[r] = buf[lp(b + j + r * nitems)];
       if (Ns > 1) {
         if (R == 16) {
           cpx<T> w1 = twiddle(T1, T2, k * tw_mul);
@@ -592,11 +599,11 @@ __device__ void stockham_pass_b(cpx<T>* buf, int L, int lgn, int G, int Ns, cons
     const int jj = tid + q * kWG;
     if (jj < total) {
       const int j = jj & (nitems - 1);
-      cpx<T>* b = buf + (size_t)(jj >> lgn) * L;
+      const int b = (jj >> lgn) * L;
       const int k = j & (Ns - 1);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) b[base + r * Ns] = v[q * R + r];
+      for (int r = 0; r < R; ++r) buf[lp(b + base + r * Ns)] = v[q * R + r];
     }
   }
   __syncthreads();
@@ -628,7 +635,7 @@ __device__ __forceinline__ void fft_lds_batch(cpx<T>* buf, int L, int log2L, int
 // Bluestein set-up with the twiddle tables at `tab` (outside the batch area):
 // chirp and the filter spectrum bhat as in bluestein_setup.
 template <typename T>
-__device__ __noinline__ void bluestein_setup_at(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
+__device__ __forceinline__ void bluestein_setup_at(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
                                    cpx<T>* buf, cpx<T>* tab, int fs) {
   const int tid = threadIdx.x;
   cpx<T>* T1 = tab;
@@ -649,17 +656,17 @@ __device__ __noinline__ void bluestein_setup_at(int p, int L, int log2L, cpx<T>*
       v = chirp[L - n];
     }
     v.y = -v.y;
-    buf[n] = v;
+    buf[lp(n)] = v;
   }
   __syncthreads();
   fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
-  for (int n = tid; n < L; n += kWG) bhat[n] = buf[n];
+  for (int n = tid; n < L; n += kWG) bhat[n] = buf[lp(n)];
   __syncthreads();
 }
 
 // G sequences x_g = x0 + g vstride (length p) transformed together, in place.
 template <typename T, int MAXV>
-__device__ __noinline__ void bluestein_dft_batch(cpx<T>* x0, int vstride, int G, int p, int L, int log2L,
+__device__ __forceinline__ void bluestein_dft_batch(cpx<T>* x0, int vstride, int G, int p, int L, int log2L,
                                     const cpx<T>* chirp, const cpx<T>* bhat, cpx<T>* buf,
                                     const cpx<T>* tab, int fs) {
   const int tid = threadIdx.x;

@@ -26,6 +26,9 @@ __host__ __device__ inline int nt_band(int p) {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// Elements of an n-point DFT buffer in LDS with its padding (one after every 16).
+__host__ __device__ inline int lds_padded(int n) { return n + (n >> 4); }
+
 // LDS carve-up of the registry merge step (shared by host sizing and device).
 struct MergeLds {
   size_t accpos, ids, key0, runflag, runpos, cnt, matchrun, keep, bytes;

@@ -445,7 +445,7 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
     // min(L_max, 8192) / L sets are transformed together
     constexpr int MAXV = MaxL<T>::value / 2 / kWG;
     if (kp.sched_dft_batch != 1 && st.L <= MAXV * kWG && 2 * st.L <= kp.L_max) {
-      cpx<T>* tab = buf + kp.L_max;
+      cpx<T>* tab = buf + lds_padded(kp.L_max);
       bluestein_setup_at<T>(st.p, st.L, st.log2L, chirp, bhat, buf, tab, kp.sched_fft);
       int cap = min(kp.L_max, MAXV * kWG) / st.L;
       if (kp.sched_dft_batch > 1) cap = min(cap, kp.sched_dft_batch);
@@ -655,13 +655,15 @@ __device__ void select_round(const KParams& kp, char* slot, WgState& st, char* l
   }
   cnt = block_sum(cnt, sh_part);
   if (cnt > st.kstar) {
-    // radix select of the k*-th largest key among the passing buckets
+    // radix select of the k*-th largest key among the passing buckets, 8 bits a
+    // pass from the top (FP32 keys have 32 bits, FP64 keys 64)
     if (threadIdx.x == 0) {
       st.prefix = 0ull;
       st.need = st.kstar;
     }
     __syncthreads();
-    for (int pass = 7; pass >= 0; --pass) {
+    constexpr int kTopPass = sizeof(T) == 4 ? 3 : 7;
+    for (int pass = kTopPass; pass >= 0; --pass) {
       const int shift = pass * 8;
       for (int b = threadIdx.x; b < 256; b += kWG) hist[b] = 0;
       __syncthreads();
@@ -672,16 +674,23 @@ __device__ void select_round(const KParams& kp, char* slot, WgState& st, char* l
           atomicAdd(&hist[(int)((keys[h] >> shift) & 255ull)], 1);
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        int cum = 0, need = st.need;
-        for (int b = 255; b >= 0; --b) {
-          if (cum + hist[b] >= need) {
-            st.prefix = prefix | ((uint64_t)b << shift);
-            st.need = need - cum;
-            break;
-          }
-          cum += hist[b];
-        }
+      // counts from the top bin down: sh_part[t] = keys in bins >= 255 - t
+      // (inclusive scan over the reversed histogram); the first t where it
+      // reaches `need` names the bin
+      const int need = st.need;
+      const int tid = threadIdx.x;
+      sh_part[tid] = (tid < 256) ? hist[255 - tid] : 0;
+      __syncthreads();
+      for (int off = 1; off < kWG; off <<= 1) {
+        const int v = (tid >= off) ? sh_part[tid - off] : 0;
+        __syncthreads();
+        sh_part[tid] += v;
+        __syncthreads();
+      }
+      const int above = (tid == 0) ? 0 : sh_part[tid - 1];
+      if (tid < 256 && above < need && sh_part[tid] >= need) {
+        st.prefix = prefix | ((uint64_t)(255 - tid) << shift);
+        st.need = need - above;
       }
       __syncthreads();
     }
@@ -1404,6 +1413,7 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
       dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
       phase_mark(kp, ko, st, 2);
       if (kp.residual == 0) subtract_registry<T>(kp, slot, st, lds, V, vstride, kp.S1, sh_part);
+      phase_mark(kp, ko, st, 7);
       select_round<T>(kp, slot, st, lds, V, sh_part);
       phase_mark(kp, ko, st, 3);
       decode_round<T>(kp, ko, slot, st, V, vstride, lds, sh_part);

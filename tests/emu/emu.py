@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import os
 import re
+import shutil
 import struct
 import subprocess
 import tempfile
@@ -61,8 +62,8 @@ def build(kind: str) -> str:
     if os.path.exists(exe):
         return exe
     os.makedirs(BUILD, exist_ok=True)
-    src_dir = os.path.join(BUILD, f"src_{kind}")
-    os.makedirs(src_dir, exist_ok=True)
+    # a private directory per build: parallel test workers may build at the same time
+    src_dir = tempfile.mkdtemp(prefix=f"src_{kind}_", dir=BUILD)
     units = []
     for f in sorted(os.listdir(CSRC)):      # headers too: the build includes these copies
         if not f.endswith((".hpp", ".h")):
@@ -88,19 +89,18 @@ def build(kind: str) -> str:
              "-Wno-unknown-pragmas", *SANITIZE[kind]]
     objs = []
     for u in units:
-        o = u + f".{kind}.o"
-        if u.endswith("emu_runtime.cpp") or u.endswith("emu_driver.cpp"):
-            o = os.path.join(BUILD, os.path.basename(u) + f".{kind}.o")
+        o = os.path.join(src_dir, os.path.basename(u) + f".{kind}.o")
         r = subprocess.run([compiler(), *flags, "-c", u, "-o", o], capture_output=True, text=True)
         if r.returncode:
             raise RuntimeError(f"emulator build failed on {u}:\n{r.stderr[-4000:]}")
         objs.append(o)
-    tmp = exe + ".tmp"
+    tmp = os.path.join(src_dir, "emu_driver")
     r = subprocess.run([compiler(), "-pthread", *SANITIZE[kind], "-o", tmp, *objs],
                        capture_output=True, text=True)
     if r.returncode:
         raise RuntimeError(f"emulator link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, exe)
+    shutil.rmtree(src_dir, ignore_errors=True)
     return exe
 
 
@@ -110,20 +110,24 @@ def build_planted(kind: str) -> str:
     if os.path.exists(exe):
         return exe
     os.makedirs(BUILD, exist_ok=True)
+    work = tempfile.mkdtemp(prefix=f"planted_{kind}_", dir=BUILD)
     flags = ["-std=c++17", "-O1", "-g", "-pthread", "-x", "c++", "-I", HERE,
              "-Wno-attributes", "-Wno-unknown-pragmas", *SANITIZE[kind]]
     objs = []
     for u in ("planted.cpp", "emu_runtime.cpp"):
-        o = os.path.join(BUILD, f"{u}.planted.{kind}.o")
+        o = os.path.join(work, f"{u}.{kind}.o")
         r = subprocess.run([compiler(), *flags, "-c", os.path.join(HERE, u), "-o", o],
                            capture_output=True, text=True)
         if r.returncode:
             raise RuntimeError(f"build failed on {u}:\n{r.stderr[-3000:]}")
         objs.append(o)
-    r = subprocess.run([compiler(), "-pthread", *SANITIZE[kind], "-o", exe, *objs],
+    tmp = os.path.join(work, "planted")
+    r = subprocess.run([compiler(), "-pthread", *SANITIZE[kind], "-o", tmp, *objs],
                        capture_output=True, text=True)
     if r.returncode:
         raise RuntimeError(f"link failed:\n{r.stderr[-3000:]}")
+    os.replace(tmp, exe)
+    shutil.rmtree(work, ignore_errors=True)
     return exe
 
 

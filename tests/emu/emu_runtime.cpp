@@ -165,7 +165,11 @@ void run_blocks(const Launch& l, void (*body)(void*), void* ctx) {
         (int)l.grid.x);
   g_block_dim = Idx{l.block.x, 1, 1};
   g_grid_dim = Idx{l.grid.x, 1, 1};
-  for (unsigned b = 0; b < l.grid.x; ++b) {
+  // Work-groups run one at a time, the last first: in the persistent kernels the
+  // first work-group to run takes every signal from the queue, and the last
+  // work-group's workspace slot ends where the allocation (and ASan's red zone)
+  // begins, so that an access past the end of a slot is reported.
+  for (int b = (int)l.grid.x - 1; b >= 0; --b) {
     // exactly the launch's dynamic LDS, fresh per work-group, filled with a
     // pattern (not zero: the hardware does not clear LDS either)
     g_lds_bytes = l.lds;
@@ -179,7 +183,7 @@ void run_blocks(const Launch& l, void (*body)(void*), void* ctx) {
     for (int t = 0; t < nt; ++t)
       th.emplace_back([=] {
         t_thread = Idx{(unsigned)t, 0, 0};
-        t_block = Idx{b, 0, 0};
+        t_block = Idx{(unsigned)b, 0, 0};
         body(ctx);
       });
     for (auto& x : th) x.join();
@@ -208,8 +212,8 @@ hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
   return hipSuccess;
 }
 hipError_t hipMalloc(void** p, size_t n) {
-  *p = aligned_alloc(256, (n + 255) & ~(size_t)255);
-  if (!*p) return hipErrorOutOfMemory;
+  // exactly n bytes (256-byte aligned), so that ASan's red zone starts at byte n
+  if (posix_memalign(p, 256, n ? n : 1) != 0) return hipErrorOutOfMemory;
   memset(*p, 0x5A, n);  // device memory is not cleared by allocation either
   return hipSuccess;
 }
