@@ -287,25 +287,26 @@ def _plain_test(F, h, p, P: Params) -> bool:
 
 
 def _test_margin(F, h, p, P: Params) -> float:
-    """Distance of bucket h's ratio test (eq. (42)) from its threshold, relative to the
-    threshold: min over the shifted sets of | thr - | |F_s/F_0| - 1 | | / thr.  A
-    diagnostic of how near a tie the decision was; it decides nothing."""
+    """Distance of bucket h's ratio test (eq. (42)) from its threshold, in units of the
+    ratio: min over the shifted sets of | thr - | |F_s/F_0| - 1 | |.  A diagnostic of how
+    near a tie the decision was; it decides nothing."""
     F0 = complex(F[0][h])
     thr = P.tau_eff + (P.tau_noise * math.sqrt(p) / abs(F0) if P.tau_noise > 0 else 0.0)
-    return min(abs(thr - abs(abs(complex(F[s][h]) / F0) - 1.0)) / thr for s in range(1, len(F)))
+    return min(abs(thr - abs(abs(complex(F[s][h]) / F0) - 1.0)) for s in range(1, len(F)))
 
 
 def _select_margin(absF0, order, kstar: int, p: int, eta: float) -> float:
-    """Relative distance of the candidate choice (R7, R8) from a tie: the gap between the
-    k*-th and (k*+1)-th largest |F_0| and the distance of each chosen |F_0|/p from the
-    floor eta.  Diagnostic only."""
+    """Distance of the candidate choice (R7, R8) from a tie, in units of |F_0|/p (a
+    coefficient): the gap between the k*-th and (k*+1)-th largest |F_0| when that cut
+    decides between candidates, and the distance of each chosen |F_0|/p from the floor
+    eta.  Diagnostic only."""
     m = math.inf
     if kstar < len(absF0):
         a, b = absF0[order[kstar - 1]], absF0[order[kstar]]
         if max(a, b) / p >= eta:          # the order at the cut changes the candidates
-            m = min(m, (a - b) / a)
+            m = min(m, (a - b) / p)
     for x in order[:kstar]:
-        m = min(m, abs(absF0[x] / p - eta) / eta)
+        m = min(m, abs(absF0[x] / p - eta))
     return m
 
 
@@ -409,9 +410,9 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
             samples += p
             veta = P.eta if P.verify_eta is None else P.verify_eta
             n_res = int(np.count_nonzero(np.abs(F0) / p >= veta))
-            vmargin = float(np.min(np.abs(np.abs(F0) / p - veta)) / veta)
+            vmargin = float(np.min(np.abs(np.abs(F0) / p - veta)))
             trace.append(dict(i=i, kstar=0, p=p, m=0, n_cand=n_res, n_acc=0, n_R=len(R),
-                              verify=1, margin=vmargin))
+                              verify=1, margin_ratio=math.inf, margin_coeff=vmargin))
             i += 1
             if n_res == 0:
                 verified = True
@@ -436,7 +437,8 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
         full_order = np.argsort(-np.abs(F0), kind="stable")
         order = full_order[:kstar]                                       # R7
         cand = sorted(int(x) for x in order if abs(F0[x]) / p >= P.eta)  # R8
-        margin = _select_margin(np.abs(F0), full_order, kstar, p, P.eta)
+        margin_coeff = _select_margin(np.abs(F0), full_order, kstar, p, P.eta)
+        margin_ratio = math.inf
         accepted = []
         for hb in cand:
             y, valid = _decode(F, hb, p, m, P)
@@ -448,7 +450,7 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
             else:
                 ok = valid and _plain_test(F, hb, p, P)
                 if valid:
-                    margin = min(margin, _test_margin(F, hb, p, P))
+                    margin_ratio = min(margin_ratio, _test_margin(F, hb, p, P))
             if collect is not None:
                 collect.append((i, hb, feats, bucket_label(hb, p, m, y_planted, coeffs, R, P.eta),
                                 int(ok), abs(F0[hb]) / p))
@@ -458,7 +460,8 @@ def multiphaseshift(freqs, coeffs, P: Params, sigma: float = 0.0, seed: int = 0,
             R[y] = R.get(y, 0.0) + a
         R = {y: a for y, a in R.items() if abs(a) >= P.eta}              # R8
         trace.append(dict(i=i, kstar=kstar, p=p, m=m, n_cand=len(cand),
-                          n_acc=len(accepted), n_R=len(R), verify=0, margin=margin))
+                          n_acc=len(accepted), n_R=len(R), verify=0,
+                          margin_ratio=margin_ratio, margin_coeff=margin_coeff))
         if keep_spectra:
             spectra.append(np.array(F))
             registry.append(snapshot)

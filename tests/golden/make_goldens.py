@@ -12,10 +12,10 @@ library's launch with them.
 Each signal becomes one compressed .npz file holding the recovered frequencies
 (int64 [k_found, d], lexicographic order of w), coefficients (complex128), the
 status, rounds and samples, the per-round trace rows (i, k*, p, m, candidates,
-accepted, |R|, verification flag), each round's smallest decision margin (how near
-a tie its ratio tests, candidate choice or verification count came, relative to the
-threshold), and a digest of the planted input so that a test can tell that it
-regenerated the same signal.  The recipe and method
+accepted, |R|, verification flag), each round's smallest decision margins (how near a
+tie its ratio tests came, in units of the ratio, and its candidate cut, eta floor and
+verification count, in units of |F|/p), and a digest of the planted input so that a
+test can tell that it regenerated the same signal.  The recipe and method
 parameters are stored beside them as JSON text.
 """
 from __future__ import annotations
@@ -103,7 +103,8 @@ def _one(job):
     secs = time.time() - t0
     trace = np.array([[t["i"], t["kstar"], t["p"], t["m"], t["n_cand"], t["n_acc"], t["n_R"],
                        t["verify"]] for t in r.trace], dtype=np.int64).reshape(-1, 8)
-    margin = np.array([t["margin"] for t in r.trace], dtype=np.float64)
+    margin_ratio = np.array([t["margin_ratio"] for t in r.trace], dtype=np.float64)
+    margin_coeff = np.array([t["margin_coeff"] for t in r.trace], dtype=np.float64)
     meta = dict(case=name, signal=b, recipe=case["recipe"], over=case["over"], B=case["B"],
                 k=case["k"], sigma=float(pb.sigma[b]), seed=pb.seed, c=cfg["c"],
                 oracle_seconds=round(secs, 1), planted_sha256=planted_digest(w, a),
@@ -111,7 +112,8 @@ def _one(job):
     np.savez_compressed(golden_path(name, b), freqs=r.freqs.astype(np.int64),
                         coeffs=r.coeffs.astype(np.complex128),
                         status=np.int64(r.status), rounds=np.int64(r.rounds),
-                        samples=np.int64(r.samples), trace=trace, margin=margin,
+                        samples=np.int64(r.samples), trace=trace, margin_ratio=margin_ratio,
+                        margin_coeff=margin_coeff,
                         meta=np.array(json.dumps(meta, sort_keys=True)))
     return name, b, r.status, r.rounds, secs
 

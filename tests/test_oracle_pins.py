@@ -178,25 +178,25 @@ def test_feature_axis_without_ladder_and_single_axis():
 # ------------------------------------------------------ decision margins -----
 
 def test_test_margin_is_the_distance_to_the_threshold():
-    # tau = 2^-10, deviations 2^-11 (set 1) and 3 * 2^-12 (set 2): margins 1/2 and 1/4
+    # tau = 2^-10, deviations 2^-11 (set 1) and 3 * 2^-12 (set 2): distances 2^-11, 2^-12
     p, F0 = 64, 8.0
     F = _spectra_with_ratios(F0, [1.0 + 2 ** -11, 1.0 - 3 * 2 ** -12], p)
     P = oracle.Params(d=2, N=64, k=1, tau=2 ** -10)
-    assert M._test_margin(F, 0, p, P) == 0.25
+    assert M._test_margin(F, 0, p, P) == 2 ** -12
 
 
 def test_select_margin_counts_only_candidate_ties():
     absF0 = np.array([50.0, 40.0, 39.0, 0.001, 0.0005])
     order = np.argsort(-absF0, kind="stable")
-    # cut between 40 and 39 (both candidates at p = 10, eta = 1e-3): gap 1/40
-    assert abs(M._select_margin(absF0, order, 2, 10, 1e-3) - 1 / 40) < 1e-15
+    # cut between 40 and 39 (both candidates at p = 10, eta = 1e-3): gap 1 / p = 0.1
+    assert abs(M._select_margin(absF0, order, 2, 10, 1e-3) - 0.1) < 1e-15
     # cut between two buckets below the floor: only the floor distances count
-    # (0.001 / 10 = 1e-4 against eta = 1e-3: 0.9)
-    assert abs(M._select_margin(absF0, order, 4, 10, 1e-3) - 0.9) < 1e-12
+    # (0.001 / 10 = 1e-4 against eta = 1e-3: 9e-4)
+    assert abs(M._select_margin(absF0, order, 4, 10, 1e-3) - 9e-4) < 1e-15
 
 
 def test_noiseless_recovery_margins_are_wide():
     import workloads
     w, a = workloads.planted_signal(1000, 0, 2, 64, 8)
     r = oracle.multiphaseshift(w, a, oracle.Params(d=2, N=64, k=8, tau=1e-6))
-    assert all(t["margin"] > 0.5 for t in r.trace)
+    assert all(t["margin_coeff"] > 0.5e-3 and t["margin_ratio"] > 1e-7 for t in r.trace)
