@@ -216,6 +216,25 @@ sfft_status sfft_plan_destroy(sfft_plan plan);
 sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch,
                          const sfft_outputs* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): sfft_recover with the
+ * per-work-group workspace and the work-queue counter taken from a fixed
+ * device array of the library (64 MiB per device, held until the process
+ * ends) instead of the plan's workspace.  Same arguments, outputs and results
+ * as sfft_recover (feature export is not offered: those fields must be NULL);
+ * as many work-groups run as workspace slots fit in the array
+ * (sfft_static_scratch_slots), each taking signals from the queue.  The call
+ * allocates nothing and clears the part of the array it uses with a kernel
+ * before the recovery.  Every call on one device shares that device's array:
+ * calls that overlap in time on one device (any plan, any stream) race and
+ * must be serialised by the caller.  SFFT_ERANGE when one workspace slot of
+ * the plan does not fit in the array; otherwise as sfft_recover. */
+sfft_status sfft_recover_static(sfft_plan plan, const sfft_signal_batch* batch,
+                                const sfft_outputs* out, void* stream);
+/* Workspace slots of this plan that fit in the fixed array (0: the plan is too
+ * large for sfft_recover_static). */
+int32_t sfft_static_scratch_slots(sfft_plan plan);
+
 /* Bucket features for training the learned classifier (not in the paper; the
  * inputs are the spectra of Algorithm MultiPhaseshift's rounds): runs the same
  * recovery as sfft_recover on `batch` and writes, for every candidate bucket

@@ -457,6 +457,12 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
     sfft_plan_destroy(plan);
     return hip_fail(e, "plan upload");
   }
+  // the fixed scratch of sfft_recover_static: its address on this device, looked up once
+  const int se = static_scratch_setup(dev);
+  if (se != 0) {
+    sfft_plan_destroy(plan);
+    return hip_fail((hipError_t)se, "hipGetSymbolAddress of the fixed scratch");
+  }
   const int le = set_kernel_lds_limits((int)lds);
   if (le != 0) {
     sfft_plan_destroy(plan);
@@ -547,6 +553,38 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
   e = launch_recover(plan->kp, to_kbatch(batch), ko, grid, stream);
   if (e) return hip_fail((hipError_t)e, "recover launch");
   return SFFT_OK;
+}
+
+sfft_status sfft_recover_static(sfft_plan plan, const sfft_signal_batch* batch,
+                                const sfft_outputs* out, void* stream) {
+  g_err[0] = 0;
+  sfft_status st = check_batch(plan, batch);
+  if (st != SFFT_OK) return st;
+  if (!out || !out->freqs || !out->coeffs || !out->k_found || !out->status)
+    return fail(SFFT_EINVAL, "outputs need freqs, coeffs, k_found and status");
+  if (out->feat || out->label || out->feat_meta || out->feat_count)
+    return fail(SFFT_EINVAL, "sfft_recover_static does not export features");
+  if (plan->kp.ws_slot + kStaticQueueBytes > kStaticScratchBytes)
+    return fail(SFFT_ERANGE,
+                "one workspace slot of this plan takes %zu bytes; the fixed scratch holds %zu",
+                plan->kp.ws_slot, kStaticScratchBytes - kStaticQueueBytes);
+  KOut ko;
+  memset(&ko, 0, sizeof(ko));
+  ko.freqs = out->freqs;
+  ko.coeffs = out->coeffs;
+  ko.k_found = out->k_found;
+  ko.status = out->status;
+  ko.rounds = out->rounds;
+  ko.samples = out->samples;
+  ko.trace = out->trace;
+  ko.phase = out->phase;
+  const int e = launch_recover_static(plan->kp, to_kbatch(batch), ko, plan->device, stream);
+  if (e) return hip_fail((hipError_t)e, "static-scratch recover launch");
+  return SFFT_OK;
+}
+
+int32_t sfft_static_scratch_slots(sfft_plan plan) {
+  return plan ? static_scratch_slots(plan->kp.ws_slot) : 0;
 }
 
 sfft_status sfft_export_bucket_features(sfft_plan plan, const sfft_signal_batch* batch,

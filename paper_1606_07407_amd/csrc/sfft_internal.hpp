@@ -169,6 +169,16 @@ int launch_mlp_accum(const float* src, float* dst, float scale, void* stream);
 int launch_fill(float* a, int n, float v, void* stream);
 constexpr int kMlpParamCount = 4866;
 int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream);
+// Fixed device scratch of sfft_recover_static (see the .hip file): its size,
+// the part the queue counter takes, the per-device address lookup (call once
+// per device with that device current), the slots of a given size it holds,
+// and the launch that uses it instead of the plan's workspace.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr size_t kStaticQueueBytes = 256;
+int static_scratch_setup(int dev);
+int static_scratch_slots(size_t ws_slot);
+int launch_recover_static(const KParams& kp, const KBatch& kb, const KOut& ko, int dev,
+                          void* stream);
 int launch_sample_lines(const KParams& kp, const KBatch& kb, int round, int p, int m,
                         const int64_t* res_off, const int64_t* res_y, const double* res_c,
                         void* V, void* stream);

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "sfft_device.hpp"
 #include "sfft_internal.hpp"
 #include "sfft_mlp.hpp"
@@ -1826,6 +1828,77 @@ int launch_zero_queue(const KParams& kp, int64_t* count, void* stream) {
 
 int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream) {
   SFFT_RT_DISPATCH(recover_kernel, dim3(grid), dim3(kWG), kp.lds_bytes, (hipStream_t)stream, kp,
+                   kb, ko);
+  return (int)hipGetLastError();
+}
+
+// ------------------------------------------------ fixed device scratch ------
+// Workspace of sfft_recover_static: the work-queue counter in the first 256
+// bytes, then as many workspace slots as fit.  One copy per device, held
+// until the process ends; every call on a device shares it.  In host code the
+// array's name is no device address: the address of each device's copy comes
+// from hipGetSymbolAddress (static_scratch_setup) and only that is used.
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};  // per device, set once with that device current
+}  // namespace
+
+int static_scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return 0;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return (int)e;
+  if (!ptr) return (int)hipErrorInvalidSymbol;
+  g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  return 0;
+}
+
+int static_scratch_slots(size_t ws_slot) {
+  return ws_slot ? (int)((kStaticScratchBytes - kStaticQueueBytes) / ws_slot) : 0;
+}
+
+// Zero-fills n16 16-byte words (a kernel, not hipMemsetAsync, so that the call
+// can be captured in a graph).
+__global__ void __launch_bounds__(256) zero_fill_kernel(uint4* p, size_t n16) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = z;
+}
+
+int launch_recover_static(const KParams& kp, const KBatch& kb, const KOut& ko, int dev,
+                          void* stream) {
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  char* base;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = g_scratch_ptr[dev];
+  }
+  if (!base) return (int)hipErrorNotInitialized;
+  const int fit = static_scratch_slots(kp.ws_slot);
+  const int grid = min(kb.B, min(kp.n_slots, fit));
+  if (grid < 1) return (int)hipErrorInvalidValue;
+  KParams k2 = kp;
+  k2.queue = reinterpret_cast<int*>(base);
+  k2.ws = base + kStaticQueueBytes;
+  k2.n_slots = grid;
+  // the slots start as a new plan's workspace does (zeroed): another plan's
+  // layout may have left anything there
+  const size_t n16 = (kStaticQueueBytes + (size_t)grid * kp.ws_slot) / 16;
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(1024), dim3(256), 0, (hipStream_t)stream,
+                     reinterpret_cast<uint4*>(base), n16);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, k2.queue,
+                     ko.count);
+  e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  SFFT_RT_DISPATCH(recover_kernel, dim3(grid), dim3(kWG), kp.lds_bytes, (hipStream_t)stream, k2,
                    kb, ko);
   return (int)hipGetLastError();
 }

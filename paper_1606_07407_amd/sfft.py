@@ -1,7 +1,8 @@
 """Python binding of libsfft (ctypes).  Argument marshalling only.
 
 The names mirror the C ABI of include/sfft.h: sfft_plan_create,
-sfft_plan_destroy, sfft_recover, sfft_export_bucket_features, sfft_sample_lines, sfft_dft,
+sfft_plan_destroy, sfft_recover, sfft_recover_static, sfft_static_scratch_slots,
+sfft_export_bucket_features, sfft_sample_lines, sfft_dft,
 sfft_plan_max_prime, sfft_plan_num_sets, sfft_autotune, sfft_last_error,
 sfft_version (and the classifier kernels sfft_mlp_forward / _grad / _train).
 PyTorch provides device memory and the current stream; every step of the
@@ -110,6 +111,11 @@ def lib() -> ctypes.CDLL:
         L.sfft_recover.argtypes = [vp, ctypes.POINTER(sfft_signal_batch),
                                    ctypes.POINTER(sfft_outputs), vp]
         L.sfft_recover.restype = i32
+        L.sfft_recover_static.argtypes = [vp, ctypes.POINTER(sfft_signal_batch),
+                                          ctypes.POINTER(sfft_outputs), vp]
+        L.sfft_recover_static.restype = i32
+        L.sfft_static_scratch_slots.argtypes = [vp]
+        L.sfft_static_scratch_slots.restype = i32
         L.sfft_export_bucket_features.argtypes = [vp, ctypes.POINTER(sfft_signal_batch), vp, vp,
                                                   vp, i64, vp, vp]
         L.sfft_export_bucket_features.restype = i32
@@ -357,6 +363,26 @@ def sfft_recover(plan: Plan, batch: DeviceBatch, out: dict | None = None, stream
     _check(lib().sfft_recover(plan.handle, ctypes.byref(b), ctypes.byref(o), _stream(stream)),
            "sfft_recover")
     return out
+
+
+def sfft_recover_static(plan: Plan, batch: DeviceBatch, out: dict | None = None,
+                        stream=None) -> dict:
+    """sfft_recover with the library's fixed device scratch instead of the plan's
+    workspace (no device allocation by the library; overlapping calls on one device
+    race)."""
+    if out is None:
+        out = alloc_outputs(plan, batch.B)
+    o = sfft_outputs(_ptr(out["freqs"]), _ptr(out["coeffs"]), _ptr(out["k_found"]),
+                     _ptr(out["status"]), _ptr(out.get("rounds")), _ptr(out.get("samples")),
+                     _ptr(out.get("trace")), None, None, None, None, 0, _ptr(out.get("phase")))
+    b = batch.to_c()
+    _check(lib().sfft_recover_static(plan.handle, ctypes.byref(b), ctypes.byref(o),
+                                     _stream(stream)), "sfft_recover_static")
+    return out
+
+
+def sfft_static_scratch_slots(plan: Plan) -> int:
+    return int(lib().sfft_static_scratch_slots(plan.handle))
 
 
 def sfft_export_bucket_features(plan: Plan, batch: DeviceBatch, cap: int, out: dict | None = None,

@@ -57,7 +57,7 @@ int main(int argc, char** argv) {
   P.mlp_weights = nullptr;
   const int32_t B = rd<int32_t>();
   const int32_t max_batch = rd<int32_t>();
-  const int32_t entry = rd<int32_t>();  // 0 sfft_recover
+  const int32_t entry = rd<int32_t>();  // 0 sfft_recover, 1 sfft_recover_static
   std::vector<int64_t> mode_off = rdv<int64_t>(B + 1);
   const int64_t total = mode_off[B];
   std::vector<int64_t> freqs = rdv<int64_t>((size_t)total * P.d);
@@ -94,7 +94,8 @@ int main(int argc, char** argv) {
   o.rounds = o_rounds.data();
   o.samples = o_samples.data();
   o.trace = o_trace.data();
-  st = entry == 0 ? sfft_recover(plan, &batch, &o, nullptr) : SFFT_EINVAL;
+  st = entry == 1 ? sfft_recover_static(plan, &batch, &o, nullptr)
+                  : sfft_recover(plan, &batch, &o, nullptr);
   st32 = st;
   fwrite(&st32, 4, 1, out);
   if (st != SFFT_OK) fprintf(stderr, "[emu] recover: %s\n", sfft_last_error());

@@ -62,6 +62,8 @@ CASES = [
     ("c3_fp32_noisy", "asan", "c3b", {}, 2, 60, 1e-5, 0),
     ("c3_fp32_noisy", "tsan", "c3b", {}, 2, 60, 1e-5, 0),
     ("c3_fp32_residual_samples", "asan", "c3b", {"residual": 1}, 2, 60, 1e-5, 0),
+    ("c3_fp32_static_scratch", "asan", "c3b", {}, 2, 60, 1e-5, 1),
+    ("c3_fp32_static_scratch", "tsan", "c3b", {}, 2, 60, 1e-5, 1),
     ("c2_fp32", "asan", "c2", {}, 1, 64, 1e-5, 0),
     ("c1_fp64_tilt", "asan", "c1", {"tilt": True}, 2, 8, 1e-9, 0),
     ("e3_fp64_partition", "asan", "e3", {}, 1, 30, 1e-9, 0),
