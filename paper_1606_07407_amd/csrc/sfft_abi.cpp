@@ -349,6 +349,16 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
       lds = std::max(lds, align16((size_t)kp.p_vmax * cs) + align16(2 * (size_t)(kp.m_max + 4)) +
                               (size_t)kp.m_max * cs + 4 * (size_t)kWG * cs);  // verification
   }
+  // FP32 spectrum subtraction staged through LDS: as many sets per block (up to 8) as
+  // fit in what the other steps already need, so that the stage never sets the size
+  if (P.precision == SFFT_FP32 && P.residual == SFFT_RESIDUAL_SPECTRUM) {
+    const size_t fixed = align16(4 * ((size_t)kp.p_max + 1 + kp.cap)) + 16 * (size_t)kp.cap;
+    for (int cs = 8; cs >= 1; --cs)
+      if (fixed + 8 * (size_t)kp.cap * cs <= lds) {
+        kp.sub_cs = cs;
+        break;
+      }
+  }
   const size_t merge_bytes = merge_lds(kp.k_max, kp.cap).bytes;
   kp.merge_global = merge_bytes > lds ? 1 : 0;
   if (!kp.merge_global) lds = merge_bytes > lds ? merge_bytes : lds;

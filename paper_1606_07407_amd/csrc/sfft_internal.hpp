@@ -103,6 +103,7 @@ struct KParams {
   int p_vmax;             // largest prime a verification round can use
   double verify_eta;
   int residual;           // 0: registry subtracted from the spectra, 1: from the samples
+  int sub_cs;             // FP32 spectrum subtraction: sets per LDS-staged block (0: unstaged)
   int sched_nt[kNtBands]; // sampler column tiles per wave per p band (0: built-in choice)
   int sched_fft;          // kFftRadix24Head or kFftRadix8Head
   int sched_dft_batch;    // FP32: most sets per batched Bluestein pass (0: all that fit)

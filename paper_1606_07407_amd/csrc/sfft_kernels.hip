@@ -569,13 +569,100 @@ __device__ void subtract_registry_f32(const KParams& kp, char* slot, WgState& st
   __syncthreads();
 }
 
+// FP32 plans whose LDS holds it (kp.sub_cs > 0): the entries are grouped by
+// bucket with a counting sort (counts, exclusive scan, placement by atomic cursors,
+// then each bucket's few entries put back in registry order), and the sets are
+// taken kp.sub_cs at a time: the shift phases of every entry for those sets are
+// first copied from the per-slot cache into LDS (independent loads, all in flight
+// together), then one item per (bucket, set) sums its entries from LDS.  The sums
+// run over each bucket's entries in registry order, as in the sorted form above.
+__device__ void subtract_registry_f32_staged(const KParams& kp, char* slot, WgState& st,
+                                             char* lds, cpx<float>* V, int vstride, int nsets,
+                                             int* sh_part) {
+  const int nR = st.nR;
+  const int p = st.p, d2 = kp.d2, m0 = st.m0, S = kp.S, CS = kp.sub_cs;
+  const int64_t* sy = reg_y(kp, slot, st.sb);
+  const double2* sa = reg_a(kp, slot, st.sb);
+  const cpx<float>* sE = reg_E(kp, slot, st.sb);
+  const int* ord = reg_ord(kp, slot, st.cur);
+  // LDS: cursors c[p + 1] | entries grouped by bucket [cap] (registry position, then
+  // slot) | coefficients [cap] (first the entries' buckets) | phases [cap][CS]
+  int* c = reinterpret_cast<int*>(lds);
+  int* list = c + (p + 1);
+  double2* asort = reinterpret_cast<double2*>(lds + align16(4 * ((size_t)p + 1 + kp.cap)));
+  int* hb = reinterpret_cast<int*>(asort);
+  cpx<float>* Es = reinterpret_cast<cpx<float>*>(asort + kp.cap);
+  for (int h = threadIdx.x; h <= p; h += kWG) c[h] = 0;
+  __syncthreads();
+  const double inv_pd = 1.0 / (double)p;
+  for (int e = threadIdx.x; e < nR; e += kWG) {
+    int h = pmod_small(sy[(size_t)ord[e] * d2 + m0], p, inv_pd);
+    h = min(max(h, 0), p - 1);
+    hb[e] = h;
+    atomicAdd(&c[h], 1);
+  }
+  __syncthreads();
+  block_exscan(c, p + 1, sh_part);
+  // placement: afterwards c[h] is the end of bucket h (the start of bucket h + 1)
+  for (int e = threadIdx.x; e < nR; e += kWG) list[atomicAdd(&c[hb[e]], 1)] = e;
+  __syncthreads();
+  for (int h = threadIdx.x; h < p; h += kWG) {
+    const int b0 = (h == 0) ? 0 : c[h - 1], b1 = c[h];
+    for (int g = b0 + 1; g < b1; ++g) {
+      const int v = list[g];
+      int q = g - 1;
+      while (q >= b0 && list[q] > v) {
+        list[q + 1] = list[q];
+        --q;
+      }
+      list[q + 1] = v;
+    }
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < nR; g += kWG) {
+    const int sl = ord[list[g]];
+    list[g] = sl;
+    asort[g] = sa[sl];
+  }
+  __syncthreads();
+  const double pd = (double)p;
+  for (int s0 = 0; s0 < nsets; s0 += CS) {
+    const int cs = min(CS, nsets - s0);
+    for (int q = threadIdx.x; q < nR * cs; q += kWG) {
+      const int g = q / cs, u = q - g * cs;
+      const int s = s0 + u;
+      Es[(size_t)g * CS + u] = (s > 0) ? sE[(size_t)list[g] * S + s - 1] : cmk<float>(1.f, 0.f);
+    }
+    __syncthreads();
+    // set index fastest: neighbouring threads read neighbouring phases
+    for (int q = threadIdx.x; q < p * cs; q += kWG) {
+      const int h = q / cs, u = q - h * cs;
+      const int b0 = (h == 0) ? 0 : c[h - 1], b1 = c[h];
+      if (b1 == b0) continue;
+      double ax = 0.0, ay = 0.0;
+      for (int g = b0; g < b1; ++g) {
+        const cpx<float> E = Es[(size_t)g * CS + u];
+        const double2 a = asort[g];
+        ax += a.x * (double)E.x - a.y * (double)E.y;
+        ay += a.x * (double)E.y + a.y * (double)E.x;
+      }
+      cpx<float>* v = V + (size_t)(s0 + u) * vstride + h;
+      *v = cmk<float>((float)((double)v->x - pd * ax), (float)((double)v->y - pd * ay));
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __device__ void subtract_registry(const KParams& kp, char* slot, WgState& st, char* lds,
                                   cpx<T>* V, int vstride, int nsets, int* sh_part) {
   const int nR = st.nR;
   if (nR == 0) return;
   if constexpr (sizeof(T) == 4) {
-    subtract_registry_f32(kp, slot, st, lds, V, vstride, nsets, sh_part);
+    if (kp.sub_cs > 0)
+      subtract_registry_f32_staged(kp, slot, st, lds, V, vstride, nsets, sh_part);
+    else
+      subtract_registry_f32(kp, slot, st, lds, V, vstride, nsets, sh_part);
     return;
   }
   const int p = st.p, d2 = kp.d2, m0 = st.m0;
