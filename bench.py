@@ -319,14 +319,14 @@ def main_part_share(sfft, plan, db, B) -> float:
 def paper_sweep(sfft, steps: int, warmup: int, name: str = "e1") -> list:
     """The paper's experiment (Section 5) at d = 100 ("e1") or d = 1000 ("e2"): d1 = 5,
     N = 20, c = 5, unit-magnitude random-phase coefficients, noiseless, FP64 end to end;
-    one batch of 100 trials (signals) per k = 2^0 .. 2^9.  Per k: exact-support rate,
+    one batch of 100 trials (signals) per k = 2^0 .. 2^10.  Per k: exact-support rate,
     largest coefficient error against the planted values, rounds, samples (and
     samples / (d k), which the paper's analysis keeps bounded), launch time and its
     main part."""
     cfg = workloads.config(name)
     B = cfg["B"]
     rows = []
-    for j in range(10):
+    for j in range(11):
         k = 2 ** j
         pb = workloads.planted_batch(cfg["seed"] + j, B, cfg["d"], cfg["N"], k, cfg["mag"], 0.0)
         db = sfft.DeviceBatch.from_planted(pb)

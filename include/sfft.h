@@ -202,7 +202,11 @@ typedef struct {
 /* Create a plan: validates `params` (SFFT_EINVAL / SFFT_ERANGE), derives the
  * prime tables, the largest prime any round can use and the DFT sizes, and
  * allocates all device workspace for up to `max_batch` signals on the
- * current device (SFFT_ENOMEM).  `*out` is set only on SFFT_OK. */
+ * current device (SFFT_ENOMEM).  `*out` is set only on SFFT_OK.  Primes reach
+ * 16384 (FP32) or 8192 (FP64): Bluestein lengths up to 16384 / 8192 points stay
+ * in LDS, longer ones (up to twice that) run as two in-LDS halves through the
+ * workspace.  SFFT_ERANGE also when a step's LDS carve-up at the largest prime
+ * exceeds the work-group's LDS. */
 sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_plan* out);
 
 /* Release a plan and its workspace (synchronises the device first).  NULL is

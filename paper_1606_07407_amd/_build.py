@@ -18,6 +18,11 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # calls between device functions keep the standard calling convention (callee-saved
+    # registers) instead of inter-procedural register allocation: with it, a kernel that
+    # calls a 256-VGPR function must assume every register that function touches is lost
+    # and spills its own long-lived values around the call
+    "-mllvm", "-enable-ipra=false",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -282,11 +282,12 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.verify_eta = (P.verify_eta > 0.0) ? P.verify_eta : P.eta;
 
   // Largest prime a round can use: the max_rounds-th rule prime >= max(ceil(c k_max), p_min),
-  // clamped to what the in-LDS DFT holds (Bluestein length 2p - 1 <= maxL).  A round that
-  // would need a larger prime (k* still near k_max after many rounds) ends its signal with
-  // SFFT_ERANGE; the first round must fit.
-  const int maxL = (P.precision == SFFT_FP32) ? 16384 : 8192;
-  const int64_t p_lim = (maxL + 1) / 2;
+  // clamped to what the DFT holds (Bluestein length 2p - 1 <= kBluesteinParts maxL: LDS
+  // holds FFTs of up to maxL points, longer ones run in parts through the slot).  A round
+  // that would need a larger prime (k* still near k_max after many rounds) ends its signal
+  // with SFFT_ERANGE; the first round must fit.
+  const int maxL = (P.precision == SFFT_FP32) ? kLdsFftMax32 : kLdsFftMax64;
+  const int64_t p_lim = ((int64_t)kBluesteinParts * maxL + 1) / 2;
   const double xd = std::max(std::ceil(P.c * (double)P.k_max), (double)P.p_min);
   if (xd > 40000.0) return fail(SFFT_ERANGE, "c * k_max = %.0f is beyond the prime range", xd);
   const int64_t x = (int64_t)xd;
@@ -305,7 +306,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   }
   if (found == 0)
     return fail(SFFT_ERANGE,
-                "the first round needs a prime >= %lld; the in-LDS DFT holds primes up to %lld",
+                "the first round needs a prime >= %lld; the DFT holds primes up to %lld",
                 (long long)x, (long long)p_lim);
   kp.p_max = (int)pmax;
   int L = 1, lg = 0;
@@ -321,19 +322,31 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   // LDS: the largest of the per-step carve-ups.  The merge/sort arrays stay in
   // LDS unless they would be the largest; then they live in the slot.
   size_t lds = 0;
-  lds = std::max(lds, (size_t)lds_padded(L) * cs + (size_t)kTwiddleEntries * cs);  // DFT buffer + twiddles
-  lds = std::max(lds, align16((size_t)kp.p_max * cs) + 2 * align16(2 * (size_t)(kp.m_max + 4)) +
-                          (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0));  // sampler
-  lds = std::max(lds, (size_t)kp.p_max * 12 + 4 * 256 + 16);             // selection
-  lds = std::max(lds, decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max);  // decode / export
+  const char* lds_step = "";
+  auto need = [&](size_t bytes, const char* step) {
+    if (bytes > lds) {
+      lds = bytes;
+      lds_step = step;
+    }
+  };
+  {
+    // FFT buffer (at most maxL points) and twiddle tables
+    const int Mx = std::min(L, maxL);
+    need((size_t)(lds_padded(Mx) + bs_tab_entries(L, Mx)) * cs, L > maxL ? "DFT (in parts)" : "DFT");
+  }
+  need(align16((size_t)kp.p_max * cs) + 2 * align16(2 * (size_t)(sampler_m_max(kp) + 4)) +
+           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0),
+       "sampler");
+  need(align16((size_t)kp.p_max * (cs / 2)) + 4 * (size_t)kp.p_max + 4 * 256 + 16, "selection");
+  need(decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max, "decode");
   {
     size_t n2 = 1;
     while (n2 < (size_t)kp.cap) n2 <<= 1;
-    lds = std::max(lds, 4 * ((size_t)kp.p_max + 1 + 2 * (size_t)kp.cap));  // registry subtraction
-    lds = std::max(lds, align16(4 * ((size_t)kp.p_max + 1 + n2)) +
-                            16 * (size_t)kp.cap);                          // (FP32: sorted entries)
+    need(4 * ((size_t)kp.p_max + 1 + 2 * (size_t)kp.cap), "registry subtraction");
+    need(align16(4 * ((size_t)kp.p_max + 1 + n2)) + 16 * (size_t)kp.cap,
+         "registry subtraction (sorted entries)");
   }
-  lds = std::max(lds, 4 * (size_t)kp.k_max);                             // output
+  need(4 * (size_t)kp.k_max, "output");
   {
     // verification rounds use the prime for k* = 1: the max_rounds-th table prime
     // >= max(ceil(c), p_min)
@@ -346,8 +359,9 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
         ++cntv;
       }
     if (P.verify)
-      lds = std::max(lds, align16((size_t)kp.p_vmax * cs) + align16(2 * (size_t)(kp.m_max + 4)) +
-                              (size_t)kp.m_max * cs + 4 * (size_t)kWG * cs);  // verification
+      need(align16((size_t)kp.p_vmax * cs) + align16(2 * (size_t)(kp.m_max + 4)) +
+               (size_t)kp.m_max * cs + 4 * (size_t)kWG * cs,
+           "verification");
   }
   // FP32 spectrum subtraction staged through LDS: as many sets per block (up to 8) as
   // fit in what the other steps already need, so that the stage never sets the size
@@ -361,10 +375,11 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   }
   const size_t merge_bytes = merge_lds(kp.k_max, kp.cap).bytes;
   kp.merge_global = merge_bytes > lds ? 1 : 0;
-  if (!kp.merge_global) lds = merge_bytes > lds ? merge_bytes : lds;
+  if (!kp.merge_global) need(merge_bytes, "merge");
   lds = align16(lds);
   if (lds > 160 * 1024 - 4096)
-    return fail(SFFT_ERANGE, "plan needs %zu bytes of LDS per work-group", lds);
+    return fail(SFFT_ERANGE, "plan needs %zu bytes of LDS per work-group (%s step, largest "
+                "prime %d)", lds, lds_step, kp.p_max);
   kp.lds_bytes = (int)lds;
 
   // Workspace layout of one slot.
@@ -385,6 +400,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   lay.V = o;      o = al256(o + cs * (size_t)S1 * kp.vstride);
   lay.chirp = o;  o = al256(o + cs * (size_t)kp.p_max);
   lay.bhat = o;   o = al256(o + cs * (size_t)L);
+  lay.big = o;    o = al256(o + (L > maxL ? cs * (size_t)L : 0));
   lay.cand = o;   o = al256(o + 4 * (size_t)kp.k_max);
   lay.acc_y = o;  o = al256(o + 8 * (size_t)kp.k_max * d2);
   lay.acc_a = o;  o = al256(o + 16 * (size_t)kp.k_max);

@@ -40,16 +40,19 @@ __device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) {
   return cmk<T>(a.x * s, a.y * s);
 }
 
-// Largest power-of-two DFT length kept in LDS for each precision.
+// Largest power-of-two FFT length kept in LDS for each precision: 32 complex
+// values per thread in the register-held Stockham pass (FP32 8192, FP64 4096
+// points).  Longer Bluestein lengths (up to 4 times these) run in parts
+// through the workspace (bluestein_run).
 template <typename T>
 struct MaxL;
 template <>
 struct MaxL<float> {
-  static constexpr int value = 16384;
+  static constexpr int value = kLdsFftMax32;
 };
 template <>
 struct MaxL<double> {
-  static constexpr int value = 8192;
+  static constexpr int value = kLdsFftMax64;
 };
 
 // exp(i pi x) in FP64 for a dyadic/rational x given as q / den, q exact.
@@ -377,27 +380,11 @@ __device__ __forceinline__ void fft_lds_v(cpx<T>* buf, int L, int log2L, const c
   }
 }
 
-// The largest lengths: their register-held pass needs twice the registers.
-// Inlined like every device function the persistent kernels call: out-of-line
-// calls from those 256-VGPR kernels gave wrong results on the GPU in some
-// register-allocation states (the same source with these helpers inlined
-// passed, out of line failed), so the kernels make no calls.
-template <typename T>
-__device__ __forceinline__ void fft_lds_large(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
-                                           const cpx<T>* T2, bool inv, int fs) {
-  fft_lds_v<T, MaxL<T>::value / kWG>(buf, L, log2L, T1, T2, inv, fs);
-}
-
-// L <= MaxL<T>.  Lengths up to half the maximum take the inlined variant with
-// half the per-thread registers.
+// L <= MaxL<T>.
 template <typename T>
 __device__ __forceinline__ void fft_lds(cpx<T>* buf, int L, int log2L, const cpx<T>* T1,
                                         const cpx<T>* T2, bool inv, int fs) {
-  constexpr int HALF = MaxL<T>::value / 2 / kWG;
-  if (L <= HALF * kWG)
-    fft_lds_v<T, HALF>(buf, L, log2L, T1, T2, inv, fs);
-  else
-    fft_lds_large<T>(buf, L, log2L, T1, T2, inv, fs);
+  fft_lds_v<T, MaxL<T>::value / kWG>(buf, L, log2L, T1, T2, inv, fs);
 }
 
 // Element-wise Bluestein steps with the global loads of U consecutive thread
@@ -469,69 +456,186 @@ __device__ __forceinline__ void bs_chirp_out(cpx<T>* x0, int vstride, int G, int
   }
 }
 
-// Bluestein set-up for prime length p and power-of-two L >= 2p - 1:
-// chirp[n] = exp(-i pi (n^2 mod 2p) / p) and bhat = FFT_L(b),
-// b[n] = conj(chirp[n]) for |n| < p (wrapped mod L), 0 elsewhere.  Also
-// fills the LDS twiddle tables that follow the L-point buffer.
+// ------------------------------------------------ Bluestein prime DFT ----
+// X[h] = sum_n x[n] exp(-2 pi i h n / p) for prime p as the cyclic convolution
+// X = chirp . IFFT_L(FFT_L(x . chirp) . bhat) / L with L a power of two >= 2p - 1,
+// chirp[n] = exp(-i pi (n^2 mod 2p) / p) and bhat = FFT_L(b), b[n] =
+// conj(chirp[|n|]) for |n| < p (indices mod L), 0 elsewhere.
+//
+// L-point transforms up to MaxL<T> run in LDS (R = 1).  Longer ones (L = R M,
+// M = MaxL<T>, R = 2 or 4) run as R in-LDS M-point FFTs: decimation in time
+// splits the forward transform into the FFTs of the points x[R m + r], kept in
+// the slot buffer G (row r of M points each); one element-wise pass over k < M
+// finishes it with the R-point butterflies X[k + j M] = sum_r W_R^{rj} W^{rk}
+// G_r[k] (W = exp(-2 pi i / L)), multiplies by the filter spectrum and starts
+// the inverse transform by decimation in frequency, a_r[k] = W^{-rk} sum_j
+// W_R^{-rj} Z[k + j M]; the inverse M-point FFTs of the rows a_r are the points
+// R m + r of the convolution.
 template <typename T>
-__device__ void bluestein_setup(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
-                                cpx<T>* buf, int fs) {
-  const int tid = threadIdx.x;
-  cpx<T>* T1 = buf + lp(L);
-  cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
-  twiddle_tables<T>(L, T1, T2);
-  for (int n = tid; n < p; n += kWG) {
-    const int64_t q = ((int64_t)n * n) % (2 * (int64_t)p);
-    double c, s;
-    expipi(-(double)q / (double)p, &c, &s);
-    chirp[n] = cmk<T>((T)c, (T)s);
-  }
-  __syncthreads();
-  for (int n = tid; n < L; n += kWG) {
-    cpx<T> v = cmk<T>(0, 0);
-    if (n < p) {
-      v = chirp[n];
-    } else if (n > L - p) {
-      v = chirp[L - n];
-    }
-    v.y = -v.y;
-    buf[lp(n)] = v;
-  }
-  __syncthreads();
-  fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
-  for (int n = tid; n < L; n += kWG) bhat[n] = buf[lp(n)];
-  __syncthreads();
+struct BsTabs {
+  const cpx<T>* T1M;  // twiddle tables of the M-point FFT
+  const cpx<T>* T2M;
+  const cpx<T>* T1L;  // of the L-point butterflies (R > 1)
+  const cpx<T>* T2L;
+};
+
+template <typename T>
+__device__ __forceinline__ BsTabs<T> bs_tables(int L, int M, cpx<T>* tab) {
+  cpx<T>* t1m = tab;
+  cpx<T>* t2m = t1m + ((M >> kTwiddleBits) > 0 ? (M >> kTwiddleBits) : 1);
+  cpx<T>* t1l = t2m + (1 << kTwiddleBits);
+  cpx<T>* t2l = t1l + (L >> kTwiddleBits);
+  twiddle_tables<T>(M, t1m, t2m);
+  if (L > M) twiddle_tables<T>(L, t1l, t2l);
+  BsTabs<T> tb;
+  tb.T1M = t1m;
+  tb.T2M = t2m;
+  tb.T1L = t1l;
+  tb.T2L = t2l;
+  return tb;
 }
 
-// In-place DFT of one prime-length sequence x (global) via Bluestein:
-// X[k] = chirp[k] * IFFT_L(FFT_L(x . chirp) . bhat)[k] / L.  Uses the LDS
-// twiddle tables written by bluestein_setup.
-template <typename T>
-__device__ void bluestein_dft(cpx<T>* x, int p, int L, int log2L, const cpx<T>* chirp,
-                              const cpx<T>* bhat, cpx<T>* buf, int fs) {
-  const int tid = threadIdx.x;
-  const cpx<T>* T1 = buf + lp(L);
-  const cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
-  if constexpr (sizeof(T) == 4) {
-    bs_chirp_in<T>(buf, x, 0, L, p, L, log2L, chirp);
-    __syncthreads();
-    fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
-    bs_filter<T>(buf, L, L, bhat);
-    __syncthreads();
-    fft_lds<T>(buf, L, log2L, T1, T2, true, fs);
-    bs_chirp_out<T>(x, 0, 1, p, L, buf, chirp);
-    __syncthreads();
+// The R-point butterflies of the element-wise pass at k (R = 2 or 4): with
+// filter = true the whole middle step on G (forward butterflies, filter,
+// inverse butterflies); with filter = false the forward butterflies alone,
+// written to out (the filter spectrum's set-up).
+template <typename T, int R>
+__device__ __forceinline__ void bs_middle(cpx<T>* G, int M, int k, const cpx<T>* bhat,
+                                          cpx<T>* out, bool filter, const BsTabs<T>& tb) {
+  cpx<T> g[R], w[R];
+  w[0] = cmk<T>(1, 0);
+  g[0] = G[k];
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    w[r] = twiddle(tb.T1L, tb.T2L, r * k);
+    g[r] = cmul(G[(size_t)r * M + k], w[r]);
+  }
+  butterfly<T, R>(g, false);
+  if (!filter) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) out[(size_t)j * M + k] = g[j];
     return;
   }
-  for (int n = tid; n < L; n += kWG) buf[lp(n)] = (n < p) ? cmul(x[n], chirp[n]) : cmk<T>(0, 0);
-  __syncthreads();
-  fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
-  for (int n = tid; n < L; n += kWG) buf[lp(n)] = cmul(buf[lp(n)], bhat[n]);
-  __syncthreads();
-  fft_lds<T>(buf, L, log2L, T1, T2, true, fs);
+#pragma unroll
+  for (int j = 0; j < R; ++j) g[j] = cmul(g[j], bhat[(size_t)j * M + k]);
+  butterfly<T, R>(g, true);
+  G[k] = g[0];
+#pragma unroll
+  for (int r = 1; r < R; ++r) G[(size_t)r * M + k] = cmul(g[r], cmk<T>(w[r].x, -w[r].y));
+}
+
+// setup = true: writes chirp (p points) and bhat (L points); x is not used.
+// setup = false: the DFT of x (p points, global) in place with them.  R = L / M
+// is 1, 2 or 4; G (L points, global) is used only when R > 1.  Every FFT of the
+// step goes through the one forward fft_lds call below: the inverse transforms
+// run as conj(FFT(conj(.))), the conjugations folded into the loads and stores.
+template <typename T>
+__device__ __noinline__ void bluestein_run(bool setup, cpx<T>* x, int p, int L, int R,
+                                              int log2M, cpx<T>* chirp, cpx<T>* bhat,
+                                              cpx<T>* G, cpx<T>* buf, const BsTabs<T>& tb,
+                                              int fs) {
+  const int M = L / R;
+  const int tid = threadIdx.x;
+  if (setup) {
+    for (int n = tid; n < p; n += kWG) {
+      const int64_t q = ((int64_t)n * n) % (2 * (int64_t)p);
+      double c, s;
+      expipi(-(double)q / (double)p, &c, &s);
+      chirp[n] = cmk<T>((T)c, (T)s);
+    }
+    __syncthreads();
+  }
   const T invL = (T)1 / (T)L;
-  for (int n = tid; n < p; n += kWG) x[n] = cscale(cmul(buf[lp(n)], chirp[n]), invL);
-  __syncthreads();
+  const int passes = setup ? R : 2 * R;
+  for (int it = 0; it < passes; ++it) {
+    const bool inv = it >= R;
+    const int r = it & (R - 1);
+    if (R > 1 && it == R) {
+      for (int k = tid; k < M; k += kWG) {
+        if (R == 2)
+          bs_middle<T, 2>(G, M, k, bhat, nullptr, true, tb);
+        else
+          bs_middle<T, 4>(G, M, k, bhat, nullptr, true, tb);
+      }
+      __syncthreads();
+    }
+    if (R > 1 || !inv) {
+      // (R = 1, inverse: the filtered spectrum is already in buf)
+      for (int m0 = tid; m0 < M; m0 += kLoadBlock * kWG) {
+        cpx<T> v[kLoadBlock];
+#pragma unroll
+        for (int u = 0; u < kLoadBlock; ++u) {
+          const int m = m0 + u * kWG, n = R * m + r;
+          cpx<T> a = cmk<T>(0, 0);
+          if (m < M) {
+            if (inv) {
+              a = G[(size_t)r * M + m];
+              a.y = -a.y;
+            } else if (setup) {
+              if (n < p) a = chirp[n];
+              else if (n > L - p) a = chirp[L - n];
+              a.y = -a.y;
+            } else if (n < p) {
+              a = cmul(x[n], chirp[n]);
+            }
+          }
+          v[u] = a;
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBlock; ++u) {
+          const int m = m0 + u * kWG;
+          if (m < M) buf[lp(m)] = v[u];
+        }
+      }
+      __syncthreads();
+    }
+    fft_lds<T>(buf, M, log2M, tb.T1M, tb.T2M, false, fs);
+    for (int m0 = tid; m0 < M; m0 += kLoadBlock * kWG) {
+      cpx<T> f[kLoadBlock];
+#pragma unroll
+      for (int u = 0; u < kLoadBlock; ++u) {
+        const int m = m0 + u * kWG, n = R * m + r;
+        f[u] = cmk<T>(0, 0);
+        if (m < M) {
+          if (inv) {
+            if (n < p) f[u] = chirp[n];
+          } else if (R == 1 && !setup) {
+            f[u] = bhat[m];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadBlock; ++u) {
+        const int m = m0 + u * kWG, n = R * m + r;
+        if (m < M) {
+          cpx<T> v = buf[lp(m)];
+          if (inv) {
+            v.y = -v.y;
+            if (n < p) x[n] = cscale(cmul(v, f[u]), invL);
+          } else if (R > 1) {
+            G[(size_t)r * M + m] = v;
+          } else if (setup) {
+            bhat[m] = v;
+          } else {
+            // filtered, and conjugated for the inverse transform that follows
+            v = cmul(v, f[u]);
+            v.y = -v.y;
+            buf[lp(m)] = v;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (setup && R > 1) {
+    for (int k = tid; k < M; k += kWG) {
+      if (R == 2)
+        bs_middle<T, 2>(G, M, k, nullptr, bhat, false, tb);
+      else
+        bs_middle<T, 4>(G, M, k, nullptr, bhat, false, tb);
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------- batched small DFTs (FP32) ------
@@ -632,38 +736,6 @@ __device__ __forceinline__ void fft_lds_batch(cpx<T>* buf, int L, int log2L, int
   }
 }
 
-// Bluestein set-up with the twiddle tables at `tab` (outside the batch area):
-// chirp and the filter spectrum bhat as in bluestein_setup.
-template <typename T>
-__device__ __forceinline__ void bluestein_setup_at(int p, int L, int log2L, cpx<T>* chirp, cpx<T>* bhat,
-                                   cpx<T>* buf, cpx<T>* tab, int fs) {
-  const int tid = threadIdx.x;
-  cpx<T>* T1 = tab;
-  cpx<T>* T2 = T1 + ((L >> kTwiddleBits) > 0 ? (L >> kTwiddleBits) : 1);
-  twiddle_tables<T>(L, T1, T2);
-  for (int n = tid; n < p; n += kWG) {
-    const int64_t q = ((int64_t)n * n) % (2 * (int64_t)p);
-    double c, s;
-    expipi(-(double)q / (double)p, &c, &s);
-    chirp[n] = cmk<T>((T)c, (T)s);
-  }
-  __syncthreads();
-  for (int n = tid; n < L; n += kWG) {
-    cpx<T> v = cmk<T>(0, 0);
-    if (n < p) {
-      v = chirp[n];
-    } else if (n > L - p) {
-      v = chirp[L - n];
-    }
-    v.y = -v.y;
-    buf[lp(n)] = v;
-  }
-  __syncthreads();
-  fft_lds<T>(buf, L, log2L, T1, T2, false, fs);
-  for (int n = tid; n < L; n += kWG) bhat[n] = buf[lp(n)];
-  __syncthreads();
-}
-
 // G sequences x_g = x0 + g vstride (length p) transformed together, in place.
 template <typename T, int MAXV>
 __device__ __forceinline__ void bluestein_dft_batch(cpx<T>* x0, int vstride, int G, int p, int L, int log2L,
@@ -698,9 +770,9 @@ __device__ __forceinline__ int mulmod(uint32_t h, uint32_t r, int p, float inv_p
   return (int)rem;
 }
 
-// The same with 24-bit multiplies, for p <= 2^13 and h < p + 128 (what the FP32
-// sampler uses): h * r < 2^27, and the FP32 quotient estimate (relative error
-// about 2^-23 on a quotient below 2^14) is off by at most one.
+// The same with 24-bit multiplies, for p <= 2^14 and h < p + 128 (what the FP32
+// sampler uses): h * r < 2^28.1, and the FP32 quotient estimate (absolute error
+// below 0.01 on a quotient below 2^14 + 128) is off by at most one.
 __device__ __forceinline__ uint32_t mulmod24(uint32_t h, uint32_t r, uint32_t p, float inv_p) {
   const uint32_t x = __umul24(h, r);
   const uint32_t q = (uint32_t)(int)((float)x * inv_p);

@@ -12,7 +12,17 @@ constexpr int kMaxD2 = 256;       // largest number of unwrapped coordinates (FP
 constexpr int kMaxRT = 8;         // MFMA row tiles: 2 (S+1) real rows <= 128
 constexpr int kChunk = 16;        // sampler: A-fragment pairs staged in LDS per chunk
 constexpr int kTwiddleBits = 6;   // DFT twiddles exp(-2 pi i t / L) = T1[t >> 6] * T2[t & 63]
-constexpr int kTwiddleEntries = 64 + 16384 / 64;  // LDS entries of T1 and T2 for L <= 16384
+// Largest FFT lengths held in LDS (FP32, FP64); Bluestein lengths up to 4 times
+// these run in 2 or 4 parts through the workspace.
+constexpr int kLdsFftMax32 = 8192;
+constexpr int kLdsFftMax64 = 4096;
+constexpr int kBluesteinParts = 4;
+// LDS entries of the Bluestein twiddle tables for an L-point convolution whose
+// FFTs have M points (M-point pair, then the L-point pair when L > M).
+__host__ __device__ inline int bs_tab_entries(int L, int M) {
+  const int n1m = (M >> kTwiddleBits) > 0 ? (M >> kTwiddleBits) : 1;
+  return n1m + (1 << kTwiddleBits) + (L > M ? (L >> kTwiddleBits) + (1 << kTwiddleBits) : 0);
+}
 // FFT radix schedules of a power-of-two length L = 2^n (n = 4 q + b): radix-2
 // (b odd) and radix-4 (b >= 2) head passes, then radix 16; or, when b = 3,
 // one radix-8 head pass in place of the radix-2 and radix-4 ones.
@@ -68,6 +78,7 @@ struct WsLayout {
   size_t V;        // cplx T [S1][vstride]      samples, then spectra
   size_t chirp;    // cplx T [p_max]            Bluestein chirp
   size_t bhat;     // cplx T [L_max]            DFT of the chirp filter
+  size_t big;      // cplx T [L_max]            halves of a DFT longer than LDS holds (else empty)
   size_t cand;     // int32  [k_max]            candidate buckets
   size_t acc_y;    // int64  [k_max][d2]        decoded frequencies
   size_t acc_a;    // double2[k_max]            decoded coefficients
@@ -119,6 +130,12 @@ struct KParams {
   int tilt;
   int64_t ta, tb, tc2;
 };
+
+// Modes the sampler's LDS residue arrays hold: the planted modes, plus the
+// registry when the residual is subtracted from the samples.
+__host__ __device__ inline int sampler_m_max(const KParams& kp) {
+  return kp.residual == 1 ? kp.m_max : 2 * ((kp.k_max + 1) / 2);
+}
 
 struct KBatch {
   int B;

@@ -11,6 +11,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "sfft_device.hpp"
 #include "sfft_internal.hpp"
@@ -255,12 +256,13 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   const int nreg = (kp.residual == 1) ? st.nslots : 0;
   const int npairs = P0 + (nreg + 1) / 2;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
-  // residues and column steps fit 16 bits (p <= 8192)
+  // residues and column steps fit 16 bits (p <= 16384)
+  const int msm = sampler_m_max(kp);
   uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
   uint16_t* rs = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(rr) +
-                                             align16(2 * (size_t)(kp.m_max + 4)));
+                                             align16(2 * (size_t)(msm + 4)));
   float* abuf = reinterpret_cast<float*>(reinterpret_cast<char*>(rs) +
-                                         align16(2 * (size_t)(kp.m_max + 4)));
+                                         align16(2 * (size_t)(msm + 4)));
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
   const int64_t* ry = reg_y(kp, slot, st.sb);
   for (int x = threadIdx.x; x < p; x += kWG) {
@@ -442,26 +444,33 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
   cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
   cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
+  constexpr int ML = MaxL<T>::value;
+  const int R = st.L > ML ? st.L / ML : 1;  // parts through the slot beyond the LDS maximum
+  const int M = st.L / R;
+  // FP32: sets of short lengths are transformed together, the twiddle tables then
+  // sitting after the whole buffer (L_max points, at most the in-LDS maximum) so
+  // that up to min(L_max, 8192) / L sets fit
+  constexpr int MAXV = MaxL<T>::value / kWG;
+  const int Lb = min(kp.L_max, ML);
+  const bool batched = sizeof(T) == 4 && R == 1 && kp.sched_dft_batch != 1 &&
+                       st.L <= MAXV * kWG && 2 * st.L <= Lb;
+  const BsTabs<T> tb = bs_tables<T>(st.L, M, buf + lds_padded(batched ? Lb : M));
+  cpx<T>* G = ws_cpx<T>(slot, kp.lay.big);
+  // s = -1 computes chirp and filter; one call site for every FFT of the step
+  for (int s = -1; s < (batched ? 0 : nsets); ++s)
+    bluestein_run<T>(s < 0, s < 0 ? nullptr : V + (size_t)s * vstride, st.p, st.L, R,
+                     st.log2L - (R >> 1), chirp, bhat, G, buf, tb, kp.sched_fft);
   if constexpr (sizeof(T) == 4) {
-    // FP32: the twiddle tables sit after the whole L_max buffer so that up to
-    // min(L_max, 8192) / L sets are transformed together
-    constexpr int MAXV = MaxL<T>::value / 2 / kWG;
-    if (kp.sched_dft_batch != 1 && st.L <= MAXV * kWG && 2 * st.L <= kp.L_max) {
-      cpx<T>* tab = buf + lds_padded(kp.L_max);
-      bluestein_setup_at<T>(st.p, st.L, st.log2L, chirp, bhat, buf, tab, kp.sched_fft);
-      int cap = min(kp.L_max, MAXV * kWG) / st.L;
+    if (batched) {
+      int cap = min(Lb, MAXV * kWG) / st.L;
       if (kp.sched_dft_batch > 1) cap = min(cap, kp.sched_dft_batch);
       for (int s0 = 0; s0 < nsets; s0 += cap) {
         const int g = min(cap, nsets - s0);
         bluestein_dft_batch<T, MAXV>(V + (size_t)s0 * vstride, vstride, g, st.p, st.L, st.log2L,
-                                     chirp, bhat, buf, tab, kp.sched_fft);
+                                     chirp, bhat, buf, tb.T1M, kp.sched_fft);
       }
-      return;
     }
   }
-  bluestein_setup<T>(st.p, st.L, st.log2L, chirp, bhat, buf, kp.sched_fft);
-  for (int s = 0; s < nsets; ++s)
-    bluestein_dft<T>(V + (size_t)s * vstride, st.p, st.L, st.log2L, chirp, bhat, buf, kp.sched_fft);
 }
 
 // ------------------------------------------- residual in the spectrum ------
@@ -723,8 +732,10 @@ template <typename T>
 __device__ void select_round(const KParams& kp, char* slot, WgState& st, char* lds,
                              const cpx<T>* F0, int* sh_part) {
   const int p = st.p;
-  uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
-  int* flag = reinterpret_cast<int*>(lds + (size_t)kp.p_max * 8);
+  // keys: the bits of |F_0| (FP32: 32, FP64: 64), 0 for buckets below the floor
+  using Key = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+  Key* keys = reinterpret_cast<Key*>(lds);
+  int* flag = reinterpret_cast<int*>(lds + align16((size_t)kp.p_max * sizeof(Key)));
   int* hist = flag + kp.p_max;  // 256 bins
   int* cand = reinterpret_cast<int*>(slot + kp.lay.cand);
   const double thr = kp.eta * (double)p;
@@ -732,13 +743,13 @@ __device__ void select_round(const KParams& kp, char* slot, WgState& st, char* l
   for (int h = threadIdx.x; h < p; h += kWG) {
     const double mag = hypot((double)F0[h].x, (double)F0[h].y);
     const int pass = (mag >= thr) ? 1 : 0;
-    uint64_t key;
+    Key key;
     if constexpr (sizeof(T) == 4) {
-      key = (uint64_t)__float_as_uint((float)mag);
+      key = __float_as_uint((float)mag);
     } else {
       key = (uint64_t)__double_as_longlong(mag);
     }
-    keys[h] = pass ? key : 0ull;
+    keys[h] = pass ? key : (Key)0;
     flag[h] = pass;
     cnt += pass;
   }
@@ -759,8 +770,9 @@ __device__ void select_round(const KParams& kp, char* slot, WgState& st, char* l
       const uint64_t himask = (pass == 7) ? 0ull : ~((1ull << (shift + 8)) - 1ull);
       const uint64_t prefix = st.prefix;
       for (int h = threadIdx.x; h < p; h += kWG) {
-        if (flag[h] && ((keys[h] ^ prefix) & himask) == 0ull)
-          atomicAdd(&hist[(int)((keys[h] >> shift) & 255ull)], 1);
+        const uint64_t kh = keys[h];
+        if (flag[h] && ((kh ^ prefix) & himask) == 0ull)
+          atomicAdd(&hist[(int)((kh >> shift) & 255ull)], 1);
       }
       __syncthreads();
       // counts from the top bin down: sh_part[t] = keys in bins >= 255 - t
@@ -786,12 +798,14 @@ __device__ void select_round(const KParams& kp, char* slot, WgState& st, char* l
     const uint64_t T_ = st.prefix;
     const int take = st.need;
     // rank among keys equal to the threshold, by ascending h
-    for (int h = threadIdx.x; h < p; h += kWG) flag[h] = (flag[h] && keys[h] == T_) ? 1 : 0;
+    for (int h = threadIdx.x; h < p; h += kWG)
+      flag[h] = (flag[h] && (uint64_t)keys[h] == T_) ? 1 : 0;
     __syncthreads();
     block_exscan(flag, p, sh_part);
     for (int h = threadIdx.x; h < p; h += kWG) {
-      const bool eq = (keys[h] == T_) && keys[h] != 0ull;
-      const bool sel = (keys[h] > T_) || (eq && flag[h] < take);
+      const uint64_t kh = keys[h];
+      const bool eq = (kh == T_) && kh != 0ull;
+      const bool sel = (kh > T_) || (eq && flag[h] < take);
       flag[h] = sel ? 1 : 0;
     }
     __syncthreads();
@@ -1881,9 +1895,20 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) d
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
   cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
   cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
-  bluestein_setup<T>(p, st.L, st.log2L, chirp, bhat, buf, kp.sched_fft);
-  for (int q = blockIdx.x; q < count; q += gridDim.x)
-    bluestein_dft<T>(data + (size_t)q * p, p, st.L, st.log2L, chirp, bhat, buf, kp.sched_fft);
+  constexpr int ML = MaxL<T>::value;
+  const int R = st.L > ML ? st.L / ML : 1;
+  const BsTabs<T> tb = bs_tables<T>(st.L, st.L / R, buf + lds_padded(st.L / R));
+  cpx<T>* G = ws_cpx<T>(slot, kp.lay.big);
+  // the first pass computes chirp and filter, then this group's sequences
+  bool setup = true;
+  for (int q = blockIdx.x; q < count;) {
+    bluestein_run<T>(setup, setup ? nullptr : data + (size_t)q * p, p, st.L, R,
+                     st.log2L - (R >> 1), chirp, bhat, G, buf, tb, kp.sched_fft);
+    if (setup)
+      setup = false;
+    else
+      q += gridDim.x;
+  }
 }
 
 __global__ void zero_queue_kernel(int* q, int64_t* count) {

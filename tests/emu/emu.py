@@ -148,9 +148,11 @@ def _params_bytes(params) -> bytes:
 
 
 def run(kind: str, params, pb, max_batch: int | None = None, entry: int = 0,
-        timeout: float = 900.0, env=None) -> dict:
+        timeout: float = 900.0, env=None, dft_x=None) -> dict:
     """Recover planted batch pb with plan parameters params (an sfft.Params) in the
-    emulation; returns the outputs as numpy arrays plus the sanitizer's stderr."""
+    emulation; returns the outputs as numpy arrays plus the sanitizer's stderr.
+    entry = 2 runs sfft_dft on the complex rows of dft_x instead (pb only fills
+    the input format) and returns them transformed under "dft"."""
     exe = build(kind)
     raw, size = _params_bytes(params)
     blocks = [] if params.blocks is None else [int(v) for v in params.blocks]
@@ -169,6 +171,10 @@ def run(kind: str, params, pb, max_batch: int | None = None, entry: int = 0,
     buf += np.asarray(pb.k, np.int32).tobytes()
     buf += np.asarray(pb.sigma, np.float64).tobytes()
     buf += struct.pack("<Q", int(pb.seed) & 0xFFFFFFFFFFFFFFFF)
+    if entry == 2:
+        x = np.asarray(dft_x, np.complex128)
+        buf += struct.pack("<ii", x.shape[1], x.shape[0])
+        buf += np.ascontiguousarray(np.stack([x.real, x.imag], -1), np.float64).tobytes()
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
         open(fin, "wb").write(bytes(buf))
@@ -196,6 +202,11 @@ def run(kind: str, params, pb, max_batch: int | None = None, entry: int = 0,
     if out["plan_status"] != 0:
         return out
     out["call_status"] = int(take(np.int32, 1)[0])
+    if entry == 2:
+        cnt, p = np.asarray(dft_x).shape
+        xo = take(np.float64, 2 * cnt * p).reshape(cnt, p, 2)
+        out["dft"] = xo[..., 0] + 1j * xo[..., 1]
+        return out
     km, d, R = params.k_max, params.d, params.max_rounds
     out["freqs"] = take(np.int64, B * km * d).reshape(B, km, d)
     co = take(np.float64, B * km * 2).reshape(B, km, 2)

@@ -4,8 +4,10 @@
 //   emu_driver IN OUT
 //
 // IN (little-endian, written by tests/emu/emu.py): the sfft_params struct bytes
-// (pointer fields ignored), the partition arrays, the batch and the entry point;
-// OUT: the call's status, then every output array of sfft_outputs.
+// (pointer fields ignored), the partition arrays, the batch and the entry point
+// (for sfft_dft also p, count and the sequences as FP64 pairs); OUT: the plan's
+// and the call's status, then every output array of sfft_outputs (sfft_dft: the
+// transformed sequences as FP64 pairs).
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -57,7 +59,7 @@ int main(int argc, char** argv) {
   P.mlp_weights = nullptr;
   const int32_t B = rd<int32_t>();
   const int32_t max_batch = rd<int32_t>();
-  const int32_t entry = rd<int32_t>();  // 0 sfft_recover, 1 sfft_recover_static
+  const int32_t entry = rd<int32_t>();  // 0 sfft_recover, 1 sfft_recover_static, 2 sfft_dft
   std::vector<int64_t> mode_off = rdv<int64_t>(B + 1);
   const int64_t total = mode_off[B];
   std::vector<int64_t> freqs = rdv<int64_t>((size_t)total * P.d);
@@ -65,6 +67,13 @@ int main(int argc, char** argv) {
   std::vector<int32_t> k = rdv<int32_t>(B);
   std::vector<double> sigma = rdv<double>(B);
   const uint64_t seed = rd<uint64_t>();
+  int32_t dft_p = 0, dft_count = 0;
+  std::vector<double> dft_x;
+  if (entry == 2) {
+    dft_p = rd<int32_t>();
+    dft_count = rd<int32_t>();
+    dft_x = rdv<double>((size_t)2 * dft_p * dft_count);
+  }
   fclose(g_in);
 
   sfft_plan plan = nullptr;
@@ -76,6 +85,22 @@ int main(int argc, char** argv) {
   if (st != SFFT_OK) {
     fprintf(stderr, "[emu] plan: %s\n", sfft_last_error());
     fclose(out);
+    return 0;
+  }
+  if (entry == 2) {
+    // the sequences in the plan's precision, transformed in place
+    const size_t n = (size_t)dft_p * dft_count;
+    const bool f32 = P.precision == SFFT_FP32;
+    std::vector<float> xf(f32 ? 2 * n : 0);
+    for (size_t i = 0; i < xf.size(); ++i) xf[i] = (float)dft_x[i];
+    st = sfft_dft(plan, f32 ? (void*)xf.data() : (void*)dft_x.data(), dft_count, dft_p, nullptr);
+    st32 = st;
+    fwrite(&st32, 4, 1, out);
+    if (st != SFFT_OK) fprintf(stderr, "[emu] dft: %s\n", sfft_last_error());
+    for (size_t i = 0; i < xf.size(); ++i) dft_x[i] = xf[i];
+    fwrite(dft_x.data(), 8, dft_x.size(), out);
+    fclose(out);
+    sfft_plan_destroy(plan);
     return 0;
   }
   sfft_signal_batch batch = {B, mode_off.data(), freqs.data(), coeffs.data(), k.data(),

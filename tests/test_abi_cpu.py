@@ -74,8 +74,8 @@ BAD = [
     (dict(d=100, d1=1), -2),                         # FP32: 2 (S+1) = 202 real rows > 128
     (dict(d=6, d1=6, N=1024), -2),                   # N^d1 = 2^60 > 2^40
     (dict(k_max=20000, c=5.0), -2),                  # primes beyond the DFT size
-    (dict(k_max=1700, c=5.0), -2),                   # first round needs p >= 8500 > 8192
-    (dict(k_max=900, c=5.0, precision=0), -2),       # FP64: p >= 4500 > 4096
+    (dict(k_max=3300, c=5.0), -2),                   # first round needs p >= 16500 > 16384
+    (dict(k_max=1700, c=5.0, precision=0), -2),      # FP64: p >= 8500 > 8192
     (dict(d=40, d1=1, ladder_K=4), -2),              # 2 (S+1) rows beyond 8 MFMA tiles
     # general partitions
     (dict(blocks=(2, 1)), -1),                       # sizes sum to 3, not d = 4

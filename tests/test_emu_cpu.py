@@ -67,6 +67,11 @@ CASES = [
     ("c2_fp32", "asan", "c2", {}, 1, 64, 1e-5, 0),
     ("c1_fp64_tilt", "asan", "c1", {"tilt": True}, 2, 8, 1e-9, 0),
     ("e3_fp64_partition", "asan", "e3", {}, 1, 30, 1e-9, 0),
+    # primes above the in-LDS DFT length: Bluestein lengths 16384 (FP64) and 32768 (FP32)
+    # run as two halves through the workspace
+    ("c1_fp64_long_dft", "asan", "c1", {"p_min": 4200}, 1, 8, 1e-9, 0),
+    ("c1_fp64_long_dft", "tsan", "c1", {"p_min": 4200}, 1, 8, 1e-9, 0),
+    ("c3_fp32_long_dft", "asan", "c3b", {"p_min": 8300}, 1, 60, 1e-5, 0),
 ]
 
 
@@ -110,3 +115,28 @@ def test_emulator_checks_fire_on_planted_defects(kind, mode, expect):
 def test_emulator_clean_kernel_passes():
     rc, err = _emu().run_planted("tsan", "clean")
     assert rc == 0, err[-2000:]
+
+
+@pytest.mark.parametrize("prec,p", [("fp64", 4093), ("fp64", 4099), ("fp64", 8191),
+                                    ("fp32", 8191), ("fp32", 8209), ("fp32", 16381)])
+def test_emulated_dft_matches_numpy(prec, p):
+    """sfft_dft under ASan at the longest in-LDS Bluestein lengths (16384 FP32, 8192
+    FP64) and beyond them, where the transforms run as two halves through the slot."""
+    from paper_1606_07407_amd import sfft
+    emu = _emu()
+    k_max = 3200 if prec == "fp32" else 1600
+    params = sfft.Params(d=2, N=64, k_max=k_max, c=5.0,
+                         precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64)
+    pb = workloads.planted_batch(1, 1, 2, 64, 1, (1.0, 2.0), 0.0)
+    rng = np.random.default_rng(p)
+    x = rng.normal(size=(2, p)) + 1j * rng.normal(size=(2, p))
+    if prec == "fp32":
+        x = x.astype(np.complex64).astype(np.complex128)
+    out = emu.run("asan", params, pb, entry=2, dft_x=x)
+    assert out["plan_status"] == 0 and out["call_status"] == 0, out["stderr"][-2000:]
+    ref = np.fft.fft(x, axis=-1)
+    L = 1 << int(np.ceil(np.log2(2 * p - 1)))
+    u = 2.0 ** -24 if prec == "fp32" else 2.0 ** -53
+    norm = np.sqrt((np.abs(x) ** 2).sum(axis=-1)).max()
+    err = np.abs(out["dft"] - ref).max()
+    assert err <= 8 * u * np.log2(L) * norm, err

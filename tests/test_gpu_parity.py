@@ -158,17 +158,18 @@ def test_sampler_matches_oracle(name, cname, over, k, p, m, nres, B):
 def test_dft_matches_numpy(prec, fsched):
     import torch
     sfft = _sfft()
-    # largest plans of each precision: Bluestein lengths up to 16384 (FP32) / 8192 (FP64),
-    # both register variants of the in-LDS FFT; both radix schedules (the radix-8 head
-    # pass differs where log2 L = 3 mod 4: L = 8, 128, 2048 below)
-    params = sfft.Params(d=2, N=64, k_max=1600 if prec == "fp32" else 800, c=5.0,
+    # largest plans of each precision: Bluestein lengths up to 32768 (FP32) / 16384 (FP64),
+    # both register variants of the in-LDS FFT and, past 16384 / 8192 points, the two
+    # halves through the workspace; both radix schedules (the radix-8 head pass differs
+    # where log2 L = 3 mod 4: L = 8, 128, 2048 below)
+    params = sfft.Params(d=2, N=64, k_max=3200 if prec == "fp32" else 1600, c=5.0,
                          precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64,
                          sched_fft=fsched)
     plan = sfft.sfft_plan_create(params, max_batch=4)
     pmax = plan.max_prime
-    assert pmax > (4096 if prec == "fp32" else 2048)
+    assert pmax > (8192 if prec == "fp32" else 4096)
     rng = np.random.default_rng(11)
-    ps = {2, 3, 5, 13, 41, 127, 907, 1283, 2053, 4093, 4099, pmax}
+    ps = {2, 3, 5, 13, 41, 127, 907, 1283, 2053, 4093, 4099, 8191, 8209, 12007, pmax}
     for p in sorted(q for q in ps if q <= pmax):
         _say(f"[dft] {prec} schedule {fsched} p={p}")
         x = rng.normal(size=(5, p)) + 1j * rng.normal(size=(5, p))
@@ -224,6 +225,8 @@ RECOVER_CASES = [
     # evaluation of exp(2 pi i w . t) at arguments of up to 1.6e6 cycles
     ("e1_fp64_d100", "e1", {}, 4, 16, 1e-8),
     ("e1_fp64_d100_k128", "e1", {}, 2, 128, 1e-8),
+    # k = 2^10, the sweep's last point: first prime 5147, Bluestein length 16384
+    ("e1_fp64_d100_k1024", "e1", {}, 2, 1024, 1e-8),
     # and at d = 1000 (200 unwrapped coordinates, 201 sets per round)
     ("e2_fp64_d1000", "e2", {}, 2, 16, 1e-8),
     ("e2_fp64_d1000_k64", "e2", {}, 2, 64, 1e-8),
@@ -260,6 +263,10 @@ RECOVER_CASES = [
      {"sched": dict(sched_fft=2, sched_dft_batch=2, sched_nt=(2, 2, 2, 2))}, 5, (20, 260), 1e-5),
     ("c3_fp32_sched_nt4_nt8_batch8", "c3b",
      {"sched": dict(sched_nt=(4, 4, 8, 8), sched_dft_batch=8)}, 3, 150, 1e-5),
+    # primes past the in-LDS DFT (Bluestein lengths 16384 FP64 / 32768 FP32: two halves
+    # through the workspace) in every round
+    ("c1_fp64_long_dft", "c1", {"p_min": 4200}, 4, 8, 1e-9),
+    ("c3_fp32_long_dft", "c3b", {"p_min": 8300}, 3, 150, 1e-5),
 ]
 
 
@@ -556,11 +563,11 @@ def test_autotune_log_and_winner():
                                  cfg["sigma"])
     db = sfft.DeviceBatch.from_planted(pb)
     base = _params(cfg, int(pb.k.max()))
-    tuned, log = sfft.sfft_autotune(base, db, c_values=(2.5, 3.0, 40.0), warmup=1, steps=2)
+    tuned, log = sfft.sfft_autotune(base, db, c_values=(2.5, 3.0, 60.0), warmup=1, steps=2)
     _say(f"[autotune] {len(log)} candidates; winner c={tuned.c} nt={tuned.sched_nt} "
          f"fft={tuned.sched_fft} batch={tuned.sched_dft_batch}")
-    assert [e["c"] for e in log[:3]] == [2.5, 3.0, 40.0]
-    assert log[2]["status"] == sfft.SFFT_ERANGE       # 40 * 300 > the largest prime
+    assert [e["c"] for e in log[:3]] == [2.5, 3.0, 60.0]
+    assert log[2]["status"] == sfft.SFFT_ERANGE       # 60 * 300 > the largest prime
     assert len(log) >= 3 + 1 + 4 + 2 + 2 + 3 + 3
     assert all(e["sched_fft"] in (1, 2) for e in log)  # the schedule as run
     ok = [e for e in log if e["status"] == 0]
