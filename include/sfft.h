@@ -329,16 +329,20 @@ sfft_status sfft_session_finish(sfft_session session, const sfft_outputs* out, v
  * are rounded to BF16 on input; y holds n labels in {0, 1}.
  *
  * sfft_mlp_forward: prob[i] = probability of one mode for row i (device, n).
- * sfft_mlp_grad: mean softmax cross-entropy over the rows and its gradient
- *   with respect to the parameters (device: grad [SFFT_MLP_PARAMS], loss [1],
- *   both overwritten); the forward and backward passes of training.
+ * sfft_mlp_grad: mean softmax cross-entropy over the rows (per row
+ *   logsumexp(z) - z[label], finite for any logits) and its gradient with
+ *   respect to the parameters (device: grad [SFFT_MLP_PARAMS], loss [1], both
+ *   overwritten); the forward and backward passes of training.  The sums over
+ *   rows are added in a fixed order: the same inputs give the same bits.
+ *   Allocates and frees 1.2 MB of partial sums and synchronises `stream`.
  * sfft_mlp_train: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master
  *   parameters initialised from `w`, `epochs` passes of ceil(n / batch) steps
  *   over minibatches drawn with replacement (counter-based hash of seed, step,
  *   row); `w` is overwritten with the BF16 rounding of the trained masters;
  *   loss_hist (device, [epochs], optional) receives the mean minibatch loss of
- *   each epoch.  Allocates and frees its optimiser state (about 80 KB) and
- *   synchronises `stream` before returning. */
+ *   each epoch.  Deterministic for a given seed.  Allocates and frees its
+ *   optimiser state and gradient partial sums (about 1.3 MB) and synchronises
+ *   `stream` before returning. */
 sfft_status sfft_mlp_forward(const void* w, const float* x, int64_t n, float* prob, void* stream);
 sfft_status sfft_mlp_grad(const void* w, const float* x, const uint8_t* y, int64_t n, float* grad,
                           float* loss, void* stream);

@@ -801,8 +801,15 @@ sfft_status sfft_mlp_grad(const void* w, const float* x, const uint8_t* y, int64
   g_err[0] = 0;
   if (!w || !x || !y || !grad || !loss) return fail(SFFT_EINVAL, "NULL argument");
   if (n < 1) return fail(SFFT_EINVAL, "n must be >= 1");
-  const int e = launch_mlp_grad(w, x, y, n, n, 0, 0, grad, loss, true, stream);
+  float* part = nullptr;
+  const size_t part_bytes = sizeof(float) * (size_t)kMlpGradGroups * kMlpPartStride;
+  hipError_t he = hipMalloc((void**)&part, part_bytes);
+  if (he != hipSuccess) return fail(SFFT_ENOMEM, "gradient partial sums: %s", hipGetErrorString(he));
+  const int e = launch_mlp_grad(w, x, y, n, n, 0, 0, part, grad, loss, stream);
+  const hipError_t se = hipStreamSynchronize((hipStream_t)stream);
+  (void)hipFree(part);
   if (e) return hip_fail((hipError_t)e, "mlp grad launch");
+  if (se != hipSuccess) return hip_fail(se, "mlp grad");
   return SFFT_OK;
 }
 
@@ -814,10 +821,12 @@ sfft_status sfft_mlp_train(void* w, const float* x, const uint8_t* y, int64_t n,
   if (n < 1 || epochs < 1 || batch < 1) return fail(SFFT_EINVAL, "n, epochs, batch must be >= 1");
   if (!(lr > 0.0) || !std::isfinite(lr)) return fail(SFFT_EINVAL, "lr must be > 0");
   const int P = kMlpParamCount;
-  float* st = nullptr;  // master, m, v, grad, loss
-  hipError_t he = hipMalloc((void**)&st, sizeof(float) * (4 * (size_t)P + 64));
+  float* st = nullptr;  // master, m, v, grad, loss, gradient partial sums
+  hipError_t he = hipMalloc((void**)&st, sizeof(float) * (4 * (size_t)P + 64 +
+                                                          (size_t)kMlpGradGroups * kMlpPartStride));
   if (he != hipSuccess) return fail(SFFT_ENOMEM, "optimiser state: %s", hipGetErrorString(he));
   float *master = st, *m = st + P, *v = st + 2 * P, *g = st + 3 * P, *loss = st + 4 * P;
+  float* part = st + 4 * (size_t)P + 64;
   const uint64_t hseed = seed ? seed : 0x5DEECE66Dull;  // 0 would mean "rows in order"
   const int64_t steps = (n + batch - 1) / batch;
   int e = launch_mlp_init(w, master, m, v, stream);
@@ -829,7 +838,7 @@ sfft_status sfft_mlp_train(void* w, const float* x, const uint8_t* y, int64_t n,
       ++t;
       b1t *= 0.9;
       b2t *= 0.999;
-      e = launch_mlp_grad(w, x, y, n, batch, hseed, t, g, loss, true, stream);
+      e = launch_mlp_grad(w, x, y, n, batch, hseed, t, part, g, loss, stream);
       if (!e) e = launch_mlp_adam(master, m, v, g, w, (float)lr, (float)(1.0 - b1t),
                                   (float)(1.0 - b2t), stream);
       if (!e && loss_hist) e = launch_mlp_accum(loss, loss_hist + ep, 1.f / (float)steps, stream);

@@ -177,15 +177,19 @@ struct KSess {
 // Launchers (defined in the .hip file).  Return a hipError_t as int.
 int launch_zero_queue(const KParams& kp, int64_t* count, void* stream);
 int launch_mlp_forward(const void* w, const float* x, int64_t n, float* prob, void* stream);
+// Gradient: per-group partial sums in `part` (kMlpGradGroups rows of
+// kMlpPartStride floats), then added in group order into grad and loss.
+constexpr int kMlpParamCount = 4866;
+constexpr int kMlpGradGroups = 64;
+constexpr int kMlpPartStride = kMlpParamCount + 1;
 int launch_mlp_grad(const void* w, const float* x, const uint8_t* y, int64_t n, int64_t rows,
-                    uint64_t seed, uint64_t step, float* grad, float* loss, bool zero,
+                    uint64_t seed, uint64_t step, float* part, float* grad, float* loss,
                     void* stream);
 int launch_mlp_init(const void* w, float* master, float* m, float* v, void* stream);
 int launch_mlp_adam(float* master, float* m, float* v, const float* g, void* w, float lr,
                     float bc1, float bc2, void* stream);
 int launch_mlp_accum(const float* src, float* dst, float scale, void* stream);
 int launch_fill(float* a, int n, float v, void* stream);
-constexpr int kMlpParamCount = 4866;
 int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream);
 // Fixed device scratch of sfft_recover_static (see the .hip file): its size,
 // the part the queue counter takes, the per-device address lookup (call once

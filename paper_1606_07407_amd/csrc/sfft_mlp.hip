@@ -1,6 +1,7 @@
 // Training and inference kernels of the learned bucket classifier: forward
-// probabilities, forward + backward (mean softmax cross-entropy gradient),
-// and Adam on FP32 master parameters with BF16 working copies.
+// probabilities, forward + backward (mean softmax cross-entropy gradient,
+// reduced in a fixed order), and Adam on FP32 master parameters with BF16
+// working copies.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -31,17 +32,25 @@ __global__ void __launch_bounds__(kWG) mlp_forward_kernel(const uint16_t* __rest
   }
 }
 
-// Gradient of the mean softmax cross-entropy over `rows` rows, accumulated
-// (atomically) into grad and loss.  Row q of the batch is row q of x when
-// seed == 0, else a row drawn by a counter-based hash of (seed, step, q).
-// Each work-group takes kTile rows: forward per row (one thread per row),
-// then the parameter gradients as sums over the tile's rows in LDS.
+// Gradient of the mean softmax cross-entropy over `rows` rows.  Row q of the
+// batch is row q of x when seed == 0, else a row drawn by a counter-based hash
+// of (seed, step, q).  Work-group g takes the tiles of kTile rows g, g + G, ...
+// in order: forward per row (one thread per row), then the parameter gradients
+// as sums over the tile's rows in LDS, added to per-thread accumulators (each
+// thread owns fixed parameters).  The group's sums go to row g of `part`
+// (kMlpPartStride floats: the parameters, then the loss sum); mlp_reduce_kernel
+// adds the rows in order, so the result does not depend on timing.
+constexpr int kN1 = kMlpH * kMlpIn + kMlpH;    // W1, b1 (contiguous from kW1)
+constexpr int kN2 = kMlpH * kMlpH + kMlpH;     // W2, b2 (from kW2)
+constexpr int kN3 = kMlpOut * kMlpH + kMlpOut; // W3, b3 (from kW3)
+constexpr int kE1 = (kN1 + kWG - 1) / kWG, kE2 = (kN2 + kWG - 1) / kWG,
+              kE3 = (kN3 + kWG - 1) / kWG;
+
 __global__ void __launch_bounds__(kWG) mlp_grad_kernel(const uint16_t* __restrict__ w,
                                                        const float* __restrict__ x,
                                                        const uint8_t* __restrict__ y, int64_t n,
                                                        int64_t rows, uint64_t seed, uint64_t step,
-                                                       float* __restrict__ grad,
-                                                       float* __restrict__ loss) {
+                                                       float* __restrict__ part) {
   __shared__ float W[kMlpParams];
   // rows padded by one word so that one row per lane spreads over the banks
   __shared__ float H1[kTile][kMlpH + 1];  // h1, later dL/da1
@@ -51,49 +60,136 @@ __global__ void __launch_bounds__(kWG) mlp_grad_kernel(const uint16_t* __restric
   __shared__ float red[kWG];
   mlp_load(w, W);
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  const int nt = (int)min<int64_t>(kTile, rows - base);
   const float inv_rows = 1.f / (float)rows;
+  float a1[kE1], a2[kE2], a3[kE3];
+#pragma unroll
+  for (int e = 0; e < kE1; ++e) a1[e] = 0.f;
+#pragma unroll
+  for (int e = 0; e < kE2; ++e) a2[e] = 0.f;
+#pragma unroll
+  for (int e = 0; e < kE3; ++e) a3[e] = 0.f;
   float lsum = 0.f;
-  if (tid < kTile) {
-    if (tid < nt) {
-      const int64_t q = base + tid;
-      const int64_t r = seed ? (int64_t)(splitmix64(seed ^ (step << 32) ^ (uint64_t)q) %
-                                         (uint64_t)n)
-                             : q;
-      float xi[kMlpIn];
+  const int64_t ntiles = (rows + kTile - 1) / kTile;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t base = tile * kTile;
+    const int nt = (int)min<int64_t>(kTile, rows - base);
+    if (tid < kTile) {
+      if (tid < nt) {
+        const int64_t q = base + tid;
+        const int64_t r = seed ? (int64_t)(splitmix64(seed ^ (step << 32) ^ (uint64_t)q) %
+                                           (uint64_t)n)
+                               : q;
+        float xi[kMlpIn];
 #pragma unroll
-      for (int i = 0; i < kMlpIn; ++i) {
-        xi[i] = bf16_round(x[r * kMlpIn + i]);
-        X[tid][i] = xi[i];
-      }
-      for (int o = 0; o < kMlpH; ++o) {
-        float a = W[kB1 + o];
+        for (int i = 0; i < kMlpIn; ++i) {
+          xi[i] = bf16_round(x[r * kMlpIn + i]);
+          X[tid][i] = xi[i];
+        }
+        for (int o = 0; o < kMlpH; ++o) {
+          float a = W[kB1 + o];
 #pragma unroll
-        for (int i = 0; i < kMlpIn; ++i) a += W[kW1 + o * kMlpIn + i] * xi[i];
-        H1[tid][o] = a > 0.f ? a : 0.f;
+          for (int i = 0; i < kMlpIn; ++i) a += W[kW1 + o * kMlpIn + i] * xi[i];
+          H1[tid][o] = a > 0.f ? a : 0.f;
+        }
+        float z0 = W[kB3], z1 = W[kB3 + 1];
+        for (int o = 0; o < kMlpH; ++o) {
+          float a = W[kB2 + o];
+          for (int i = 0; i < kMlpH; ++i) a += W[kW2 + o * kMlpH + i] * H1[tid][i];
+          const float h = a > 0.f ? a : 0.f;
+          H2[tid][o] = h;
+          z0 += W[kW3 + o] * h;
+          z1 += W[kW3 + kMlpH + o] * h;
+        }
+        // loss = logsumexp(z) - z[label], finite however far apart the logits are
+        const float zm = fmaxf(z0, z1);
+        const float e0 = expf(z0 - zm), e1 = expf(z1 - zm);
+        const float den = e0 + e1;
+        const int lab = y[r] ? 1 : 0;
+        lsum += zm + logf(den) - (lab ? z1 : z0);
+        DZ[tid][0] = (e0 / den - (lab == 0 ? 1.f : 0.f)) * inv_rows;
+        DZ[tid][1] = (e1 / den - (lab == 1 ? 1.f : 0.f)) * inv_rows;
+      } else {
+        for (int i = 0; i < kMlpIn; ++i) X[tid][i] = 0.f;
+        for (int o = 0; o < kMlpH; ++o) H1[tid][o] = H2[tid][o] = 0.f;
+        DZ[tid][0] = DZ[tid][1] = 0.f;
       }
-      float z0 = W[kB3], z1 = W[kB3 + 1];
-      for (int o = 0; o < kMlpH; ++o) {
-        float a = W[kB2 + o];
-        for (int i = 0; i < kMlpH; ++i) a += W[kW2 + o * kMlpH + i] * H1[tid][i];
-        const float h = a > 0.f ? a : 0.f;
-        H2[tid][o] = h;
-        z0 += W[kW3 + o] * h;
-        z1 += W[kW3 + kMlpH + o] * h;
-      }
-      const float zm = fmaxf(z0, z1);
-      const float e0 = expf(z0 - zm), e1 = expf(z1 - zm);
-      const float s0 = e0 / (e0 + e1), s1 = e1 / (e0 + e1);
-      const int lab = y[r] ? 1 : 0;
-      lsum = -logf(lab ? s1 : s0);
-      DZ[tid][0] = (s0 - (lab == 0 ? 1.f : 0.f)) * inv_rows;
-      DZ[tid][1] = (s1 - (lab == 1 ? 1.f : 0.f)) * inv_rows;
-    } else {
-      for (int i = 0; i < kMlpIn; ++i) X[tid][i] = 0.f;
-      for (int o = 0; o < kMlpH; ++o) H1[tid][o] = H2[tid][o] = 0.f;
-      DZ[tid][0] = DZ[tid][1] = 0.f;
     }
+    __syncthreads();
+    // dW3 = DZ^T H2, db3 = sum DZ
+#pragma unroll
+    for (int e = 0; e < kE3; ++e) {
+      const int q = tid + e * kWG;
+      if (q < kN3) {
+        float g = 0.f;
+        if (q < kMlpOut * kMlpH) {
+          const int c = q / kMlpH, o = q - c * kMlpH;
+          for (int s = 0; s < kTile; ++s) g += DZ[s][c] * H2[s][o];
+        } else {
+          const int c = q - kMlpOut * kMlpH;
+          for (int s = 0; s < kTile; ++s) g += DZ[s][c];
+        }
+        a3[e] += g;
+      }
+    }
+    __syncthreads();
+    // dL/da2 = (DZ W3) * [h2 > 0], in place of H2
+    for (int q = tid; q < kTile * kMlpH; q += kWG) {
+      const int s = q / kMlpH, o = q - s * kMlpH;
+      const float d = DZ[s][0] * W[kW3 + o] + DZ[s][1] * W[kW3 + kMlpH + o];
+      H2[s][o] = H2[s][o] > 0.f ? d : 0.f;
+    }
+    __syncthreads();
+    // dW2 = dA2^T H1, db2 = sum dA2
+#pragma unroll
+    for (int e = 0; e < kE2; ++e) {
+      const int q = tid + e * kWG;
+      if (q < kN2) {
+        float g = 0.f;
+        if (q < kMlpH * kMlpH) {
+          const int o = q / kMlpH, i = q - o * kMlpH;
+          for (int s = 0; s < kTile; ++s) g += H2[s][o] * H1[s][i];
+        } else {
+          const int o = q - kMlpH * kMlpH;
+          for (int s = 0; s < kTile; ++s) g += H2[s][o];
+        }
+        a2[e] += g;
+      }
+    }
+    // dL/da1 = (dA2 W2) * [h1 > 0]; computed into registers, then written over H1
+    constexpr int PER = kTile * kMlpH / kWG;
+    float d1[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int q = tid + e * kWG;
+      const int s = q / kMlpH, i = q - s * kMlpH;
+      float d = 0.f;
+      for (int o = 0; o < kMlpH; ++o) d += H2[s][o] * W[kW2 + o * kMlpH + i];
+      d1[e] = H1[s][i] > 0.f ? d : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int q = tid + e * kWG;
+      H1[q / kMlpH][q % kMlpH] = d1[e];
+    }
+    __syncthreads();
+    // dW1 = dA1^T X, db1 = sum dA1
+#pragma unroll
+    for (int e = 0; e < kE1; ++e) {
+      const int q = tid + e * kWG;
+      if (q < kN1) {
+        float g = 0.f;
+        if (q < kMlpH * kMlpIn) {
+          const int o = q / kMlpIn, i = q - o * kMlpIn;
+          for (int s = 0; s < kTile; ++s) g += H1[s][o] * X[s][i];
+        } else {
+          const int o = q - kMlpH * kMlpIn;
+          for (int s = 0; s < kTile; ++s) g += H1[s][o];
+        }
+        a1[e] += g;
+      }
+    }
+    __syncthreads();  // the next tile overwrites X, H1, H2, DZ
   }
   red[tid] = lsum;
   __syncthreads();
@@ -101,71 +197,30 @@ __global__ void __launch_bounds__(kWG) mlp_grad_kernel(const uint16_t* __restric
     if (tid < off) red[tid] += red[tid + off];
     __syncthreads();
   }
-  if (tid == 0) atomicAdd(loss, red[0] * inv_rows);
-  // dW3 = DZ^T H2, db3 = sum DZ
-  for (int q = tid; q < kMlpOut * kMlpH + kMlpOut; q += kWG) {
-    float g = 0.f;
-    if (q < kMlpOut * kMlpH) {
-      const int c = q / kMlpH, o = q - c * kMlpH;
-      for (int s = 0; s < kTile; ++s) g += DZ[s][c] * H2[s][o];
-      atomicAdd(&grad[kW3 + q], g);
-    } else {
-      const int c = q - kMlpOut * kMlpH;
-      for (int s = 0; s < kTile; ++s) g += DZ[s][c];
-      atomicAdd(&grad[kB3 + c], g);
-    }
-  }
-  __syncthreads();
-  // dL/da2 = (DZ W3) * [h2 > 0], in place of H2
-  for (int q = tid; q < kTile * kMlpH; q += kWG) {
-    const int s = q / kMlpH, o = q - s * kMlpH;
-    const float d = DZ[s][0] * W[kW3 + o] + DZ[s][1] * W[kW3 + kMlpH + o];
-    H2[s][o] = H2[s][o] > 0.f ? d : 0.f;
-  }
-  __syncthreads();
-  // dW2 = dA2^T H1, db2 = sum dA2
-  for (int q = tid; q < kMlpH * kMlpH + kMlpH; q += kWG) {
-    float g = 0.f;
-    if (q < kMlpH * kMlpH) {
-      const int o = q / kMlpH, i = q - o * kMlpH;
-      for (int s = 0; s < kTile; ++s) g += H2[s][o] * H1[s][i];
-      atomicAdd(&grad[kW2 + q], g);
-    } else {
-      const int o = q - kMlpH * kMlpH;
-      for (int s = 0; s < kTile; ++s) g += H2[s][o];
-      atomicAdd(&grad[kB2 + o], g);
-    }
-  }
-  // dL/da1 = (dA2 W2) * [h1 > 0]; computed into registers, then written over H1
-  constexpr int PER = kTile * kMlpH / kWG;
-  float d1[PER];
+  float* pg = part + (size_t)blockIdx.x * kMlpPartStride;
+  if (tid == 0) pg[kMlpParams] = red[0];
 #pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int q = tid + e * kWG;
-    const int s = q / kMlpH, i = q - s * kMlpH;
-    float d = 0.f;
-    for (int o = 0; o < kMlpH; ++o) d += H2[s][o] * W[kW2 + o * kMlpH + i];
-    d1[e] = H1[s][i] > 0.f ? d : 0.f;
-  }
-  __syncthreads();
+  for (int e = 0; e < kE1; ++e)
+    if (tid + e * kWG < kN1) pg[kW1 + tid + e * kWG] = a1[e];
 #pragma unroll
-  for (int e = 0; e < PER; ++e) {
-    const int q = tid + e * kWG;
-    H1[q / kMlpH][q % kMlpH] = d1[e];
-  }
-  __syncthreads();
-  // dW1 = dA1^T X, db1 = sum dA1
-  for (int q = tid; q < kMlpH * kMlpIn + kMlpH; q += kWG) {
-    float g = 0.f;
-    if (q < kMlpH * kMlpIn) {
-      const int o = q / kMlpIn, i = q - o * kMlpIn;
-      for (int s = 0; s < kTile; ++s) g += H1[s][o] * X[s][i];
-      atomicAdd(&grad[kW1 + q], g);
-    } else {
-      const int o = q - kMlpH * kMlpIn;
-      for (int s = 0; s < kTile; ++s) g += H1[s][o];
-      atomicAdd(&grad[kB1 + o], g);
-    }
+  for (int e = 0; e < kE2; ++e)
+    if (tid + e * kWG < kN2) pg[kW2 + tid + e * kWG] = a2[e];
+#pragma unroll
+  for (int e = 0; e < kE3; ++e)
+    if (tid + e * kWG < kN3) pg[kW3 + tid + e * kWG] = a3[e];
+}
+
+// grad[q] = sum over the groups' rows of part in group order; loss = mean row loss.
+__global__ void mlp_reduce_kernel(const float* __restrict__ part, int groups, float inv_rows,
+                                  float* __restrict__ grad, float* __restrict__ loss) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q <= kMlpParams;
+       q += gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int g = 0; g < groups; ++g) s += part[(size_t)g * kMlpPartStride + q];
+    if (q < kMlpParams)
+      grad[q] = s;
+    else
+      loss[0] = s * inv_rows;
   }
 }
 
@@ -215,16 +270,15 @@ int launch_mlp_forward(const void* w, const float* x, int64_t n, float* prob, vo
 }
 
 int launch_mlp_grad(const void* w, const float* x, const uint8_t* y, int64_t n, int64_t rows,
-                    uint64_t seed, uint64_t step, float* grad, float* loss, bool zero,
+                    uint64_t seed, uint64_t step, float* part, float* grad, float* loss,
                     void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (zero) {
-    hipLaunchKernelGGL(mlp_fill_kernel, dim3(20), dim3(256), 0, s, grad, kMlpParams, 0.f);
-    hipLaunchKernelGGL(mlp_fill_kernel, dim3(1), dim3(64), 0, s, loss, 1, 0.f);
-  }
-  const int grid = (int)((rows + kTile - 1) / kTile);
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(grid), dim3(kWG), 0, s, (const uint16_t*)w, x, y, n,
-                     rows, seed, step, grad, loss);
+  const int64_t ntiles = (rows + kTile - 1) / kTile;
+  const int groups = (int)(ntiles < kMlpGradGroups ? ntiles : kMlpGradGroups);
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3(groups), dim3(kWG), 0, s, (const uint16_t*)w, x, y,
+                     n, rows, seed, step, part);
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kMlpParams + 256) / 256), dim3(256), 0, s,
+                     (const float*)part, groups, 1.f / (float)rows, grad, loss);
   return (int)hipGetLastError();
 }
 

@@ -430,14 +430,31 @@ class Session:
         self.stream = stream
         self._req = torch.zeros((2, self.B), dtype=torch.int32, device="cuda")
         h = ctypes.c_void_p()
+        self._after_current()
         _check(lib().sfft_session_create(plan.handle, self.B, _ptr(self.k), _stream(stream),
                                          ctypes.byref(h)), "sfft_session_create")
         self.handle = h
+        self._before_current(self.k, self._req)
+
+    def _side(self) -> bool:
+        """True when the session runs on a stream other than torch's current one."""
+        return (self.stream is not None and hasattr(self.stream, "wait_stream")
+                and self.stream != _torch().cuda.current_stream())
 
     def _after_current(self):
         """Order the session's stream after torch's current one (tensors made there)."""
-        if self.stream is not None and hasattr(self.stream, "wait_stream"):
+        if self._side():
             self.stream.wait_stream(_torch().cuda.current_stream())
+
+    def _before_current(self, *tensors):
+        """After a launch on a side stream: order torch's current stream after it (so
+        that what the launch wrote is seen there) and tell the caching allocator that
+        the side stream uses these tensors (made on the current stream)."""
+        if self._side():
+            _torch().cuda.current_stream().wait_stream(self.stream)
+            for t in tensors:
+                if t is not None:
+                    t.record_stream(self.stream)
 
     def request(self):
         self._after_current()
@@ -456,6 +473,7 @@ class Session:
         self._after_current()
         _check(lib().sfft_session_points(self.handle, _ptr(t), _stream(self.stream)),
                "sfft_session_points")
+        self._before_current(t)
         return t
 
     def feed(self, samples):
@@ -467,6 +485,7 @@ class Session:
         self._after_current()
         _check(lib().sfft_session_feed(self.handle, _ptr(samples), _stream(self.stream)),
                "sfft_session_feed")
+        self._before_current(samples)
 
     def finish(self, out: dict | None = None) -> dict:
         if out is None:
@@ -477,6 +496,7 @@ class Session:
         self._after_current()
         _check(lib().sfft_session_finish(self.handle, ctypes.byref(o), _stream(self.stream)),
                "sfft_session_finish")
+        self._before_current(*[v for v in out.values() if hasattr(v, "record_stream")])
         return out
 
     def close(self):

@@ -174,6 +174,43 @@ def test_mlp_forward_and_grad_match_oracle():
     assert err < 1e-4
 
 
+def test_mlp_grad_is_deterministic_and_loss_finite():
+    """The gradient's sums over rows are added in a fixed order: 20000 rows (157 tiles over
+    64 work-groups) give bit-identical results on repeated calls.  With logits far apart
+    (the output layer scaled up) the loss is logsumexp(z) - z[label] per row, finite and
+    equal to that expression on the oracle network's logits."""
+    import torch
+    sfft = _sfft()
+    theta = _rand_params(9)
+    rng = np.random.default_rng(10)
+    X = rng.normal(scale=2.0, size=(20000, 8)).astype(np.float32)
+    y = rng.integers(0, 2, size=20000).astype(np.uint8)
+    xt = torch.tensor(X, device="cuda")
+    yt = torch.tensor(y, device="cuda")
+    w = _to_bf16_tensor(theta)
+    l1, g1 = sfft.sfft_mlp_grad(w, xt, yt)
+    l2, g2 = sfft.sfft_mlp_grad(w, xt, yt)
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+    Xb = C.bf16_round(X.astype(np.float64))
+    rl, rg = C.loss_and_grad(theta, Xb, y)
+    err = np.abs(g1.cpu().numpy() - rg).max() / np.abs(rg).max()
+    _say(f"[mlp] 20000 rows: loss {float(l1.item()):.6f} vs {rl:.6f}; grad rel err {err:.2e}")
+    assert abs(float(l1.item()) - rl) <= 1e-5 * max(1.0, abs(rl)) and err < 1e-4
+    # saturated logits: output weights x 2^12 (exact in BF16)
+    big = theta.copy()
+    o3 = C.N_PARAMS - (2 * 64 + 2)
+    big[o3:] *= 4096.0
+    lb, _ = sfft.sfft_mlp_grad(_to_bf16_tensor(big), xt, yt)
+    z, _ = C.forward(big, Xb)
+    zm = z.max(axis=1)
+    ref = float(np.mean(zm + np.log(np.exp(z[:, 0] - zm) + np.exp(z[:, 1] - zm))
+                        - z[np.arange(len(y)), y.astype(np.int64)]))
+    _say(f"[mlp] saturated logits: loss {float(lb.item()):.6e} vs {ref:.6e} "
+         f"(largest logit gap {np.abs(z[:, 0] - z[:, 1]).max():.3e})")
+    assert np.abs(z[:, 0] - z[:, 1]).max() > 200.0   # exp(-gap) underflows FP32
+    assert np.isfinite(float(lb.item())) and abs(float(lb.item()) - ref) <= 1e-4 * abs(ref)
+
+
 def test_train_then_learned_recovery():
     import torch
     sfft = _sfft()

@@ -324,6 +324,8 @@ SESSION_CASES = [
     ("c3_fp32_ladder_verify", "c3b", {}, 3, 120, 1e-5),
     ("c1_fp64_verify", "c1", {"verify": True}, 4, 8, 1e-9),
     ("e3_fp64_uneven_verify", "e3", {"verify": True}, 2, 100, 1e-9),
+    # the session on a stream of its own while the caller samples on torch's current one
+    ("c2_fp32_side_stream", "c2", {"stream": "side"}, 2, 256, 1e-5),
 ]
 
 
@@ -334,11 +336,13 @@ def test_session_matches_oracle(name, cname, over, B, k, tol):
     (which samples the same signal itself), round by round."""
     import torch
     sfft = _sfft()
+    over = dict(over)
+    side = over.pop("stream", None) == "side"
     cfg = workloads.config(cname, **over)
     _say(f"[session] {name} B={B} k={k}")
     pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], k, cfg["mag"], 0.0)
     plan = sfft.sfft_plan_create(_params(cfg, k), max_batch=B)
-    sess = sfft.Session(plan, np.full(B, k))
+    sess = sfft.Session(plan, np.full(B, k), stream=torch.cuda.Stream() if side else None)
     dt = torch.complex64 if cfg["precision"] == "fp32" else torch.complex128
     P = _oracle_params(cfg, k)
     fed = 0
