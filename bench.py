@@ -35,6 +35,7 @@ import workloads  # noqa: E402
 METRIC = "signal recoveries/sec at exact support, d=10 k=1000; learned vs plain"
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_FP32_VALU = 157.3  # TFLOP/s, MI355X FP32 vector
+PEAK_FP64 = 78.6        # TFLOP/s, MI355X FP64 (vector and matrix)
 TUNE_C_OFFSETS = (-1.0, -0.5, 0.0, 0.5)  # c values the autotuner measures around the recipe's c
 TUNE_WARMUP, TUNE_STEPS = 3, 10
 
@@ -343,12 +344,21 @@ def paper_sweep(sfft, steps: int, warmup: int, name: str = "e1") -> list:
             err = max(err, float(np.abs(h["coeffs"][b, :k] - a[o]).max()))
         share = main_part_share(sfft, plan, db, B)
         samples = float(np.mean(h["samples"]))
-        rows.append(dict(d=cfg["d"], k=k, trials=B, success_rate=float(ok.mean()),
-                         max_coeff_err=err,
-                         mean_rounds=float(np.mean(h["rounds"])), mean_samples=samples,
-                         samples_per_dk=samples / (cfg["d"] * k), batch_ms=gpu_ms,
-                         ms_per_signal=gpu_ms / B, main_part_ms=gpu_ms * share,
-                         prime_round1=int(h["trace"][0, 0, 2])))
+        alg = algorithmic_flops(h["trace"], pb.k, plan.num_sets)
+        row = dict(d=cfg["d"], k=k, trials=B, success_rate=float(ok.mean()),
+                   max_coeff_err=err,
+                   mean_rounds=float(np.mean(h["rounds"])), mean_samples=samples,
+                   samples_per_dk=samples / (cfg["d"] * k), batch_ms=gpu_ms,
+                   ms_per_signal=gpu_ms / B, main_part_ms=gpu_ms * share,
+                   prime_round1=int(h["trace"][0, 0, 2]),
+                   alg_tflops=alg / (gpu_ms * 1e-3) / 1e12,
+                   frac_fp64=alg / (gpu_ms * 1e-3) / 1e12 / PEAK_FP64)
+        if k >= 256:
+            # the FP64 sampler alone at the first round's shape
+            p1, m1 = int(h["trace"][0, 0, 2]), int(h["trace"][0, 0, 3])
+            row["sampler_round1"] = components(sfft, plan, pb, db, plan.num_sets, p1, m1,
+                                               steps)["sampler"]
+        rows.append(row)
         plan.close()
         print(f"[paper sweep] d={cfg['d']} k={k}: success {ok.mean():.2f}, "
               f"{gpu_ms:.3f} ms per launch", file=sys.stderr, flush=True)
@@ -486,7 +496,9 @@ def components(sfft, plan, pb, db, S1, p, m, steps):
     import torch
     B = pb.B
     stream = torch.cuda.current_stream()
-    V = torch.zeros((B, S1, p), dtype=torch.complex64, device="cuda")
+    f64 = plan.params.precision == sfft.SFFT_FP64
+    V = torch.zeros((B, S1, p), dtype=torch.complex128 if f64 else torch.complex64,
+                    device="cuda")
     X = V.view(B * S1, p)
     sfft.sfft_sample_lines(plan, db, 1, p, m, V=V, stream=stream)
     sfft.sfft_dft(plan, X, stream=stream)
@@ -508,11 +520,15 @@ def components(sfft, plan, pb, db, S1, p, m, steps):
     alg = n_dft * 5.0 * p * math.log2(p)
     # executed: two L-point FFTs, the filter and both chirp products per sequence
     exe = n_dft * (2 * 5.0 * L * math.log2(L) + 6.0 * L + 12.0 * p)
+    samp = {"kernel": "sample_kernel", "ms": ts, "terms": terms,
+            "tflops": 8.0 * terms / (ts * 1e-3) / 1e12}
+    if f64:
+        samp["frac_fp64"] = samp["tflops"] / PEAK_FP64
+    else:
+        samp["frac_mfma_fp32"] = samp["tflops"] / PEAK_FP32_MFMA
     return {
         "shape": f"{B} signals x {S1} sets x {p} points, {int(pb.k[0])} modes, round 1",
-        "sampler": {"kernel": "sample_kernel", "ms": ts, "terms": terms,
-                    "tflops": 8.0 * terms / (ts * 1e-3) / 1e12,
-                    "frac_mfma_fp32": 8.0 * terms / (ts * 1e-3) / 1e12 / PEAK_FP32_MFMA},
+        "sampler": samp,
         "dft": {"kernel": "dft_kernel", "ms": td, "bluestein_L": L,
                 "algorithmic_tflops": alg / (td * 1e-3) / 1e12,
                 "executed_tflops": exe / (td * 1e-3) / 1e12,

@@ -1004,20 +1004,80 @@ __device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int S1, ui
   }
 }
 
-// FP64 line sampler on the vector units: one thread per (set, point).
-__device__ inline void expsum_valu_f64(const cpx<double>* __restrict__ C, const uint16_t* rr,
-                                       const cpx<double>* tw, int M, int p, int S1,
-                                       cpx<double>* __restrict__ V, int vstride) {
+// FP64 line sampler on the vector units, V[s][h] = sum_j C[j][s] omega_p^{(h r_j) mod p}
+// (C: [M][S1] coefficient rows, global; rr: r_j, LDS; tw: omega_p^x, LDS).  A work
+// item is a block of SB sets times 64 HB points; the four waves take items in turn,
+// lane l of a wave the points h0 + l + 64 u (u < HB).  Per mode the item's SB
+// coefficients are the same for the whole wave (one load each, served by the cache),
+// the HB twiddles come from the table at indices stepped by (64 r_j) mod p, and each
+// lane accumulates SB x HB complex sums in registers: one twiddle and one coefficient
+// read feed SB and HB products instead of one.
+template <int SB, int HB>
+__device__ void expsum_f64_tiled(const cpx<double>* __restrict__ C, const uint16_t* rr,
+                                 const cpx<double>* tw, int M, int p, int S1,
+                                 cpx<double>* __restrict__ V, int vstride) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ngroups = (S1 + SB - 1) / SB;
+  const int nchunks = (p + 64 * HB - 1) / (64 * HB);
   const float inv_p = 1.0f / (float)p;
-  for (int q = threadIdx.x; q < S1 * p; q += kWG) {
-    const int s = q / p, h = q - s * p;
-    cpx<double> acc = cmk<double>(0.0, 0.0);
+  for (int item = wave; item < ngroups * nchunks; item += kWG / 64) {
+    const int g = item / nchunks, hc = item - g * nchunks;
+    const int s0 = g * SB;
+    const uint32_t h0 = (uint32_t)(hc * 64 * HB + lane);
+    int sidx[SB];
+#pragma unroll
+    for (int b = 0; b < SB; ++b) sidx[b] = min(s0 + b, S1 - 1);  // padding sets repeat the last
+    cpx<double> acc[SB][HB];
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int u = 0; u < HB; ++u) acc[b][u] = cmk<double>(0.0, 0.0);
+#pragma unroll 2
     for (int j = 0; j < M; ++j) {
-      const int idx = mulmod((uint32_t)h, (uint32_t)rr[j], p, inv_p);
-      acc = cadd(acc, cmul(C[(size_t)j * S1 + s], tw[idx]));
+      const uint32_t r = rr[j];
+      const uint32_t step = (uint32_t)mulmod(64u, r, p, inv_p);
+      uint32_t idx = (uint32_t)mulmod(h0, r, p, inv_p);
+      cpx<double> t[HB];
+#pragma unroll
+      for (int u = 0; u < HB; ++u) {
+        t[u] = tw[idx];
+        const uint32_t nx = idx + step;
+        idx = min(nx, nx - (uint32_t)p);  // nx - p wraps above nx when nx < p
+      }
+      const cpx<double>* cj = C + (size_t)j * S1;
+#pragma unroll
+      for (int b = 0; b < SB; ++b) {
+        const cpx<double> c = cj[sidx[b]];
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+          acc[b][u].x = fma(c.x, t[u].x, fma(-c.y, t[u].y, acc[b][u].x));
+          acc[b][u].y = fma(c.x, t[u].y, fma(c.y, t[u].x, acc[b][u].y));
+        }
+      }
     }
-    V[(size_t)s * vstride + h] = acc;
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int u = 0; u < HB; ++u) {
+        const int s = s0 + b, h = (int)h0 + 64 * u;
+        if (s < S1 && h < p) V[(size_t)s * vstride + h] = acc[b][u];
+      }
   }
+}
+
+// Sets per work item of the FP64 sampler: 2, 3 or 4, the fewest padding sets
+// (ties to the larger block).
+__host__ __device__ inline int f64_set_block(int S1) {
+  int best = 4, waste = (4 - S1 % 4) % 4;
+  for (int sb = 3; sb >= 2; --sb) {
+    const int w = (sb - S1 % sb) % sb;
+    if (w < waste) {
+      waste = w;
+      best = sb;
+    }
+  }
+  return best;
 }
 
 }  // namespace sfft

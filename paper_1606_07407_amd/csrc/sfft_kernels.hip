@@ -297,8 +297,15 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
       expsum_mfma<RT, 2>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride);
   } else {
     const cpx<double>* cc = reinterpret_cast<const cpx<double>*>(slot + kp.lay.ccomp);
-    expsum_valu_f64(cc, rr, (const cpx<double>*)tw, 2 * npairs, p, kp.S1, (cpx<double>*)V,
-                    vstride);
+    const cpx<double>* twd = (const cpx<double>*)tw;
+    cpx<double>* Vd = (cpx<double>*)V;
+    const int sb = f64_set_block(kp.S1);
+    if (sb == 4)
+      expsum_f64_tiled<4, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride);
+    else if (sb == 3)
+      expsum_f64_tiled<3, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride);
+    else
+      expsum_f64_tiled<2, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride);
   }
   __syncthreads();
   add_noise<T>(V, vstride, p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);

@@ -141,6 +141,9 @@ inline emu_floatx4 emu_mfma(float a, float b, emu_floatx4 c) {
 }
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu_mfma((a), (b), (c))
 #define __builtin_amdgcn_sched_group_barrier(a, b, c) ((void)0)
+// The kernels apply it only to values that are the same on every lane of the wave
+// (the wave index), where lane 0's value is the thread's own.
+#define __builtin_amdgcn_readfirstlane(v) (v)
 
 // ------------------------------------------------------------- runtime API --
 typedef int hipError_t;
