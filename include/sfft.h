@@ -148,6 +148,16 @@ typedef struct {
   int32_t tilt_a, tilt_b, tilt_c; /* the triple: a^2 + b^2 = c^2, 1 <= a < b, b > 2N,
                               gcd(a, b) = 1; all 0: the plan takes the triple with
                               the smallest a + b (then the smallest b)               */
+  /* Work-groups per signal in sfft_recover (0..16).  The S+1 sample sets of a round
+   * are sampled at points h/p that split into independent column blocks (the
+   * loop over the sets in Algorithm MultiPhaseshift needs no order), so a batch
+   * smaller than the device runs each ordinary round's sampling on several
+   * work-groups and the rest of the round on one (three launches per round, no
+   * host synchronisation; results identical bit for bit).  0: automatic (FP32
+   * plans: as many as fill the device, at most 8, when the batch takes at most
+   * half of it and k_max >= 256); 1: one work-group per signal (one launch);
+   * 2..16.  Phase timestamps (sfft_outputs.phase) come from the one launch. */
+  int32_t split_groups;
 } sfft_params;
 
 /* A batch of synthetic black-box signals with planted spectra.  All pointers
@@ -216,7 +226,9 @@ sfft_status sfft_plan_destroy(sfft_plan plan);
 /* Recover every signal of `batch` (MultiPhaseshift, Section 4.1.2 listing):
  * one persistent launch in which each work-group takes signals from a queue
  * and runs all rounds of one signal (sample, DFT, select, test, decode,
- * registry update) before taking the next.  Allocates nothing. */
+ * registry update) before taking the next; or, for batches smaller than the
+ * device (see split_groups), several work-groups per signal over three
+ * launches per round.  Allocates nothing. */
 sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch,
                          const sfft_outputs* out, void* stream);
 

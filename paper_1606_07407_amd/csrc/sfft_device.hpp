@@ -817,11 +817,15 @@ __device__ __forceinline__ void twiddle_column(const float* twf, uint32_t h0, ui
   }
 }
 
+// grp / ngrp: when ngrp work-groups share the line, this group takes the
+// column-tile blocks grp, grp + ngrp, ... (block = one tile per wave); every
+// point's sum is formed the same way whichever group computes it.
 template <int RT, int NT, bool BLK = (RT * NT <= 12)>
 __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
                             const uint16_t* rs,
                             const cpx<float>* tw, float* abuf, int npairs, int p, int S1,
-                            cpx<float>* __restrict__ V, int vstride) {
+                            cpx<float>* __restrict__ V, int vstride, int grp = 0,
+                            int ngrp = 1) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   constexpr int NWAVES = kWG / 64;
@@ -830,7 +834,7 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
   constexpr int BUF = (kChunk + 1) * PAIR;        // floats per chunk buffer
   constexpr int CPY = (BUF + kWG - 1) / kWG;      // floats copied per thread per chunk
   const int ntiles = (p + NCOL - 1) / NCOL;
-  const int passes = (ntiles + NWAVES - 1) / NWAVES;
+  const int passes = (ntiles + NWAVES * ngrp - 1) / (NWAVES * ngrp);
   const int nchunks = (npairs + kChunk - 1) / kChunk;
   const float inv_p = 1.0f / (float)p;
   const int kk = lane >> 4;       // K row of the B fragment
@@ -839,7 +843,7 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
   const int tpart = kk & 1;       // Re / Im of the twiddle
   const float* twf = reinterpret_cast<const float*>(tw) + tpart;
   for (int pass = 0; pass < passes; ++pass) {
-    const int tile = pass * NWAVES + wave;
+    const int tile = (pass * ngrp + grp) * NWAVES + wave;
     const bool active = tile < ntiles;
     const int hbase = tile * NCOL;
     const uint32_t h0 = (uint32_t)(hbase + col);
@@ -1012,16 +1016,20 @@ __device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int S1, ui
 // the HB twiddles come from the table at indices stepped by (64 r_j) mod p, and each
 // lane accumulates SB x HB complex sums in registers: one twiddle and one coefficient
 // read feed SB and HB products instead of one.
+// (grp / ngrp: several work-groups on one line, this one taking every ngrp-th
+// block of four items.)
 template <int SB, int HB>
 __device__ void expsum_f64_tiled(const cpx<double>* __restrict__ C, const uint16_t* rr,
                                  const cpx<double>* tw, int M, int p, int S1,
-                                 cpx<double>* __restrict__ V, int vstride) {
+                                 cpx<double>* __restrict__ V, int vstride, int grp = 0,
+                                 int ngrp = 1) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ngroups = (S1 + SB - 1) / SB;
   const int nchunks = (p + 64 * HB - 1) / (64 * HB);
   const float inv_p = 1.0f / (float)p;
-  for (int item = wave; item < ngroups * nchunks; item += kWG / 64) {
+  for (int item = grp * (kWG / 64) + wave; item < ngroups * nchunks;
+       item += ngrp * (kWG / 64)) {
     const int g = item / nchunks, hc = item - g * nchunks;
     const int s0 = g * SB;
     const uint32_t h0 = (uint32_t)(hc * 64 * HB + lane);

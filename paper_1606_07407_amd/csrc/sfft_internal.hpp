@@ -191,6 +191,11 @@ int launch_mlp_adam(float* master, float* m, float* v, const float* g, void* w, 
 int launch_mlp_accum(const float* src, float* dst, float scale, void* stream);
 int launch_fill(float* a, int n, float v, void* stream);
 int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream);
+// Several work-groups per signal (batches smaller than the chip): `state` holds
+// kb.B round states (split_state_bytes() each), ngrp groups sample each line.
+size_t split_state_bytes();
+int launch_recover_split(const KParams& kp, const KBatch& kb, const KOut& ko, void* state,
+                         int ngrp, void* stream);
 // Fixed device scratch of sfft_recover_static (see the .hip file): its size,
 // the part the queue counter takes, the per-device address lookup (call once
 // per device with that device current), the slots of a given size it holds,

@@ -126,6 +126,8 @@ struct WgState {
   double sigma;
   uint64_t prefix;
   int need;
+  int split;         // several groups per signal: 1 while an ordinary round awaits its
+                     // samples, 2 once the signal is finished
 };
 
 // --------------------------------------------------- per-signal set-up -----
@@ -249,9 +251,12 @@ __device__ void rebuild_rows(const KParams& kp, char* slot, WgState& st, int P0,
 // [0, 2 P0)), minus g(t_h) (registry rows [2 P0, 2 P0 + 2 ceil(nslots / 2)))
 // when the residual is subtracted from the samples; otherwise the registry is
 // subtracted after the DFT (subtract_registry).
+// grp / ngrp: ngrp work-groups share the line, this one computing its share of
+// the points (see expsum_mfma); noise = false leaves the noise to the caller.
 template <typename T, int RT>
 __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, WgState& st,
-                             int P0, char* lds, cpx<T>* V, int vstride) {
+                             int P0, char* lds, cpx<T>* V, int vstride, int grp = 0,
+                             int ngrp = 1, bool noise = true) {
   const int p = st.p, m0 = st.m0, d2 = kp.d2;
   const int nreg = (kp.residual == 1) ? st.nslots : 0;
   const int npairs = P0 + (nreg + 1) / 2;
@@ -290,26 +295,30 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     const cpx<float>* twc = (const cpx<float>*)tw;
     cpx<float>* Vf = (cpx<float>*)V;
     if (nt >= 8 && NTMAX >= 8)
-      expsum_mfma<RT, (NTMAX >= 8 ? 8 : NTMAX)>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride);
+      expsum_mfma<RT, (NTMAX >= 8 ? 8 : NTMAX)>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf,
+                                                 vstride, grp, ngrp);
     else if (nt >= 4 && NTMAX >= 4)
-      expsum_mfma<RT, (NTMAX >= 4 ? 4 : NTMAX)>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride);
+      expsum_mfma<RT, (NTMAX >= 4 ? 4 : NTMAX)>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf,
+                                                 vstride, grp, ngrp);
     else
-      expsum_mfma<RT, 2>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride);
+      expsum_mfma<RT, 2>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride, grp, ngrp);
   } else {
     const cpx<double>* cc = reinterpret_cast<const cpx<double>*>(slot + kp.lay.ccomp);
     const cpx<double>* twd = (const cpx<double>*)tw;
     cpx<double>* Vd = (cpx<double>*)V;
     const int sb = f64_set_block(kp.S1);
     if (sb == 4)
-      expsum_f64_tiled<4, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride);
+      expsum_f64_tiled<4, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride, grp, ngrp);
     else if (sb == 3)
-      expsum_f64_tiled<3, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride);
+      expsum_f64_tiled<3, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride, grp, ngrp);
     else
-      expsum_f64_tiled<2, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride);
+      expsum_f64_tiled<2, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride, grp, ngrp);
   }
   __syncthreads();
-  add_noise<T>(V, vstride, p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
-  __syncthreads();
+  if (noise) {
+    add_noise<T>(V, vstride, p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
+    __syncthreads();
+  }
 }
 
 // The S+1 (or `nsets`) prime-length DFTs of a round (defined with the DFT step below).
@@ -1557,6 +1566,198 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
   }
 }
 
+// ------------------------------------------ several work-groups per signal --
+// Batches smaller than the chip (fewer signals than the device holds work-groups)
+// run with ngrp work-groups per signal, three kinds of launch: split_setup_kernel
+// (one work-group per signal: the per-signal set-up and the rounds up to the first
+// ordinary one), then per ordinary round split_sample_kernel (ngrp work-groups per
+// signal, group g sampling every ngrp-th block of column tiles, each point's sum
+// formed as in the one-group sampler) and split_post_kernel (one per signal: the
+// noise, the DFTs, subtraction, selection, decode and merge, then the rounds up to
+// the next ordinary one).  Verification rounds sample a single line and run whole
+// in the one-group kernels.  Signal b uses workspace slot b; its round state stays
+// in global memory between launches.  The outputs equal the one-kernel recovery's
+// bit for bit.
+
+// recover_kernel's round loop from the current state up to the next ordinary
+// round, which is left pending (st.split = 1, prime, axis and length set);
+// verification rounds run here whole; a finished signal writes its outputs
+// (st.split = 2).
+template <typename T>
+__device__ void split_advance(const KParams& kp, const KBatch& kb, const KOut& ko, char* slot,
+                              WgState& st, char* lds, cpx<T>* V, int* sh_part) {
+  while (st.i <= kp.max_rounds) {
+    const bool at_k = st.nR >= st.k && st.kv == 0;
+    if (at_k && (!kp.verify || st.verified)) break;
+    if (threadIdx.x == 0) {
+      st.kstar = at_k ? 0 : (st.nR < st.k ? st.k - st.nR : st.kv);
+      st.p = prime_for_round(kp, at_k ? 1 : st.kstar, st.i);
+      st.m0 = st.i % kp.d2;
+      if (st.p < 2 || st.p > kp.p_max) {
+        st.flag = 1;
+      } else {
+        int L = 1, lg = 0;
+        while (L < 2 * st.p - 1) {
+          L <<= 1;
+          ++lg;
+        }
+        st.L = L;
+        st.log2L = lg;
+      }
+    }
+    __syncthreads();
+    if (st.flag) {
+      if (threadIdx.x == 0) st.status = -2;  // SFFT_ERANGE
+      __syncthreads();
+      break;
+    }
+    if (!at_k) {
+      if (threadIdx.x == 0) st.split = 1;
+      __syncthreads();
+      return;
+    }
+    verify_round<T>(kp, kb, slot, st, lds, V, sh_part, nullptr);
+    if (threadIdx.x == 0) {
+      st.samples += st.p;
+      if (ko.trace) {
+        int32_t* tr = ko.trace + ((size_t)st.sig * kp.max_rounds + (st.i - 1)) * 8;
+        tr[0] = st.i;
+        tr[1] = 0;
+        tr[2] = st.p;
+        tr[3] = 0;
+        tr[4] = st.ncand;
+        tr[5] = 0;
+        tr[6] = st.nR;
+        tr[7] = 1;
+      }
+      st.i += 1;
+      if (st.ncand == 0) {
+        st.verified = 1;
+      } else {
+        const int room = st.k + max(16, (st.k + 7) / 8) - st.nR;
+        st.kv = min(min(st.ncand, st.k), room);
+        if (st.kv <= 0) {
+          st.kv = 0;
+          st.flag = 2;  // no room: stop with RESIDUAL_NONZERO
+        }
+      }
+    }
+    __syncthreads();
+    if (st.flag) break;
+  }
+  if (threadIdx.x == 0 && st.status == 0)
+    st.status = (st.nR < st.k) ? 1 : (st.nR > st.k || (kp.verify && !st.verified)) ? 2 : 0;
+  __syncthreads();
+  write_output(kp, ko, slot, st, lds);
+  if (threadIdx.x == 0) st.split = 2;
+  __syncthreads();
+}
+
+template <typename T, int RT>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+split_setup_kernel(KParams kp, KBatch kb, KOut ko, WgState* state) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  __shared__ int sh_part[kWG];
+  const int b = blockIdx.x;
+  char* slot = kp.ws + (size_t)b * kp.ws_slot;
+  cpx<T>* V = ws_cpx<T>(slot, kp.lay.V);
+  if (threadIdx.x == 0) {
+    WgState z;
+    memset(&z, 0, sizeof(z));
+    z.sig = b;
+    z.off = kb.mode_off[b];
+    z.M_pl = (int)(kb.mode_off[b + 1] - z.off);
+    z.k = kb.k[b];
+    z.sigma = kb.sigma[b];
+    z.i = 1;
+    if (z.M_pl > kp.k_max || z.M_pl < 0 || z.k < 1 || z.k > kp.k_max) z.flag = 1;
+    st = z;
+  }
+  __syncthreads();
+  if (st.flag) {
+    if (threadIdx.x == 0) {
+      if (ko.k_found) {
+        ko.k_found[b] = 0;
+        ko.status[b] = -1;  // SFFT_EINVAL
+        if (ko.rounds) ko.rounds[b] = 0;
+        if (ko.samples) ko.samples[b] = 0;
+      }
+      st.split = 2;
+      state[b] = st;
+    }
+    return;
+  }
+  planted_setup<T>(kp, kb, slot, st);
+  const int P0 = (st.M_pl + 1) / 2;
+  if constexpr (sizeof(T) == 4) {
+    scatter_afrag(kp, ws_cpx<float>(slot, kp.lay.ccomp),
+                  reinterpret_cast<float*>(slot + kp.lay.afrag), 0, 2 * P0);
+    __syncthreads();
+  }
+  if (ko.feat) export_sort_planted(kp, slot, st, lds);
+  split_advance<T>(kp, kb, ko, slot, st, lds, V, sh_part);
+  if (threadIdx.x == 0) state[b] = st;
+}
+
+template <typename T, int RT>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+split_sample_kernel(KParams kp, KBatch kb, const WgState* state, int ngrp) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  const int b = blockIdx.x / ngrp, g = blockIdx.x - b * ngrp;
+  if (threadIdx.x == 0) st = state[b];
+  __syncthreads();
+  if (st.split != 1) return;  // uniform over the work-group
+  char* slot = kp.ws + (size_t)b * kp.ws_slot;
+  cpx<T>* V = ws_cpx<T>(slot, kp.lay.V);
+  sample_round<T, RT>(kp, kb, slot, st, (st.M_pl + 1) / 2, lds, V, kp.vstride, g, ngrp, false);
+}
+
+template <typename T, int RT>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+split_post_kernel(KParams kp, KBatch kb, KOut ko, WgState* state) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  __shared__ int sh_part[kWG];
+  const int b = blockIdx.x;
+  char* slot = kp.ws + (size_t)b * kp.ws_slot;
+  cpx<T>* V = ws_cpx<T>(slot, kp.lay.V);
+  const int vstride = kp.vstride;
+  if (threadIdx.x == 0) st = state[b];
+  __syncthreads();
+  if (st.split != 1) return;
+  add_noise<T>(V, vstride, st.p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
+  __syncthreads();
+  dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
+  if (kp.residual == 0) subtract_registry<T>(kp, slot, st, lds, V, vstride, kp.S1, sh_part);
+  select_round<T>(kp, slot, st, lds, V, sh_part);
+  decode_round<T>(kp, ko, slot, st, V, vstride, lds, sh_part);
+  if (ko.feat) export_round(kp, kb, ko, slot, st, lds);
+  decode_finish(kp, st, lds, sh_part);
+  merge_round<T>(kp, slot, st, lds, sh_part, (st.M_pl + 1) / 2);
+  if (threadIdx.x == 0) {
+    st.samples += (int64_t)kp.S1 * st.p;
+    if (ko.trace) {
+      int32_t* tr = ko.trace + ((size_t)st.sig * kp.max_rounds + (st.i - 1)) * 8;
+      tr[0] = st.i;
+      tr[1] = st.kstar;
+      tr[2] = st.p;
+      tr[3] = st.m0 + 1;
+      tr[4] = st.ncand;
+      tr[5] = st.nacc;
+      tr[6] = st.nR;
+      tr[7] = 0;
+    }
+    st.kv = 0;
+    st.i += 1;
+    st.split = 0;
+  }
+  __syncthreads();
+  split_advance<T>(kp, kb, ko, slot, st, lds, V, sh_part);
+  if (threadIdx.x == 0) state[b] = st;
+}
+
 // ------------------------------------------ caller-supplied samples ------
 // A session recovers signals the library cannot evaluate itself: every round
 // is one launch, the caller samples f on the lines the session asks for, and
@@ -1951,6 +2152,26 @@ int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid
   return (int)hipGetLastError();
 }
 
+size_t split_state_bytes() { return sizeof(WgState); }
+
+// One set-up launch, then max_rounds (sample, post) pairs: every ordinary round
+// takes one round index, so no signal has more; launches past a signal's end
+// return at once.  No host synchronisation (the sequence can be captured).
+int launch_recover_split(const KParams& kp, const KBatch& kb, const KOut& ko, void* state,
+                         int ngrp, void* stream) {
+  hipStream_t hs = (hipStream_t)stream;
+  WgState* stt = reinterpret_cast<WgState*>(state);
+  SFFT_RT_DISPATCH(split_setup_kernel, dim3(kb.B), dim3(kWG), kp.lds_bytes, hs, kp, kb, ko, stt);
+  hipError_t e = hipGetLastError();
+  for (int r = 0; r < kp.max_rounds && e == hipSuccess; ++r) {
+    SFFT_RT_DISPATCH(split_sample_kernel, dim3(kb.B * ngrp), dim3(kWG), kp.lds_bytes, hs, kp,
+                     kb, (const WgState*)stt, ngrp);
+    SFFT_RT_DISPATCH(split_post_kernel, dim3(kb.B), dim3(kWG), kp.lds_bytes, hs, kp, kb, ko, stt);
+    e = hipGetLastError();
+  }
+  return (int)e;
+}
+
 // ------------------------------------------------ fixed device scratch ------
 // Workspace of sfft_recover_static: the work-queue counter in the first 256
 // bytes, then as many workspace slots as fit.  One copy per device, held
@@ -2088,7 +2309,14 @@ int set_kernel_lds_limits(int lds_bytes) {
       (const void*)sample_kernel<float, 8>,  (const void*)sample_kernel<double, 0>,
       (const void*)dft_kernel<float>,        (const void*)dft_kernel<double>,
       (const void*)session_feed_kernel<float>, (const void*)session_feed_kernel<double>,
-      (const void*)session_finish_kernel<float>, (const void*)session_finish_kernel<double>};
+      (const void*)session_finish_kernel<float>, (const void*)session_finish_kernel<double>,
+#define SFFT_SPLIT_FNS(K)                                                               \
+  (const void*)K<float, 1>, (const void*)K<float, 2>, (const void*)K<float, 3>,        \
+      (const void*)K<float, 4>, (const void*)K<float, 5>, (const void*)K<float, 6>,    \
+      (const void*)K<float, 7>, (const void*)K<float, 8>, (const void*)K<double, 0>
+      SFFT_SPLIT_FNS(split_setup_kernel), SFFT_SPLIT_FNS(split_sample_kernel),
+      SFFT_SPLIT_FNS(split_post_kernel)};
+#undef SFFT_SPLIT_FNS
   for (const void* f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (r != hipSuccess) e = r;

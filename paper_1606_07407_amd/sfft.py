@@ -57,6 +57,7 @@ class sfft_params(ctypes.Structure):
         ("order", ctypes.POINTER(ctypes.c_int32)),
         ("tilt", ctypes.c_int32),
         ("tilt_a", ctypes.c_int32), ("tilt_b", ctypes.c_int32), ("tilt_c", ctypes.c_int32),
+        ("split_groups", ctypes.c_int32),
     ]
 
 
@@ -211,6 +212,7 @@ class Params:
     order: tuple | None = None      # coordinate order (a permutation of 0..d-1)
     tilt: int = 0                   # 1: 2D tilting (d = 2); tilt_abc (0, 0, 0) = plan's triple
     tilt_abc: tuple = (0, 0, 0)
+    split_groups: int = 0           # work-groups per signal: 0 automatic, 1 one, 2..16
 
     def to_c(self) -> sfft_params:
         c = sfft_params(self.d, self.d1, self.N, self.k_max, self.c, self.prime_rule,
@@ -230,6 +232,7 @@ class Params:
             c.order = ctypes.cast(c._order, ctypes.POINTER(ctypes.c_int32))
         c.tilt = int(self.tilt)
         c.tilt_a, c.tilt_b, c.tilt_c = (int(v) for v in self.tilt_abc)
+        c.split_groups = int(self.split_groups)
         return c
 
 

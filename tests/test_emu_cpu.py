@@ -72,6 +72,11 @@ CASES = [
     ("c1_fp64_long_dft", "asan", "c1", {"p_min": 4200}, 1, 8, 1e-9, 0),
     ("c1_fp64_long_dft", "tsan", "c1", {"p_min": 4200}, 1, 8, 1e-9, 0),
     ("c3_fp32_long_dft", "asan", "c3b", {"p_min": 8300}, 1, 60, 1e-5, 0),
+    # several work-groups per signal: three launches per round, the sampling of each
+    # line dealt out over 3 (FP32) or 2 (FP64) work-groups
+    ("c3_fp32_split", "asan", "c3b", {"split": 3}, 2, 60, 1e-5, 0),
+    ("c3_fp32_split", "tsan", "c3b", {"split": 3}, 2, 60, 1e-5, 0),
+    ("c1_fp64_split", "asan", "c1", {"split": 2, "verify": True}, 2, 8, 1e-9, 0),
 ]
 
 
@@ -80,9 +85,13 @@ CASES = [
 def test_emulated_recovery_matches_oracle(name, kind, recipe, over, B, k, tol, entry):
     from paper_1606_07407_amd import sfft
     emu = _emu()
+    over = dict(over)
+    split = over.pop("split", 0)
     cfg = workloads.config(recipe, **over)
     pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], k, cfg["mag"], cfg["sigma"])
-    out = emu.run(kind, _params(sfft, cfg, k), pb, entry=entry)
+    prm = _params(sfft, cfg, k)
+    prm.split_groups = split
+    out = emu.run(kind, prm, pb, entry=entry)
     assert out["plan_status"] == 0 and out["call_status"] == 0, out["stderr"][-2000:]
     for b in range(B):
         w, a = pb.signal(b)

@@ -503,6 +503,38 @@ def test_recover_deterministic_and_reusable():
     plan.close()
 
 
+@pytest.mark.parametrize("cname,over,B,k,groups", [
+    ("c3b", {}, 8, 300, 4),                      # FP32, three MFMA row tiles, verification
+    ("c5", {}, 4, 4096, 8),                      # FP32, six row tiles, p = 8161
+    ("c5", {"c": 2.5}, 2, 4096, 3),              # and the DFT in four parts
+    ("e1", {}, 4, 512, 5),                       # FP64, d = 100
+    ("c3b", {"residual": 1}, 4, 200, 2),         # registry rows in the sampler
+])
+def test_split_groups_equal_one_kernel(cname, over, B, k, groups):
+    """Several work-groups per signal (three launches per round, the line's points dealt
+    out over the groups) give the one-kernel recovery's outputs bit for bit; the
+    automatic choice (split_groups = 0) too."""
+    import dataclasses
+    import torch
+    sfft = _sfft()
+    cfg = workloads.config(cname, **over)
+    _say(f"[split] {cname} {over} B={B} k={k} groups={groups}")
+    pb = workloads.planted_batch(cfg["seed"], B, cfg["d"], cfg["N"], k, cfg["mag"],
+                                 cfg["sigma"])
+    db = sfft.DeviceBatch.from_planted(pb)
+    outs = {}
+    for g in (1, groups, 0):
+        plan = sfft.sfft_plan_create(dataclasses.replace(_params(cfg, k), split_groups=g),
+                                     max_batch=B)
+        outs[g] = sfft.outputs_to_host(sfft.sfft_recover(plan, db))
+        torch.cuda.synchronize()
+        plan.close()
+    for g in (groups, 0):
+        for key in ("freqs", "coeffs", "k_found", "status", "rounds", "samples", "trace"):
+            assert np.array_equal(outs[1][key], outs[g][key]), (g, key)
+    _say(f"    statuses {outs[1]['status'].tolist()} rounds {outs[1]['rounds'].tolist()}")
+
+
 def test_full_size_headline_batch():
     """The bench's launch: 512 signals, d = 10, N = 65536, k = 1000, sigma = 1e-3, with
     c and the kernel schedules picked by the autotuner as the bench picks them.  Every
