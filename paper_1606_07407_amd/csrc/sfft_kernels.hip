@@ -2230,7 +2230,9 @@ int launch_recover_static(const KParams& kp, const KBatch& kb, const KOut& ko, i
   // the slots start as a new plan's workspace does (zeroed): another plan's
   // layout may have left anything there
   const size_t n16 = (kStaticQueueBytes + (size_t)grid * kp.ws_slot) / 16;
-  hipLaunchKernelGGL(zero_fill_kernel, dim3(1024), dim3(256), 0, (hipStream_t)stream,
+  // about 16 words per thread, at most 1024 work-groups
+  const int zb = (int)(n16 / 4096 + 1 < 1024 ? n16 / 4096 + 1 : 1024);
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(zb), dim3(256), 0, (hipStream_t)stream,
                      reinterpret_cast<uint4*>(base), n16);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;

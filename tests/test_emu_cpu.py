@@ -71,12 +71,14 @@ CASES = [
     # run as two halves through the workspace
     ("c1_fp64_long_dft", "asan", "c1", {"p_min": 4200}, 1, 8, 1e-9, 0),
     ("c1_fp64_long_dft", "tsan", "c1", {"p_min": 4200}, 1, 8, 1e-9, 0),
-    ("c3_fp32_long_dft", "asan", "c3b", {"p_min": 8300}, 1, 60, 1e-5, 0),
+    ("c3_fp32_long_dft", "asan", "c3b", {"p_min": 8300}, 1, 20, 1e-5, 0),
     # several work-groups per signal: three launches per round, the sampling of each
     # line dealt out over 3 (FP32) or 2 (FP64) work-groups
-    ("c3_fp32_split", "asan", "c3b", {"split": 3}, 2, 60, 1e-5, 0),
-    ("c3_fp32_split", "tsan", "c3b", {"split": 3}, 2, 60, 1e-5, 0),
-    ("c1_fp64_split", "asan", "c1", {"split": 2, "verify": True}, 2, 8, 1e-9, 0),
+    # (max_rounds bounds the launches: one pair per possible round)
+    ("c3_fp32_split", "asan", "c3b", {"split": 3, "max_rounds": 12}, 2, 60, 1e-5, 0),
+    ("c3_fp32_split", "tsan", "c3b", {"split": 3, "max_rounds": 12}, 2, 60, 1e-5, 0),
+    ("c1_fp64_split", "asan", "c1", {"split": 2, "verify": True, "max_rounds": 8}, 2, 8,
+     1e-9, 0),
 ]
 
 
