@@ -120,9 +120,9 @@ typedef struct {
                               1 = a radix-2 (n odd) and a radix-4 (n mod 4 >= 2) head
                               pass, then radix 16; 2 = the same, except one radix-8
                               head pass when n = 3 mod 4; 0 = 1                      */
-  int32_t sched_dft_batch; /* FP32: most sample sets transformed together in one
-                              Bluestein pass over the LDS buffer: 1 = one set at a
-                              time, 2..64, 0 = as many as fit                        */
+  int32_t sched_dft_batch; /* most sample sets transformed together in one Bluestein
+                              pass over the LDS buffer: 1 = one set at a time,
+                              2..64, 0 = as many as fit                              */
   /* General partitions (Section 4.1: a block's coordinates need not be in their
    * natural order and blocks need not have one size; Section 4.1.2: d prime).
    * Host arrays, read only by sfft_plan_create (and sfft_autotune), owned by the

@@ -355,7 +355,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
     need((size_t)(lds_padded(Mx) + bs_tab_entries(L, Mx)) * cs, L > maxL ? "DFT (in parts)" : "DFT");
   }
   need(align16((size_t)kp.p_max * cs) + 2 * align16(2 * (size_t)(sampler_m_max(kp) + 4)) +
-           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : 0),
+           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : kF64StageBytes),
        "sampler");
   need(align16((size_t)kp.p_max * (cs / 2)) + 4 * (size_t)kp.p_max + 4 * 256 + 16, "selection");
   need(decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max, "decode");

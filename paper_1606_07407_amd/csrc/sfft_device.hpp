@@ -1009,68 +1009,98 @@ __device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int S1, ui
 }
 
 // FP64 line sampler on the vector units, V[s][h] = sum_j C[j][s] omega_p^{(h r_j) mod p}
-// (C: [M][S1] coefficient rows, global; rr: r_j, LDS; tw: omega_p^x, LDS).  A work
-// item is a block of SB sets times 64 HB points; the four waves take items in turn,
-// lane l of a wave the points h0 + l + 64 u (u < HB).  Per mode the item's SB
-// coefficients are the same for the whole wave (one load each, served by the cache),
-// the HB twiddles come from the table at indices stepped by (64 r_j) mod p, and each
-// lane accumulates SB x HB complex sums in registers: one twiddle and one coefficient
-// read feed SB and HB products instead of one.
-// (grp / ngrp: several work-groups on one line, this one taking every ngrp-th
-// block of four items.)
+// (C: [M][S1] coefficient rows, global; rr: r_j, LDS; tw: omega_p^x, LDS).  A tile
+// is a block of SB sets times 64 HB points; the four waves of the work-group share
+// a tile, each summing a quarter of every chunk of kF64Chunk modes, whose
+// coefficients for the tile's sets are first staged in LDS (`stage`, kF64StageBytes):
+// per mode a wave reads SB coefficients (one address for all lanes) and HB twiddles
+// (indices stepped by (64 r_j) mod p), and each lane accumulates SB x HB complex
+// sums in registers.  The four partial sums are added in wave order through
+// `stage`.  (grp / ngrp: several work-groups on one line, this one taking every
+// ngrp-th tile.)
 template <int SB, int HB>
 __device__ void expsum_f64_tiled(const cpx<double>* __restrict__ C, const uint16_t* rr,
-                                 const cpx<double>* tw, int M, int p, int S1,
+                                 const cpx<double>* tw, cpx<double>* stage, int M, int p, int S1,
                                  cpx<double>* __restrict__ V, int vstride, int grp = 0,
                                  int ngrp = 1) {
+  static_assert(kF64Chunk * SB * 16 <= kF64StageBytes && SB * HB * 64 * 16 <= kF64StageBytes,
+                "FP64 sampler stage");
+  constexpr int NW = kWG / 64;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ngroups = (S1 + SB - 1) / SB;
   const int nchunks = (p + 64 * HB - 1) / (64 * HB);
   const float inv_p = 1.0f / (float)p;
-  for (int item = grp * (kWG / 64) + wave; item < ngroups * nchunks;
-       item += ngrp * (kWG / 64)) {
-    const int g = item / nchunks, hc = item - g * nchunks;
+  for (int tile = grp; tile < ngroups * nchunks; tile += ngrp) {
+    const int g = tile / nchunks, hc = tile - g * nchunks;
     const int s0 = g * SB;
     const uint32_t h0 = (uint32_t)(hc * 64 * HB + lane);
-    int sidx[SB];
-#pragma unroll
-    for (int b = 0; b < SB; ++b) sidx[b] = min(s0 + b, S1 - 1);  // padding sets repeat the last
     cpx<double> acc[SB][HB];
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
       for (int u = 0; u < HB; ++u) acc[b][u] = cmk<double>(0.0, 0.0);
-#pragma unroll 2
-    for (int j = 0; j < M; ++j) {
-      const uint32_t r = rr[j];
-      const uint32_t step = (uint32_t)mulmod(64u, r, p, inv_p);
-      uint32_t idx = (uint32_t)mulmod(h0, r, p, inv_p);
-      cpx<double> t[HB];
-#pragma unroll
-      for (int u = 0; u < HB; ++u) {
-        t[u] = tw[idx];
-        const uint32_t nx = idx + step;
-        idx = min(nx, nx - (uint32_t)p);  // nx - p wraps above nx when nx < p
+    for (int j0 = 0; j0 < M; j0 += kF64Chunk) {
+      const int jn = min(kF64Chunk, M - j0);
+      // the chunk's coefficients of the tile's sets (padding sets repeat the last)
+      for (int e = threadIdx.x; e < jn * SB; e += kWG) {
+        const int q = e / SB, b = e - q * SB;
+        stage[e] = C[(size_t)(j0 + q) * S1 + min(s0 + b, S1 - 1)];
       }
-      const cpx<double>* cj = C + (size_t)j * S1;
-#pragma unroll
-      for (int b = 0; b < SB; ++b) {
-        const cpx<double> c = cj[sidx[b]];
+      __syncthreads();
+      const int jq = (jn + NW - 1) / NW;
+      const int ja = wave * jq, jb = min(jn, ja + jq);
+#pragma unroll 2
+      for (int q = ja; q < jb; ++q) {
+        const uint32_t r = rr[j0 + q];
+        const uint32_t step = (uint32_t)mulmod(64u, r, p, inv_p);
+        uint32_t idx = (uint32_t)mulmod(h0, r, p, inv_p);
+        cpx<double> t[HB];
 #pragma unroll
         for (int u = 0; u < HB; ++u) {
-          acc[b][u].x = fma(c.x, t[u].x, fma(-c.y, t[u].y, acc[b][u].x));
-          acc[b][u].y = fma(c.x, t[u].y, fma(c.y, t[u].x, acc[b][u].y));
+          t[u] = tw[idx];
+          const uint32_t nx = idx + step;
+          idx = min(nx, nx - (uint32_t)p);  // nx - p wraps above nx when nx < p
+        }
+        const cpx<double>* cq = stage + q * SB;
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+          const cpx<double> c = cq[b];
+#pragma unroll
+          for (int u = 0; u < HB; ++u) {
+            acc[b][u].x = fma(c.x, t[u].x, fma(-c.y, t[u].y, acc[b][u].x));
+            acc[b][u].y = fma(c.x, t[u].y, fma(c.y, t[u].x, acc[b][u].y));
+          }
         }
       }
+      __syncthreads();
     }
+    // wave 0 adds the other waves' sums, in wave order
+    for (int w = 1; w < NW; ++w) {
+      if (wave == w) {
 #pragma unroll
-    for (int b = 0; b < SB; ++b)
+        for (int b = 0; b < SB; ++b)
 #pragma unroll
-      for (int u = 0; u < HB; ++u) {
-        const int s = s0 + b, h = (int)h0 + 64 * u;
-        if (s < S1 && h < p) V[(size_t)s * vstride + h] = acc[b][u];
+          for (int u = 0; u < HB; ++u) stage[(b * HB + u) * 64 + lane] = acc[b][u];
       }
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int b = 0; b < SB; ++b)
+#pragma unroll
+          for (int u = 0; u < HB; ++u) acc[b][u] = cadd(acc[b][u], stage[(b * HB + u) * 64 + lane]);
+      }
+      __syncthreads();
+    }
+    if (wave == 0) {
+#pragma unroll
+      for (int b = 0; b < SB; ++b)
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+          const int s = s0 + b, h = (int)h0 + 64 * u;
+          if (s < S1 && h < p) V[(size_t)s * vstride + h] = acc[b][u];
+        }
+    }
   }
 }
 

@@ -11,6 +11,8 @@ constexpr int kWG = 256;          // threads per work-group (4 waves of 64)
 constexpr int kMaxD2 = 256;       // largest number of unwrapped coordinates (FP32: also 2 (S+1) <= 128)
 constexpr int kMaxRT = 8;         // MFMA row tiles: 2 (S+1) real rows <= 128
 constexpr int kChunk = 16;        // sampler: A-fragment pairs staged in LDS per chunk
+constexpr int kF64Chunk = 256;    // FP64 sampler: modes whose coefficients are staged at once
+constexpr size_t kF64StageBytes = 16384;  // FP64 sampler: LDS for that stage and the wave sums
 constexpr int kTwiddleBits = 6;   // DFT twiddles exp(-2 pi i t / L) = T1[t >> 6] * T2[t & 63]
 // Largest FFT lengths held in LDS (FP32, FP64); Bluestein lengths up to 4 times
 // these run in 2 or 4 parts through the workspace.

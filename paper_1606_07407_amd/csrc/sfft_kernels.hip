@@ -306,13 +306,24 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     const cpx<double>* cc = reinterpret_cast<const cpx<double>*>(slot + kp.lay.ccomp);
     const cpx<double>* twd = (const cpx<double>*)tw;
     cpx<double>* Vd = (cpx<double>*)V;
+    cpx<double>* stage = reinterpret_cast<cpx<double>*>(abuf);
+    // short lines (p <= 64): one point per lane, so that fewer lanes idle past p
     const int sb = f64_set_block(kp.S1);
-    if (sb == 4)
-      expsum_f64_tiled<4, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride, grp, ngrp);
-    else if (sb == 3)
-      expsum_f64_tiled<3, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride, grp, ngrp);
-    else
-      expsum_f64_tiled<2, 4>(cc, rr, twd, 2 * npairs, p, kp.S1, Vd, vstride, grp, ngrp);
+    const int M2 = 2 * npairs;
+    if (p <= 64) {
+      if (sb == 4)
+        expsum_f64_tiled<4, 1>(cc, rr, twd, stage, M2, p, kp.S1, Vd, vstride, grp, ngrp);
+      else if (sb == 3)
+        expsum_f64_tiled<3, 1>(cc, rr, twd, stage, M2, p, kp.S1, Vd, vstride, grp, ngrp);
+      else
+        expsum_f64_tiled<2, 1>(cc, rr, twd, stage, M2, p, kp.S1, Vd, vstride, grp, ngrp);
+    } else if (sb == 4) {
+      expsum_f64_tiled<4, 4>(cc, rr, twd, stage, M2, p, kp.S1, Vd, vstride, grp, ngrp);
+    } else if (sb == 3) {
+      expsum_f64_tiled<3, 4>(cc, rr, twd, stage, M2, p, kp.S1, Vd, vstride, grp, ngrp);
+    } else {
+      expsum_f64_tiled<2, 4>(cc, rr, twd, stage, M2, p, kp.S1, Vd, vstride, grp, ngrp);
+    }
   }
   __syncthreads();
   if (noise) {
@@ -463,28 +474,26 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
   constexpr int ML = MaxL<T>::value;
   const int R = st.L > ML ? st.L / ML : 1;  // parts through the slot beyond the LDS maximum
   const int M = st.L / R;
-  // FP32: sets of short lengths are transformed together, the twiddle tables then
-  // sitting after the whole buffer (L_max points, at most the in-LDS maximum) so
-  // that up to min(L_max, 8192) / L sets fit
+  // sets of short lengths are transformed together, the twiddle tables then sitting
+  // after the whole buffer (L_max points, at most the in-LDS maximum) so that up to
+  // min(L_max, ML) / L sets fit
   constexpr int MAXV = MaxL<T>::value / kWG;
   const int Lb = min(kp.L_max, ML);
-  const bool batched = sizeof(T) == 4 && R == 1 && kp.sched_dft_batch != 1 &&
-                       st.L <= MAXV * kWG && 2 * st.L <= Lb;
+  const bool batched = R == 1 && kp.sched_dft_batch != 1 && st.L <= MAXV * kWG &&
+                       2 * st.L <= Lb;
   const BsTabs<T> tb = bs_tables<T>(st.L, M, buf + lds_padded(batched ? Lb : M));
   cpx<T>* G = ws_cpx<T>(slot, kp.lay.big);
   // s = -1 computes chirp and filter; one call site for every FFT of the step
   for (int s = -1; s < (batched ? 0 : nsets); ++s)
     bluestein_run<T>(s < 0, s < 0 ? nullptr : V + (size_t)s * vstride, st.p, st.L, R,
                      st.log2L - (R >> 1), chirp, bhat, G, buf, tb, kp.sched_fft);
-  if constexpr (sizeof(T) == 4) {
-    if (batched) {
-      int cap = min(Lb, MAXV * kWG) / st.L;
-      if (kp.sched_dft_batch > 1) cap = min(cap, kp.sched_dft_batch);
-      for (int s0 = 0; s0 < nsets; s0 += cap) {
-        const int g = min(cap, nsets - s0);
-        bluestein_dft_batch<T, MAXV>(V + (size_t)s0 * vstride, vstride, g, st.p, st.L, st.log2L,
-                                     chirp, bhat, buf, tb.T1M, kp.sched_fft);
-      }
+  if (batched) {
+    int cap = min(Lb, MAXV * kWG) / st.L;
+    if (kp.sched_dft_batch > 1) cap = min(cap, kp.sched_dft_batch);
+    for (int s0 = 0; s0 < nsets; s0 += cap) {
+      const int g = min(cap, nsets - s0);
+      bluestein_dft_batch<T, MAXV>(V + (size_t)s0 * vstride, vstride, g, st.p, st.L, st.log2L,
+                                   chirp, bhat, buf, tb.T1M, kp.sched_fft);
     }
   }
 }
