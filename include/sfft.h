@@ -153,10 +153,10 @@ typedef struct {
    * loop over the sets in Algorithm MultiPhaseshift needs no order), so a batch
    * smaller than the device runs each ordinary round's sampling on several
    * work-groups and the rest of the round on one (three launches per round, no
-   * host synchronisation; results identical bit for bit).  0: automatic (FP32
-   * plans: as many as fill the device, at most 8, when the batch takes at most
-   * half of it and k_max >= 256); 1: one work-group per signal (one launch);
-   * 2..16.  Phase timestamps (sfft_outputs.phase) come from the one launch. */
+   * host synchronisation; results identical bit for bit).  0: automatic (as
+   * many as fill the device, at most 8, when the batch takes at most half of
+   * it and k_max >= 256); 1: one work-group per signal (one launch); 2..16.  Split, the phase timestamps' sampling interval (marks 0 to 1) also
+   * holds the gap between the launches and the noise. */
   int32_t split_groups;
 } sfft_params;
 

@@ -221,18 +221,15 @@ static sfft_status validate_params(const sfft_params* p) {
 }
 
 // Work-groups per signal for a batch of B signals: the plan's split_groups, or
-// automatically (0), for FP32 plans, as many as fill the device (at most 8) when the
-// batch takes at most half of it and the rounds are large (k_max >= 256); 1 when
-// each signal needs its own slot and fewer are there, and with phase timestamps
-// (recorded by the one-kernel recovery only).  (Measured: the large FP32 workload,
-// 64 signals at k = 4096, runs 1.9x faster with 4 groups; the FP64 sweeps at
-// 100 signals run slower split, so FP64 plans split only when asked.)
-static int split_groups_for(const sfft_plan_s* plan, int B, bool phase) {
-  if (phase || B < 1 || B > plan->kp.n_slots) return 1;
+// automatically (0) as many as fill the device (at most 8) when the batch takes at
+// most half of it and the rounds are large (k_max >= 256); 1 when each signal needs
+// its own slot and fewer are there.  (Measured: 64 signals at d = 20, k = 4096, FP32,
+// 1.9x faster with 4 groups; 100 signals at d = 100, k = 1024, FP64, 1.2x with 2.)
+static int split_groups_for(const sfft_plan_s* plan, int B) {
+  if (B < 1 || B > plan->kp.n_slots) return 1;
   const int want = plan->prm.split_groups;
   if (want >= 1) return want;
-  if (plan->prm.precision != SFFT_FP32 || 2 * B > plan->capacity || plan->kp.k_max < 256)
-    return 1;
+  if (2 * B > plan->capacity || plan->kp.k_max < 256) return 1;
   return std::max(1, std::min(8, plan->capacity / B));
 }
 
@@ -366,7 +363,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
     need(align16(4 * ((size_t)kp.p_max + 1 + n2)) + 16 * (size_t)kp.cap,
          "registry subtraction (sorted entries)");
   }
-  need(4 * (size_t)kp.k_max, "output");
+  need(12 * (size_t)kp.k_max, "output");  // rank keys and ranks
   {
     // verification rounds use the prime for k* = 1: the max_rounds-th table prime
     // >= max(ceil(c), p_min)
@@ -402,6 +399,17 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
                 "prime %d)", lds, lds_step, kp.p_max);
   kp.lds_bytes = (int)lds;
 
+  // Lexicographic order of w equals that of y (the registry's order) only for blocks of
+  // one coordinate in the natural order, untilted; otherwise the output is ranked.
+  {
+    bool natural = !kp.tilt;
+    for (int q = 0; q < kp.d2; ++q)
+      if (blocks[q] != 1) natural = false;
+    for (int l = 0; l < P.d; ++l)
+      if (order[l] != l) natural = false;
+    kp.wrap_rank = natural ? 0 : 1;
+  }
+
   // Workspace layout of one slot.
   WsLayout lay;
   size_t o = 0;
@@ -429,6 +437,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   lay.pl_sorted = o; o = al256(o + 4 * (size_t)kp.k_max);
   lay.feat_tmp = o;  o = al256(o + 4 * 8 * (size_t)kp.k_max);
   lay.merge = o;     o = al256(o + (kp.merge_global ? merge_bytes : 0));
+  lay.wtmp = o;      o = al256(o + (kp.wrap_rank ? 8 * (size_t)kp.k_max * P.d : 0));
   lay.bytes = o;
   kp.lay = lay;
   kp.ws_slot = lay.bytes;
@@ -457,7 +466,6 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   // partition tables: block starts [d2 + 1], coordinate order [d], bands [d2][2]
   std::vector<int32_t> blk(kp.d2 + 1, 0);
   std::vector<int64_t> band(2 * (size_t)kp.d2, 0);
-  bool natural = true;
   const int64_t wlo = -(P.N / 2), whi = P.N / 2 - 1;
   for (int q = 0; q < kp.d2; ++q) {
     blk[q + 1] = blk[q] + blocks[q];
@@ -468,19 +476,14 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
     }
     band[2 * q] = wlo * s;
     band[2 * q + 1] = whi * s;
-    if (blocks[q] != 1) natural = false;
   }
-  for (int l = 0; l < P.d; ++l)
-    if (order[l] != l) natural = false;
   if (kp.tilt) {
     // y0 = b w0 - a w1, y1 = a w0 + b w1 over w in [wlo, whi]^2
     band[0] = tb * wlo - ta * whi;
     band[1] = tb * whi - ta * wlo;
     band[2] = (ta + tb) * wlo;
     band[3] = (ta + tb) * whi;
-    natural = false;
   }
-  kp.wrap_rank = natural ? 0 : 1;
   const size_t part_blk = 0, part_perm = al256(4 * (size_t)(kp.d2 + 1));
   const size_t part_band = part_perm + al256(4 * (size_t)P.d);
   const size_t part_bytes = part_band + 16 * (size_t)kp.d2;
@@ -600,7 +603,7 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
   ko.phase = out->phase;
   int e = launch_zero_queue(plan->kp, out->feat_count, stream);
   if (e) return hip_fail((hipError_t)e, "queue reset launch");
-  const int groups = split_groups_for(plan, batch->B, out->phase != nullptr);
+  const int groups = split_groups_for(plan, batch->B);
   if (groups > 1) {
     e = launch_recover_split(plan->kp, to_kbatch(batch), ko, plan->d_split, groups, stream);
     if (e) return hip_fail((hipError_t)e, "recover launch (several groups per signal)");

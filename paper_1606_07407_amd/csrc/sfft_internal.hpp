@@ -89,6 +89,7 @@ struct WsLayout {
   size_t pl_sorted;// int32  [k_max]            planted modes in lexicographic order (export)
   size_t feat_tmp; // float  [k_max][8]         candidate features (export)
   size_t merge;    // MergeLds carve-up when it does not stay in LDS (merge_global)
+  size_t wtmp;     // int64  [k_max][d]         outputs before ranking (wrap_rank only)
   size_t bytes;    // size of one slot
 };
 

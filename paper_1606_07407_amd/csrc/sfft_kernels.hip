@@ -1351,42 +1351,56 @@ __device__ void write_output(const KParams& kp, const KOut& ko, char* slot, WgSt
   double* co = ko.coeffs + (size_t)st.sig * kp.k_max * 2;
   const int nOut = min(nR, kp.k_max);
   const int64_t half = kp.N / 2;
-  // entries in registry order first (lexicographic in y)
+  // entries in registry order first (lexicographic in y): into the output when that is
+  // also the order of w, else into wtmp to be ranked
+  int64_t* wo = kp.wrap_rank ? reinterpret_cast<int64_t*>(slot + kp.lay.wtmp) : fo;
   for (int e = threadIdx.x; e < nOut && kp.tilt; e += kWG) {
     // rotation back, w = U y / c^2 (exact: decode admits only such y)
     const int64_t y0 = ry[(size_t)ord[e] * 2], y1 = ry[(size_t)ord[e] * 2 + 1];
-    fo[(size_t)e * 2] = (kp.tb * y0 + kp.ta * y1) / kp.tc2;
-    fo[(size_t)e * 2 + 1] = (kp.tb * y1 - kp.ta * y0) / kp.tc2;
+    wo[(size_t)e * 2] = (kp.tb * y0 + kp.ta * y1) / kp.tc2;
+    wo[(size_t)e * 2 + 1] = (kp.tb * y1 - kp.ta * y0) / kp.tc2;
   }
   for (int e = threadIdx.x; e < nOut && !kp.tilt; e += kWG) {
     for (int q = 0; q < d2; ++q) {
       int64_t rest = ry[(size_t)ord[e] * d2 + q];
       for (int l = kp.blk[q]; l < kp.blk[q + 1]; ++l) {
         const int64_t digit = pmod64(rest + half, kp.N) - half;
-        fo[(size_t)e * d + kp.perm[l]] = digit;
+        wo[(size_t)e * d + kp.perm[l]] = digit;
         rest = (rest - digit) / kp.N;
       }
     }
   }
   __syncthreads();
-  if (kp.wrap_rank && nOut > 1) {
-    // lexicographic order of w differs from that of y: rank and permute
-    int* rank = reinterpret_cast<int*>(lds);
+  if (kp.wrap_rank) {
+    // rank by lexicographic order of w: a key of the leading coordinates packed into 63
+    // bits (each shifted to [0, N)) decides most comparisons in LDS; equal keys compare
+    // the rows themselves
+    uint64_t* key = reinterpret_cast<uint64_t*>(lds);
+    int* rank = reinterpret_cast<int*>(lds + 8 * (size_t)kp.k_max);
+    int bits = 1;
+    while ((int64_t(1) << bits) < kp.N) ++bits;
+    const int nk = min(d, 63 / bits);
     for (int e = threadIdx.x; e < nOut; e += kWG) {
+      uint64_t kv = 0;
+      for (int i = 0; i < nk; ++i) kv = (kv << bits) | (uint64_t)(wo[(size_t)e * d + i] + half);
+      key[e] = kv;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nOut; e += kWG) {
+      const uint64_t ke = key[e];
       int rk = 0;
-      for (int f = 0; f < nOut; ++f)
-        if (lexcmp(fo + (size_t)f * d, fo + (size_t)e * d, d) < 0) ++rk;
+      for (int f = 0; f < nOut; ++f) {
+        const uint64_t kf = key[f];
+        if (kf < ke || (kf == ke && f != e &&
+                        lexcmp(wo + (size_t)f * d + nk, wo + (size_t)e * d + nk, d - nk) < 0))
+          ++rk;
+      }
       rank[e] = rk;
     }
     __syncthreads();
-    // stash w of each entry in the candidate-decode area, then scatter
-    int64_t* tmp = reinterpret_cast<int64_t*>(slot + kp.lay.acc_y);  // k_max * d2 * 8 bytes
-    // acc_y is too small for d columns in general; permute column by column
-    for (int col = 0; col < d; ++col) {
-      for (int e = threadIdx.x; e < nOut; e += kWG) tmp[e] = fo[(size_t)e * d + col];
-      __syncthreads();
-      for (int e = threadIdx.x; e < nOut; e += kWG) fo[(size_t)rank[e] * d + col] = tmp[e];
-      __syncthreads();
+    for (size_t q = threadIdx.x; q < (size_t)nOut * d; q += kWG) {
+      const int e = (int)(q / d), col = (int)(q - (size_t)e * d);
+      fo[(size_t)rank[e] * d + col] = wo[q];
     }
     for (int e = threadIdx.x; e < nOut; e += kWG) {
       co[2 * rank[e]] = ra[ord[e]].x;
@@ -1620,12 +1634,14 @@ __device__ void split_advance(const KParams& kp, const KBatch& kb, const KOut& k
       __syncthreads();
       break;
     }
+    phase_mark(kp, ko, st, 0);
     if (!at_k) {
       if (threadIdx.x == 0) st.split = 1;
       __syncthreads();
       return;
     }
     verify_round<T>(kp, kb, slot, st, lds, V, sh_part, nullptr);
+    phase_mark(kp, ko, st, 6);
     if (threadIdx.x == 0) {
       st.samples += st.p;
       if (ko.trace) {
@@ -1738,13 +1754,19 @@ split_post_kernel(KParams kp, KBatch kb, KOut ko, WgState* state) {
   if (st.split != 1) return;
   add_noise<T>(V, vstride, st.p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
   __syncthreads();
+  phase_mark(kp, ko, st, 1);  // (the sampling launch and the noise)
   dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
+  phase_mark(kp, ko, st, 2);
   if (kp.residual == 0) subtract_registry<T>(kp, slot, st, lds, V, vstride, kp.S1, sh_part);
+  phase_mark(kp, ko, st, 7);
   select_round<T>(kp, slot, st, lds, V, sh_part);
+  phase_mark(kp, ko, st, 3);
   decode_round<T>(kp, ko, slot, st, V, vstride, lds, sh_part);
   if (ko.feat) export_round(kp, kb, ko, slot, st, lds);
   decode_finish(kp, st, lds, sh_part);
+  phase_mark(kp, ko, st, 4);
   merge_round<T>(kp, slot, st, lds, sh_part, (st.M_pl + 1) / 2);
+  phase_mark(kp, ko, st, 5);
   if (threadIdx.x == 0) {
     st.samples += (int64_t)kp.S1 * st.p;
     if (ko.trace) {
