@@ -2136,17 +2136,36 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) d
   cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
   constexpr int ML = MaxL<T>::value;
   const int R = st.L > ML ? st.L / ML : 1;
-  const BsTabs<T> tb = bs_tables<T>(st.L, st.L / R, buf + lds_padded(st.L / R));
+  // short lengths: several sequences per batched pass, as in a round's DFTs
+  constexpr int MAXV = MaxL<T>::value / kWG;
+  const int Lb = min(kp.L_max, ML);
+  const bool batched = R == 1 && kp.sched_dft_batch != 1 && st.L <= MAXV * kWG &&
+                       2 * st.L <= Lb;
+  const BsTabs<T> tb = bs_tables<T>(st.L, st.L / R, buf + lds_padded(batched ? Lb : st.L / R));
   cpx<T>* G = ws_cpx<T>(slot, kp.lay.big);
-  // the first pass computes chirp and filter, then this group's sequences
+  int cap = 1;
+  if (batched) {
+    cap = min(Lb, MAXV * kWG) / st.L;
+    if (kp.sched_dft_batch > 1) cap = min(cap, kp.sched_dft_batch);
+  }
+  // the first pass computes chirp and filter, then this group's sequences: blocks of
+  // cap consecutive sequences, block b = blockIdx.x, blockIdx.x + gridDim.x, ...
   bool setup = true;
-  for (int q = blockIdx.x; q < count;) {
+  for (int q = blockIdx.x * cap; q < count && !batched;) {
     bluestein_run<T>(setup, setup ? nullptr : data + (size_t)q * p, p, st.L, R,
                      st.log2L - (R >> 1), chirp, bhat, G, buf, tb, kp.sched_fft);
     if (setup)
       setup = false;
     else
       q += gridDim.x;
+  }
+  if (batched) {
+    bluestein_run<T>(true, nullptr, p, st.L, 1, st.log2L, chirp, bhat, G, buf, tb, kp.sched_fft);
+    for (int q0 = blockIdx.x * cap; q0 < count; q0 += gridDim.x * cap) {
+      const int g = min(cap, count - q0);
+      bluestein_dft_batch<T, MAXV>(data + (size_t)q0 * p, p, g, p, st.L, st.log2L, chirp, bhat,
+                                   buf, tb.T1M, kp.sched_fft);
+    }
   }
 }
 

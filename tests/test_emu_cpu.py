@@ -129,10 +129,12 @@ def test_emulator_clean_kernel_passes():
 
 
 @pytest.mark.parametrize("prec,p", [("fp64", 4093), ("fp64", 4099), ("fp64", 8191),
-                                    ("fp32", 8191), ("fp32", 8209), ("fp32", 16381)])
+                                    ("fp32", 8191), ("fp32", 8209), ("fp32", 16381),
+                                    ("fp32", 127), ("fp64", 127)])
 def test_emulated_dft_matches_numpy(prec, p):
-    """sfft_dft under ASan at the longest in-LDS Bluestein lengths (16384 FP32, 8192
-    FP64) and beyond them, where the transforms run as two halves through the slot."""
+    """sfft_dft under ASan: short lengths transformed several sequences per pass, the
+    longest in-LDS Bluestein lengths (8192 FP32, 4096 FP64) and the longer ones that run in
+    two or four parts through the workspace."""
     from paper_1606_07407_amd import sfft
     emu = _emu()
     k_max = 3200 if prec == "fp32" else 1600
@@ -140,7 +142,7 @@ def test_emulated_dft_matches_numpy(prec, p):
                          precision=sfft.SFFT_FP32 if prec == "fp32" else sfft.SFFT_FP64)
     pb = workloads.planted_batch(1, 1, 2, 64, 1, (1.0, 2.0), 0.0)
     rng = np.random.default_rng(p)
-    x = rng.normal(size=(2, p)) + 1j * rng.normal(size=(2, p))
+    x = rng.normal(size=(5, p)) + 1j * rng.normal(size=(5, p))
     if prec == "fp32":
         x = x.astype(np.complex64).astype(np.complex128)
     out = emu.run("asan", params, pb, entry=2, dft_x=x)
