@@ -216,7 +216,11 @@ typedef struct {
  * 16384 (FP32) or 8192 (FP64): Bluestein lengths up to 16384 / 8192 points stay
  * in LDS, longer ones (up to twice that) run as two in-LDS halves through the
  * workspace.  SFFT_ERANGE also when a step's LDS carve-up at the largest prime
- * exceeds the work-group's LDS. */
+ * exceeds the work-group's LDS.  FP32 plans whose sampler cannot hold the whole
+ * table of p twiddles next to its staged operands keep p/2 + 1 of them (omega^(p-x)
+ * = conj omega^x); sfft_recover then always runs the several-groups launches (see
+ * split_groups, at most one signal per workspace slot) and sfft_recover_static
+ * refuses the plan (SFFT_ERANGE). */
 sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_plan* out);
 
 /* Release a plan and its workspace (synchronises the device first).  NULL is

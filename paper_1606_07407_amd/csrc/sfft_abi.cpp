@@ -229,6 +229,7 @@ static int split_groups_for(const sfft_plan_s* plan, int B) {
   if (B < 1 || B > plan->kp.n_slots) return 1;
   const int want = plan->prm.split_groups;
   if (want >= 1) return want;
+  if (plan->kp.tw_half) return std::max(1, std::min(8, plan->capacity / B));
   if (2 * B > plan->capacity || plan->kp.k_max < 256) return 1;
   return std::max(1, std::min(8, plan->capacity / B));
 }
@@ -351,9 +352,17 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
     const int Mx = std::min(L, maxL);
     need((size_t)(lds_padded(Mx) + bs_tab_entries(L, Mx)) * cs, L > maxL ? "DFT (in parts)" : "DFT");
   }
-  need(align16((size_t)kp.p_max * cs) + 2 * align16(2 * (size_t)(sampler_m_max(kp) + 4)) +
-           (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256 : kF64StageBytes),
-       "sampler");
+  {
+    // the sampler's twiddle table: all p points, or (FP32) p/2 + 1 when the whole table and
+    // the staged A fragments do not fit
+    const size_t rest = 2 * align16(2 * (size_t)(sampler_m_max(kp) + 4)) +
+                        (P.precision == SFFT_FP32 ? 2 * (size_t)(kChunk + 1) * kp.RT * 256
+                                                  : kF64StageBytes);
+    const size_t full = align16((size_t)kp.p_max * cs) + rest;
+    kp.tw_half = 0;
+    if (P.precision == SFFT_FP32 && full > kLdsLimit) kp.tw_half = 1;
+    need(kp.tw_half ? align16((size_t)(kp.p_max / 2 + 1) * cs) + rest : full, "sampler");
+  }
   need(align16((size_t)kp.p_max * (cs / 2)) + 4 * (size_t)kp.p_max + 4 * 256 + 16, "selection");
   need(decode_lds_cnt(kp.k_max) + 4 * (size_t)kp.p_max, "decode");
   {
@@ -394,7 +403,7 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
   kp.merge_global = merge_bytes > lds ? 1 : 0;
   if (!kp.merge_global) need(merge_bytes, "merge");
   lds = align16(lds);
-  if (lds > 160 * 1024 - 4096)
+  if (lds > kLdsLimit)
     return fail(SFFT_ERANGE, "plan needs %zu bytes of LDS per work-group (%s step, largest "
                 "prime %d)", lds, lds_step, kp.p_max);
   kp.lds_bytes = (int)lds;
@@ -604,7 +613,10 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
   int e = launch_zero_queue(plan->kp, out->feat_count, stream);
   if (e) return hip_fail((hipError_t)e, "queue reset launch");
   const int groups = split_groups_for(plan, batch->B);
-  if (groups > 1) {
+  if (plan->kp.tw_half && batch->B > plan->kp.n_slots)
+    return fail(SFFT_ERANGE, "this plan's lines run as the several-groups recovery, one "
+                "workspace slot per signal: at most %d signals", plan->kp.n_slots);
+  if (groups > 1 || plan->kp.tw_half) {
     e = launch_recover_split(plan->kp, to_kbatch(batch), ko, plan->d_split, groups, stream);
     if (e) return hip_fail((hipError_t)e, "recover launch (several groups per signal)");
     return SFFT_OK;
@@ -624,6 +636,8 @@ sfft_status sfft_recover_static(sfft_plan plan, const sfft_signal_batch* batch,
     return fail(SFFT_EINVAL, "outputs need freqs, coeffs, k_found and status");
   if (out->feat || out->label || out->feat_meta || out->feat_count)
     return fail(SFFT_EINVAL, "sfft_recover_static does not export features");
+  if (plan->kp.tw_half)
+    return fail(SFFT_ERANGE, "this plan's lines need the several-groups recovery (sfft_recover)");
   if (plan->kp.ws_slot + kStaticQueueBytes > kStaticScratchBytes)
     return fail(SFFT_ERANGE,
                 "one workspace slot of this plan takes %zu bytes; the fixed scratch holds %zu",

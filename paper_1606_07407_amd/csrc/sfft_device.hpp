@@ -804,14 +804,23 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // B fragments of one K step: omega_p^{((h0 + 16 u) r) mod p} (Re or Im part
 // selected by the caller's table offset) for the NT column tiles of a lane;
 // `step` = (16 r) mod p.
-template <int NT>
+// HALF: the table holds omega_p^x for x <= p/2 only (long lines whose full table does
+// not fit in LDS); omega_p^x = conj(omega_p^(p - x)) above that, so the lanes reading
+// the imaginary part (neg_im) negate it there.
+template <int NT, bool HALF = false>
 __device__ __forceinline__ void twiddle_column(const float* twf, uint32_t h0, uint32_t r,
                                                uint32_t step, uint32_t p, float inv_p,
-                                               float* b) {
+                                               float* b, bool neg_im = false) {
   uint32_t idx = mulmod24(h0, r, p, inv_p);
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
-    b[u] = twf[2 * idx];
+    if constexpr (HALF) {
+      const uint32_t j = min(idx, p - idx);
+      const float v = twf[2 * j];
+      b[u] = (neg_im && j != idx) ? -v : v;
+    } else {
+      b[u] = twf[2 * idx];
+    }
     const uint32_t t = idx + step;
     idx = min(t, t - p);  // t - p wraps above t when t < p
   }
@@ -820,7 +829,7 @@ __device__ __forceinline__ void twiddle_column(const float* twf, uint32_t h0, ui
 // grp / ngrp: when ngrp work-groups share the line, this group takes the
 // column-tile blocks grp, grp + ngrp, ... (block = one tile per wave); every
 // point's sum is formed the same way whichever group computes it.
-template <int RT, int NT, bool BLK = (RT * NT <= 12)>
+template <int RT, int NT, bool HALF = false, bool BLK = (RT * NT <= 12)>
 __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
                             const uint16_t* rs,
                             const cpx<float>* tw, float* abuf, int npairs, int p, int S1,
@@ -869,7 +878,8 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
 #pragma unroll
     for (int t = 0; t < RT; ++t) a_cur[t] = abuf[t * 64 + lane];
     const uint32_t up = (uint32_t)p;
-    twiddle_column<NT>(twf, h0, (uint32_t)rr[jsel], (uint32_t)rs[jsel], up, inv_p, b_cur);
+    twiddle_column<NT, HALF>(twf, h0, (uint32_t)rr[jsel], (uint32_t)rs[jsel], up, inv_p, b_cur,
+                             tpart == 1);
     uint32_t r1 = (uint32_t)rr[2 + jsel];       // residue of step pr + 1
     uint32_t s1 = (uint32_t)rs[2 + jsel];
     for (int c = 0; c < nchunks; ++c) {
@@ -897,7 +907,7 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
           // operands of step pr + 1 (A from this chunk buffer, twiddles from the
           // residue loaded one step earlier) and the residue of step pr + 2
           float a_nxt[RT], b_nxt[NT];
-          twiddle_column<NT>(twf, h0, r1, s1, up, inv_p, b_nxt);
+          twiddle_column<NT, HALF>(twf, h0, r1, s1, up, inv_p, b_nxt, tpart == 1);
 #pragma unroll
           for (int t = 0; t < RT; ++t) a_nxt[t] = ab[(q + 1) * PAIR + t * 64 + lane];
           const uint32_t r2 = (uint32_t)rr[2 * (pr + 2) + jsel];

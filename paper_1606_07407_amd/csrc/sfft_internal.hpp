@@ -8,6 +8,8 @@
 namespace sfft {
 
 constexpr int kWG = 256;          // threads per work-group (4 waves of 64)
+constexpr size_t kLdsLimit = 160 * 1024 - 4096;  // dynamic LDS per work-group (the rest
+                                                 // is the kernels' static LDS)
 constexpr int kMaxD2 = 256;       // largest number of unwrapped coordinates (FP32: also 2 (S+1) <= 128)
 constexpr int kMaxRT = 8;         // MFMA row tiles: 2 (S+1) real rows <= 128
 constexpr int kChunk = 16;        // sampler: A-fragment pairs staged in LDS per chunk
@@ -118,6 +120,8 @@ struct KParams {
   double verify_eta;
   int residual;           // 0: registry subtracted from the spectra, 1: from the samples
   int sub_cs;             // FP32 spectrum subtraction: sets per LDS-staged block (0: unstaged)
+  int tw_half;            // FP32 sampler: twiddle table of p/2 + 1 points (long lines; the
+                          // recovery then runs as the several-groups launches)
   int sched_nt[kNtBands]; // sampler column tiles per wave per p band (0: built-in choice)
   int sched_fft;          // kFftRadix24Head or kFftRadix8Head
   int sched_dft_batch;    // FP32: most sets per batched Bluestein pass (0: all that fit)

@@ -253,7 +253,9 @@ __device__ void rebuild_rows(const KParams& kp, char* slot, WgState& st, int P0,
 // subtracted after the DFT (subtract_registry).
 // grp / ngrp: ngrp work-groups share the line, this one computing its share of
 // the points (see expsum_mfma); noise = false leaves the noise to the caller.
-template <typename T, int RT>
+// HALF (FP32): the twiddle table holds only omega_p^x for x <= p/2 (plans whose lines
+// are too long for the whole table next to the staged A fragments).
+template <typename T, int RT, bool HALF = false>
 __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, WgState& st,
                              int P0, char* lds, cpx<T>* V, int vstride, int grp = 0,
                              int ngrp = 1, bool noise = true) {
@@ -263,14 +265,17 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
   // residues and column steps fit 16 bits (p <= 16384)
   const int msm = sampler_m_max(kp);
-  uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16((size_t)kp.p_max * sizeof(cpx<T>)));
+  // LDS: twiddle table [p_max, or p_max / 2 + 1] | residues | column steps | A stage
+  const size_t ntab = HALF ? (size_t)(kp.p_max / 2 + 1) : (size_t)kp.p_max;
+  uint16_t* rr = reinterpret_cast<uint16_t*>(lds + align16(ntab * sizeof(cpx<T>)));
   uint16_t* rs = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(rr) +
                                              align16(2 * (size_t)(msm + 4)));
   float* abuf = reinterpret_cast<float*>(reinterpret_cast<char*>(rs) +
                                          align16(2 * (size_t)(msm + 4)));
   const int64_t* ypl = reinterpret_cast<const int64_t*>(slot + kp.lay.ypl);
   const int64_t* ry = reg_y(kp, slot, st.sb);
-  for (int x = threadIdx.x; x < p; x += kWG) {
+  const int ntw = HALF ? p / 2 + 1 : p;
+  for (int x = threadIdx.x; x < ntw; x += kWG) {
     double c, s;
     expipi(2.0 * (double)x / (double)p, &c, &s);  // omega_p^x = exp(2 pi i x / p)
     tw[x] = cmk<T>((T)c, (T)s);
@@ -295,13 +300,14 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     const cpx<float>* twc = (const cpx<float>*)tw;
     cpx<float>* Vf = (cpx<float>*)V;
     if (nt >= 8 && NTMAX >= 8)
-      expsum_mfma<RT, (NTMAX >= 8 ? 8 : NTMAX)>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf,
-                                                 vstride, grp, ngrp);
+      expsum_mfma<RT, (NTMAX >= 8 ? 8 : NTMAX), HALF>(af, rr, rs, twc, abuf, npairs, p, kp.S1,
+                                                       Vf, vstride, grp, ngrp);
     else if (nt >= 4 && NTMAX >= 4)
-      expsum_mfma<RT, (NTMAX >= 4 ? 4 : NTMAX)>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf,
-                                                 vstride, grp, ngrp);
+      expsum_mfma<RT, (NTMAX >= 4 ? 4 : NTMAX), HALF>(af, rr, rs, twc, abuf, npairs, p, kp.S1,
+                                                       Vf, vstride, grp, ngrp);
     else
-      expsum_mfma<RT, 2>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride, grp, ngrp);
+      expsum_mfma<RT, 2, HALF>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride, grp,
+                               ngrp);
   } else {
     const cpx<double>* cc = reinterpret_cast<const cpx<double>*>(slot + kp.lay.ccomp);
     const cpx<double>* twd = (const cpx<double>*)tw;
@@ -1736,7 +1742,11 @@ split_sample_kernel(KParams kp, KBatch kb, const WgState* state, int ngrp) {
   if (st.split != 1) return;  // uniform over the work-group
   char* slot = kp.ws + (size_t)b * kp.ws_slot;
   cpx<T>* V = ws_cpx<T>(slot, kp.lay.V);
-  sample_round<T, RT>(kp, kb, slot, st, (st.M_pl + 1) / 2, lds, V, kp.vstride, g, ngrp, false);
+  if (sizeof(T) == 4 && kp.tw_half)
+    sample_round<T, RT, true>(kp, kb, slot, st, (st.M_pl + 1) / 2, lds, V, kp.vstride, g, ngrp,
+                              false);
+  else
+    sample_round<T, RT>(kp, kb, slot, st, (st.M_pl + 1) / 2, lds, V, kp.vstride, g, ngrp, false);
 }
 
 template <typename T, int RT>
@@ -2084,7 +2094,10 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) s
     }
     cpx<T>* Vs = Vout + (size_t)sig * kp.S1 * p;
     if (kp.residual == 1) rebuild_rows<T>(kp, slot, st, P0, false);
-    sample_round<T, RT>(kp, kb, slot, st, P0, lds, Vs, p);
+    if (sizeof(T) == 4 && kp.tw_half)
+      sample_round<T, RT, true>(kp, kb, slot, st, P0, lds, Vs, p);
+    else
+      sample_round<T, RT>(kp, kb, slot, st, P0, lds, Vs, p);
     // spectrum-mode plans subtract the registry after the DFT; here the caller
     // asked for samples: V[s][h] -= sum_e a_e exp(2 pi i y_e . t_{s,h}), FP64 per value
     if (kp.residual == 0 && st.nR > 0) {

@@ -50,6 +50,8 @@ CASES = {
     "c5_full_c149": dict(recipe="c5", over={"c": 1.49}, B=64, k=4096, signals=(0, 1)),
     # and at c = 2.5 (first prime 10243: Bluestein length 32768, past the in-LDS FFT)
     "c5_full_c25": dict(recipe="c5", over={"c": 2.5}, B=64, k=4096, signals=(0, 1)),
+    # and at c = 3 (first prime 12301: the sampler keeps half the twiddle table)
+    "c5_full_c30": dict(recipe="c5", over={"c": 3.0}, B=64, k=4096, signals=(0, 1)),
     # the classifier workload's signals at full size, plain ratio test: d = 6, N = 4096,
     # k = 2000, sigma ~ U[0, 1e-2] per signal.  Signals 3 and 11 are the two least noisy of
     # the 16 (sigma 1.07e-3 and 1.31e-3): above sigma ~ 3e-3 the plain test's decisions

@@ -79,6 +79,10 @@ CASES = [
     ("c3_fp32_split", "tsan", "c3b", {"split": 3, "max_rounds": 12}, 2, 60, 1e-5, 0),
     ("c1_fp64_split", "asan", "c1", {"split": 2, "verify": True, "max_rounds": 8}, 2, 8,
      1e-9, 0),
+    # lines too long for the whole twiddle table next to six row tiles of staged A
+    # fragments: the sampler keeps p/2 + 1 twiddles (and the recovery runs split)
+    ("c5_fp32_half_table", "asan", "c5", {"p_min": 14500, "verify": False, "max_rounds": 2},
+     1, 12, 1e-5, 0),
 ]
 
 

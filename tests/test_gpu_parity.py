@@ -507,6 +507,7 @@ def test_recover_deterministic_and_reusable():
     ("c3b", {}, 8, 300, 4),                      # FP32, three MFMA row tiles, verification
     ("c5", {}, 4, 4096, 8),                      # FP32, six row tiles, p = 8161
     ("c5", {"c": 2.5}, 2, 4096, 3),              # and the DFT in four parts
+    ("c5", {"c": 3.0}, 2, 4096, 4),              # and half the sampler's twiddle table
     ("e1", {}, 4, 512, 5),                       # FP64, d = 100
     ("c3b", {"residual": 1}, 4, 200, 2),         # registry rows in the sampler
 ])
