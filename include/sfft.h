@@ -113,9 +113,9 @@ typedef struct {
    * same results up to FP32 rounding; 0 takes the built-in choice, and
    * sfft_autotune picks them by measurement. */
   int32_t sched_nt[4];     /* FP32 sampler: 16-point column tiles per wave in rounds
-                              with p < 320, < 640, < 1600 and >= 1600: 2 or 4, or 8 in
-                              the last two bands (below 640 points the chunked FP32
-                              accumulation needs at most 4); 0 = chosen from p      */
+                              with p < 320, < 640, < 1600 and >= 1600: 2 to 4, or up
+                              to 8 in the last two bands (below 640 points the chunked
+                              FP32 accumulation needs at most 4); 0 = chosen from p */
   int32_t sched_fft;       /* passes of the power-of-two FFTs inside Bluestein, L = 2^n:
                               1 = a radix-2 (n odd) and a radix-4 (n mod 4 >= 2) head
                               pass, then radix 16; 2 = the same, except one radix-8

@@ -208,7 +208,7 @@ static sfft_status validate_params(const sfft_params* p) {
     return fail(SFFT_EINVAL, "unknown residual mode");
   for (int b = 0; b < kNtBands; ++b) {
     const int v = p->sched_nt[b];
-    const bool ok = v == 0 || v == 2 || v == 4 || (v == 8 && b >= 2);
+    const bool ok = v == 0 || (v >= 2 && v <= (b >= 2 ? 8 : 4));
     if (!ok) return fail(SFFT_EINVAL, "sched_nt[%d] = %d is not allowed", b, v);
   }
   if (p->sched_fft < 0 || p->sched_fft > kFftRadix8Head)

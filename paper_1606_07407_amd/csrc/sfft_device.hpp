@@ -975,13 +975,15 @@ __device__ void expsum_mfma(const float* __restrict__ afrag, const uint16_t* rr,
 
 // Column tiles per wave for a round with prime p: the widest tile (best reuse
 // of each A fragment) that still gives every wave about the same number of
-// columns; a tile pass costs about 4 columns' worth of fixed overhead.
+// columns; a tile pass costs about 4 column tiles' worth of fixed overhead.  Any
+// width from 2 to 8 tiles: e.g. p = 323 takes 7 tiles of 48 points in two passes
+// (96 points per wave) where 64-point tiles would need 128.
 __host__ __device__ inline int choose_nt(int p) {
   // below 640 points the chunk-blocked accumulation (at most 4 column tiles)
   // keeps the FP32 error of the long planted sum small relative to F / p
   int best = 8;
   int best_cost = 1 << 30;
-  for (int nt = (p < 640 ? 4 : 8); nt >= 2; nt >>= 1) {
+  for (int nt = (p < 640 ? 4 : 8); nt >= 2; --nt) {
     const int tiles = (p + 16 * nt - 1) / (16 * nt);
     const int passes = (tiles + 3) / 4;
     const int cost = passes * (16 * nt + 64);

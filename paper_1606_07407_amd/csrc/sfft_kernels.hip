@@ -299,15 +299,19 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     const int nt = min(nt_plan > 0 ? nt_plan : choose_nt(p), NTMAX);
     const cpx<float>* twc = (const cpx<float>*)tw;
     cpx<float>* Vf = (cpx<float>*)V;
-    if (nt >= 8 && NTMAX >= 8)
-      expsum_mfma<RT, (NTMAX >= 8 ? 8 : NTMAX), HALF>(af, rr, rs, twc, abuf, npairs, p, kp.S1,
-                                                       Vf, vstride, grp, ngrp);
-    else if (nt >= 4 && NTMAX >= 4)
-      expsum_mfma<RT, (NTMAX >= 4 ? 4 : NTMAX), HALF>(af, rr, rs, twc, abuf, npairs, p, kp.S1,
-                                                       Vf, vstride, grp, ngrp);
-    else
-      expsum_mfma<RT, 2, HALF>(af, rr, rs, twc, abuf, npairs, p, kp.S1, Vf, vstride, grp,
-                               ngrp);
+#define SFFT_EXPSUM(NTV)                                                                   \
+  expsum_mfma<RT, (NTV <= NTMAX ? NTV : NTMAX), HALF>(af, rr, rs, twc, abuf, npairs, p, kp.S1, \
+                                                      Vf, vstride, grp, ngrp)
+    switch (nt) {
+      case 8: SFFT_EXPSUM(8); break;
+      case 7: SFFT_EXPSUM(7); break;
+      case 6: SFFT_EXPSUM(6); break;
+      case 5: SFFT_EXPSUM(5); break;
+      case 4: SFFT_EXPSUM(4); break;
+      case 3: SFFT_EXPSUM(3); break;
+      default: SFFT_EXPSUM(2); break;
+    }
+#undef SFFT_EXPSUM
   } else {
     const cpx<double>* cc = reinterpret_cast<const cpx<double>*>(slot + kp.lay.ccomp);
     const cpx<double>* twd = (const cpx<double>*)tw;
@@ -668,10 +672,27 @@ __device__ void subtract_registry_f32_staged(const KParams& kp, char* slot, WgSt
   const double pd = (double)p;
   for (int s0 = 0; s0 < nsets; s0 += CS) {
     const int cs = min(CS, nsets - s0);
-    for (int q = threadIdx.x; q < nR * cs; q += kWG) {
-      const int g = q / cs, u = q - g * cs;
-      const int s = s0 + u;
-      Es[(size_t)g * CS + u] = (s > 0) ? sE[(size_t)list[g] * S + s - 1] : cmk<float>(1.f, 0.f);
+    // U copies per thread at a time: their global loads are issued together, before
+    // any of the LDS stores
+    constexpr int U = 8;
+    const int nq = nR * cs;
+    for (int q0 = threadIdx.x; q0 < nq; q0 += U * kWG) {
+      cpx<float> ev[U];
+      int dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * kWG;
+        ev[u] = cmk<float>(1.f, 0.f);
+        dst[u] = -1;
+        if (q < nq) {
+          const int g = q / cs, w = q - g * cs;
+          dst[u] = g * CS + w;
+          if (s0 + w > 0) ev[u] = sE[(size_t)list[g] * S + s0 + w - 1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (dst[u] >= 0) Es[dst[u]] = ev[u];
     }
     __syncthreads();
     // set index fastest: neighbouring threads read neighbouring phases
@@ -858,12 +879,18 @@ __device__ void select_round(const KParams& kp, char* slot, WgState& st, char* l
 
 // Ratio F_s[h] / F_0[h] in FP64.
 template <typename T>
-__device__ __forceinline__ void ratio(const cpx<T>* V, int vstride, int s, int h, double f0x,
-                                      double f0y, double den, double* rx, double* ry) {
-  const double fx = (double)V[(size_t)s * vstride + h].x;
-  const double fy = (double)V[(size_t)s * vstride + h].y;
+__device__ __forceinline__ void ratio_of(cpx<T> v, double f0x, double f0y, double den,
+                                         double* rx, double* ry) {
+  const double fx = (double)v.x;
+  const double fy = (double)v.y;
   *rx = (fx * f0x + fy * f0y) / den;
   *ry = (fy * f0x - fx * f0y) / den;
+}
+
+template <typename T>
+__device__ __forceinline__ void ratio(const cpx<T>* V, int vstride, int s, int h, double f0x,
+                                      double f0y, double den, double* rx, double* ry) {
+  ratio_of<T>(V[(size_t)s * vstride + h], f0x, f0y, den, rx, ry);
 }
 
 // The 8 classifier features of bucket h (see include/sfft.h): ratios of the
@@ -931,17 +958,27 @@ __device__ void decode_round(const KParams& kp, const KOut& ko, char* slot, WgSt
     const double den = f0x * f0x + f0y * f0y;
     int64_t* y = acc_y + (size_t)c * d2;
     bool valid = true;
+    const bool lad = kp.ladder_K > 1;
+    // the values of coordinate n + 1 are loaded before coordinate n is decoded, so
+    // that their latency overlaps its arithmetic (V is only read here)
+    cpx<T> vc = V[(size_t)vstride + h];
+    cpx<T> vf = lad ? V[(size_t)(d2 + 1) * vstride + h] : cmk<T>((T)0, (T)0);
     for (int n = 0; n < d2; ++n) {
+      cpx<T> vc1 = vc, vf1 = vf;
+      if (n + 1 < d2) {
+        vc1 = V[(size_t)(n + 2) * vstride + h];
+        if (lad) vf1 = V[(size_t)(d2 + n + 2) * vstride + h];
+      }
       double rx, ry;
-      ratio<T>(V, vstride, n + 1, h, f0x, f0y, den, &rx, &ry);
+      ratio_of<T>(vc, f0x, f0y, den, &rx, &ry);
       double th = atan2(ry, rx);
       if (th >= M_PI) th = -M_PI;
       const double yc_real = th * NBd / M_PI;
       int64_t yn = llround(yc_real);
-      if (kp.ladder_K > 1) {
+      if (lad) {
         const int64_t K = kp.ladder_K;
         double sx, sy;
-        ratio<T>(V, vstride, d2 + n + 1, h, f0x, f0y, den, &sx, &sy);
+        ratio_of<T>(vf, f0x, f0y, den, &sx, &sy);
         double thf = atan2(sy, sx);
         if (thf >= M_PI) thf = -M_PI;
         const int64_t q = pmod64(K * yn, 2 * NB);
@@ -952,6 +989,8 @@ __device__ void decode_round(const KParams& kp, const KOut& ko, char* slot, WgSt
       }
       if (yn < kp.band[2 * n] || yn > kp.band[2 * n + 1]) valid = false;
       y[n] = yn;
+      vc = vc1;
+      vf = vf1;
     }
     if (kp.tilt && valid) {
       // tilted: y must be U^T w for an integer w in the box (U y divisible by c^2)
@@ -976,10 +1015,13 @@ __device__ void decode_round(const KParams& kp, const KOut& ko, char* slot, WgSt
       double thr = kp.tau;
       if (kp.tau_noise > 0.0) thr += kp.tau_noise * sqrt((double)p) / absF0;
       ok = valid;
+      cpx<T> vs = ok ? V[(size_t)vstride + h] : cmk<T>((T)0, (T)0);
       for (int s = 1; s <= S && ok; ++s) {
+        const cpx<T> vn = (s < S) ? V[(size_t)(s + 1) * vstride + h] : vs;
         double rx, ry;
-        ratio<T>(V, vstride, s, h, f0x, f0y, den, &rx, &ry);
+        ratio_of<T>(vs, f0x, f0y, den, &rx, &ry);
         if (!(fabs(hypot(rx, ry) - 1.0) < thr)) ok = false;
+        vs = vn;
       }
     }
     if (exporting) {
@@ -1292,16 +1334,35 @@ __device__ void merge_round(const KParams& kp, char* slot, WgState& st, char* ld
   // FP32 spectrum plans: shift phases of the new slots for subtract_registry
   if (sizeof(T) == 4 && !rows) {
     cpx<float>* sE = reg_E(kp, slot, st.sb);
-    for (int q = threadIdx.x; q < nU * kp.S; q += kWG) {
-      const int sl = ns0 + q / kp.S, s = 1 + q % kp.S;
-      int n0;
-      int64_t K;
-      shift_of(kp, s, &n0, &K);
-      // exp(i pi q / NB), q = K y mod 2 NB exact; the FP32 phase is what is stored
-      const int64_t qq = pmod64(K * sy[(size_t)sl * d2 + n0], 2 * kp.NB);
-      float sn, cs;
-      sincospif((float)((double)qq / (double)kp.NB), &sn, &cs);
-      sE[(size_t)sl * kp.S + s - 1] = cmk<float>(cs, sn);
+    // U phases per thread at a time, their coordinate loads issued together
+    constexpr int U = 4;
+    const int nq = nU * kp.S;
+    for (int q0 = threadIdx.x; q0 < nq; q0 += U * kWG) {
+      int64_t yv[U], Kv[U];
+      int dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * kWG;
+        yv[u] = 0;
+        Kv[u] = 0;
+        dst[u] = -1;
+        if (q < nq) {
+          const int sl = ns0 + q / kp.S, s = 1 + q % kp.S;
+          int n0;
+          shift_of(kp, s, &n0, &Kv[u]);
+          yv[u] = sy[(size_t)sl * d2 + n0];
+          dst[u] = sl * kp.S + s - 1;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (dst[u] < 0) continue;
+        // exp(i pi q / NB), q = K y mod 2 NB exact; the FP32 phase is what is stored
+        const int64_t qq = pmod64(Kv[u] * yv[u], 2 * kp.NB);
+        float sn, cs;
+        sincospif((float)((double)qq / (double)kp.NB), &sn, &cs);
+        sE[dst[u]] = cmk<float>(cs, sn);
+      }
     }
     __syncthreads();
   }

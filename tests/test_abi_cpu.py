@@ -68,7 +68,8 @@ BAD = [
     (dict(max_rounds=0), -1), (dict(max_rounds=1000), -1), (dict(precision=5), -1),
     (dict(robust=2), -1), (dict(classifier=3), -1),
     (dict(sched_nt=(8, 0, 0, 0)), -1),               # 8 column tiles below p = 640
-    (dict(sched_nt=(0, 0, 3, 0)), -1), (dict(sched_fft=3), -1), (dict(sched_fft=-1), -1),
+    (dict(sched_nt=(5, 0, 0, 0)), -1), (dict(sched_nt=(0, 0, 9, 0)), -1),
+    (dict(sched_nt=(0, 1, 0, 0)), -1), (dict(sched_fft=3), -1), (dict(sched_fft=-1), -1),
     (dict(sched_dft_batch=65), -1), (dict(sched_dft_batch=-1), -1),
     (dict(d=300, d1=1, precision=0), -2),            # d2 beyond 256
     (dict(d=100, d1=1), -2),                         # FP32: 2 (S+1) = 202 real rows > 128

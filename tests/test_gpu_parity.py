@@ -263,6 +263,9 @@ RECOVER_CASES = [
      {"sched": dict(sched_fft=2, sched_dft_batch=2, sched_nt=(2, 2, 2, 2))}, 5, (20, 260), 1e-5),
     ("c3_fp32_sched_nt4_nt8_batch8", "c3b",
      {"sched": dict(sched_nt=(4, 4, 8, 8), sched_dft_batch=8)}, 3, 150, 1e-5),
+    ("c3_fp32_sched_nt3_nt5_nt7", "c3b", {"sched": dict(sched_nt=(3, 3, 5, 7))}, 3,
+     (100, 600), 1e-5),
+    ("c3_fp32_sched_nt6", "c3b", {"sched": dict(sched_nt=(2, 4, 6, 6))}, 3, (20, 260), 1e-5),
     # primes past the in-LDS DFT (Bluestein lengths 16384 FP64 / 32768 FP32: two halves
     # through the workspace) in every round
     ("c1_fp64_long_dft", "c1", {"p_min": 4200}, 4, 8, 1e-9),
