@@ -639,11 +639,24 @@ __device__ void subtract_registry_f32_staged(const KParams& kp, char* slot, WgSt
   for (int h = threadIdx.x; h <= p; h += kWG) c[h] = 0;
   __syncthreads();
   const double inv_pd = 1.0 / (double)p;
-  for (int e = threadIdx.x; e < nR; e += kWG) {
-    int h = pmod_small(sy[(size_t)ord[e] * d2 + m0], p, inv_pd);
-    h = min(max(h, 0), p - 1);
-    hb[e] = h;
-    atomicAdd(&c[h], 1);
+  // four entries per thread at a time: their slot and coordinate loads in flight together
+  for (int e0 = threadIdx.x; e0 < nR; e0 += 4 * kWG) {
+    int sl[4];
+    int64_t yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sl[u] = (e0 + u * kWG < nR) ? ord[e0 + u * kWG] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yv[u] = (e0 + u * kWG < nR) ? sy[(size_t)sl[u] * d2 + m0] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * kWG;
+      if (e < nR) {
+        int h = pmod_small(yv[u], p, inv_pd);
+        h = min(max(h, 0), p - 1);
+        hb[e] = h;
+        atomicAdd(&c[h], 1);
+      }
+    }
   }
   __syncthreads();
   block_exscan(c, p + 1, sh_part);
@@ -663,10 +676,22 @@ __device__ void subtract_registry_f32_staged(const KParams& kp, char* slot, WgSt
     }
   }
   __syncthreads();
-  for (int g = threadIdx.x; g < nR; g += kWG) {
-    const int sl = ord[list[g]];
-    list[g] = sl;
-    asort[g] = sa[sl];
+  for (int g0 = threadIdx.x; g0 < nR; g0 += 4 * kWG) {
+    int sl[4];
+    double2 av[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sl[u] = (g0 + u * kWG < nR) ? ord[list[g0 + u * kWG]] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      av[u] = (g0 + u * kWG < nR) ? sa[sl[u]] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int g = g0 + u * kWG;
+      if (g < nR) {
+        list[g] = sl[u];
+        asort[g] = av[u];
+      }
+    }
   }
   __syncthreads();
   const double pd = (double)p;
