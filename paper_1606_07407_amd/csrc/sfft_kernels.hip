@@ -280,15 +280,28 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     expipi(2.0 * (double)x / (double)p, &c, &s);  // omega_p^x = exp(2 pi i x / p)
     tw[x] = cmk<T>((T)c, (T)s);
   }
-  for (int j = threadIdx.x; j < 2 * npairs + 4; j += kWG) {
-    int r = 0;
-    if (j < st.M_pl) {
-      r = (int)pmod64(ypl[(size_t)j * d2 + m0], p);
-    } else if (j >= 2 * P0 && j - 2 * P0 < nreg) {
-      r = (int)pmod64(ry[(size_t)(j - 2 * P0) * d2 + m0], p);
+  // four residues per thread at a time: their coordinate loads in flight together
+  const int nrr = 2 * npairs + 4;
+  for (int j0 = threadIdx.x; j0 < nrr; j0 += 4 * kWG) {
+    int64_t yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u * kWG;
+      yv[u] = 0;
+      if (j < st.M_pl)
+        yv[u] = ypl[(size_t)j * d2 + m0];
+      else if (j < nrr && j >= 2 * P0 && j - 2 * P0 < nreg)
+        yv[u] = ry[(size_t)(j - 2 * P0) * d2 + m0];
     }
-    rr[j] = (uint16_t)r;
-    rs[j] = (uint16_t)((16 * r) % p);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u * kWG;
+      if (j < nrr) {
+        const int r = (int)pmod64(yv[u], p);
+        rr[j] = (uint16_t)r;
+        rs[j] = (uint16_t)((16 * r) % p);
+      }
+    }
   }
   __syncthreads();
   if constexpr (sizeof(T) == 4) {
@@ -380,17 +393,32 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   for (int j = threadIdx.x; j < M; j += kWG) {
     const int64_t* y = (j < st.M_pl) ? ypl + (size_t)j * d2 : ry + (size_t)(j - st.M_pl) * d2;
     int64_t r = 0, v = 1;
-    if constexpr (sizeof(T) == 4) {
-      int r32 = 0, v32 = 1;
-      for (int n = 0; n < d2; ++n) {
-        r32 = (r32 + v32 * pmod_small(y[n], p, inv_pd)) % p;
-        v32 = (v32 * (int)q) % p;
-      }
-      r = r32;
-    } else {
-      for (int n = 0; n < d2; ++n) {
-        r = (r + v * pmod64(y[n], p)) % p;
-        v = (v * q) % p;
+    // the coordinates are read 8 at a time (their loads in flight together), then
+    // folded in coordinate order
+    constexpr int NB8 = 8;
+    for (int n0 = 0; n0 < d2; n0 += NB8) {
+      int64_t yv[NB8];
+#pragma unroll
+      for (int u = 0; u < NB8; ++u) yv[u] = (n0 + u < d2) ? y[n0 + u] : 0;
+      if constexpr (sizeof(T) == 4) {
+        int r32 = (int)r, v32 = (int)v;
+#pragma unroll
+        for (int u = 0; u < NB8; ++u) {
+          if (n0 + u < d2) {
+            r32 = (r32 + v32 * pmod_small(yv[u], p, inv_pd)) % p;
+            v32 = (v32 * (int)q) % p;
+          }
+        }
+        r = r32;
+        v = v32;
+      } else {
+#pragma unroll
+        for (int u = 0; u < NB8; ++u) {
+          if (n0 + u < d2) {
+            r = (r + v * pmod64(yv[u], p)) % p;
+            v = (v * q) % p;
+          }
+        }
       }
     }
     rr[j] = (uint16_t)r;
