@@ -66,6 +66,8 @@ struct sfft_plan_s {
   char* d_ws = nullptr;
   int* d_queue = nullptr;
   char* d_split = nullptr;  // round states of the several-groups-per-signal launches
+  char* d_split_dft = nullptr;   // their DFT groups' Bluestein tables (grown on demand)
+  size_t split_dft_bytes = 0;
   int capacity = 0;         // work-groups of this plan the device holds at once
 };
 
@@ -550,6 +552,7 @@ sfft_status sfft_plan_destroy(sfft_plan plan) {
   if (plan->d_ws) (void)hipFree(plan->d_ws);
   if (plan->d_queue) (void)hipFree(plan->d_queue);
   if (plan->d_split) (void)hipFree(plan->d_split);
+  if (plan->d_split_dft) (void)hipFree(plan->d_split_dft);
   delete plan;
   return SFFT_OK;
 }
@@ -617,7 +620,21 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
     return fail(SFFT_ERANGE, "this plan's lines run as the several-groups recovery, one "
                 "workspace slot per signal: at most %d signals", plan->kp.n_slots);
   if (groups > 1 || plan->kp.tw_half) {
-    e = launch_recover_split(plan->kp, to_kbatch(batch), ko, plan->d_split, groups, stream);
+    // each DFT group's tables: grown on demand (hipFree waits for the launches that
+    // may still use the smaller buffer)
+    const size_t need = (size_t)batch->B * groups * split_dft_scratch(plan->kp).bytes;
+    if (need > plan->split_dft_bytes) {
+      if (plan->d_split_dft) (void)hipFree(plan->d_split_dft);
+      plan->d_split_dft = nullptr;
+      plan->split_dft_bytes = 0;
+      const hipError_t ea = hipMalloc((void**)&plan->d_split_dft, need);
+      if (ea != hipSuccess)
+        return fail(SFFT_ENOMEM, "device allocation of %zu bytes failed: %s", need,
+                    hipGetErrorString(ea));
+      plan->split_dft_bytes = need;
+    }
+    e = launch_recover_split(plan->kp, to_kbatch(batch), ko, plan->d_split, groups,
+                             plan->d_split_dft, stream);
     if (e) return hip_fail((hipError_t)e, "recover launch (several groups per signal)");
     return SFFT_OK;
   }

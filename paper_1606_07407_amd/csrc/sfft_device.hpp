@@ -995,15 +995,15 @@ __host__ __device__ inline int choose_nt(int p) {
   return best;
 }
 
-// Noise of the synthetic black box, added to every sample of the round (one
-// Philox block per pair of points).
+// Noise of the synthetic black box, added to every sample of sets s_begin ..
+// s_end - 1 of the round (one Philox block per pair of points).
 template <typename T>
-__device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int S1, uint64_t seed,
-                          uint64_t signal, int round, double sigma) {
+__device__ void add_noise(cpx<T>* __restrict__ V, int vstride, int p, int s_begin, int s_end,
+                          uint64_t seed, uint64_t signal, int round, double sigma) {
   if (!(sigma > 0.0)) return;
   const int np2 = (p + 1) / 2;
-  for (int q = threadIdx.x; q < S1 * np2; q += kWG) {
-    const int s = q / np2, hp = q - s * np2;
+  for (int q = threadIdx.x; q < (s_end - s_begin) * np2; q += kWG) {
+    const int s = s_begin + q / np2, hp = q - (s - s_begin) * np2;
     cpx<T>* v = V + (size_t)s * vstride + 2 * hp;
     if constexpr (sizeof(T) == 4) {
       cpx<float> n0, n1;

@@ -144,6 +144,23 @@ __host__ __device__ inline int sampler_m_max(const KParams& kp) {
   return kp.residual == 1 ? kp.m_max : 2 * ((kp.k_max + 1) / 2);
 }
 
+// Per-work-group Bluestein chirp, filter spectrum and parts buffer of the DFT launch
+// of the several-groups recovery (byte offsets, 256-aligned, and the total).
+struct SplitDftScratch {
+  size_t chirp, bhat, big, bytes;
+};
+__host__ __device__ inline SplitDftScratch split_dft_scratch(const KParams& kp) {
+  const size_t cs = kp.precision == 1 ? 8 : 16;
+  const int maxL = kp.precision == 1 ? kLdsFftMax32 : kLdsFftMax64;
+  auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  SplitDftScratch s;
+  s.chirp = 0;
+  s.bhat = a256(cs * (size_t)kp.p_max);
+  s.big = s.bhat + a256(cs * (size_t)kp.L_max);
+  s.bytes = s.big + a256(kp.L_max > maxL ? cs * (size_t)kp.L_max : 0);
+  return s;
+}
+
 struct KBatch {
   int B;
   const int64_t* mode_off;
@@ -199,10 +216,12 @@ int launch_mlp_accum(const float* src, float* dst, float scale, void* stream);
 int launch_fill(float* a, int n, float v, void* stream);
 int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream);
 // Several work-groups per signal (batches smaller than the chip): `state` holds
-// kb.B round states (split_state_bytes() each), ngrp groups sample each line.
+// kb.B round states (split_state_bytes() each), ngrp groups sample each line and
+// transform its sets, each group with split_dft_scratch(kp).bytes of `dft_scratch`
+// (kb.B * ngrp of them).
 size_t split_state_bytes();
 int launch_recover_split(const KParams& kp, const KBatch& kb, const KOut& ko, void* state,
-                         int ngrp, void* stream);
+                         int ngrp, void* dft_scratch, void* stream);
 // Fixed device scratch of sfft_recover_static (see the .hip file): its size,
 // the part the queue counter takes, the per-device address lookup (call once
 // per device with that device current), the slots of a given size it holds,

@@ -315,13 +315,14 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
 #define SFFT_EXPSUM(NTV)                                                                   \
   expsum_mfma<RT, (NTV <= NTMAX ? NTV : NTMAX), HALF>(af, rr, rs, twc, abuf, npairs, p, kp.S1, \
                                                       Vf, vstride, grp, ngrp)
+    // widths above NTMAX are never taken (nt <= NTMAX) and not instantiated
     switch (nt) {
-      case 8: SFFT_EXPSUM(8); break;
-      case 7: SFFT_EXPSUM(7); break;
-      case 6: SFFT_EXPSUM(6); break;
-      case 5: SFFT_EXPSUM(5); break;
-      case 4: SFFT_EXPSUM(4); break;
-      case 3: SFFT_EXPSUM(3); break;
+      case 8: if constexpr (NTMAX >= 8) SFFT_EXPSUM(8); break;
+      case 7: if constexpr (NTMAX >= 7) SFFT_EXPSUM(7); break;
+      case 6: if constexpr (NTMAX >= 6) SFFT_EXPSUM(6); break;
+      case 5: if constexpr (NTMAX >= 5) SFFT_EXPSUM(5); break;
+      case 4: if constexpr (NTMAX >= 4) SFFT_EXPSUM(4); break;
+      case 3: if constexpr (NTMAX >= 3) SFFT_EXPSUM(3); break;
       default: SFFT_EXPSUM(2); break;
     }
 #undef SFFT_EXPSUM
@@ -350,15 +351,25 @@ __device__ void sample_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   }
   __syncthreads();
   if (noise) {
-    add_noise<T>(V, vstride, p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
+    add_noise<T>(V, vstride, p, 0, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
     __syncthreads();
   }
 }
 
-// The S+1 (or `nsets`) prime-length DFTs of a round (defined with the DFT step below).
+// The prime-length DFTs of sets grp, grp + ngrp, ... of a round (defined with the DFT
+// step below).
 template <typename T>
-__device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds, cpx<T>* V,
-                          int vstride, int nsets);
+__device__ __noinline__ void dft_sets(const KParams& kp, const WgState& st, char* lds, cpx<T>* V,
+                                      int vstride, int nsets, cpx<T>* chirp, cpx<T>* bhat,
+                                      cpx<T>* G, int grp, int ngrp, bool noise, uint64_t seed);
+
+// The S+1 (or `nsets`) DFTs of a round with the slot's Bluestein tables and parts buffer.
+template <typename T>
+__device__ __forceinline__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
+                                          cpx<T>* V, int vstride, int nsets) {
+  dft_sets<T>(kp, st, lds, V, vstride, nsets, ws_cpx<T>(slot, kp.lay.chirp),
+              ws_cpx<T>(slot, kp.lay.bhat), ws_cpx<T>(slot, kp.lay.big), 0, 1, false, 0);
+}
 
 // Verification samples (the check at |R| = k): the residual, planted modes
 // minus registry, on the tilted line t_h = (h/p) U v, v_n = q^(n-1) mod p, so
@@ -490,7 +501,7 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     for (int h = threadIdx.x; h < p; h += kWG) V[h] = cadd(V[h], extra[h]);
     __syncthreads();
   }
-  add_noise<T>(V, kp.vstride, p, 1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
+  add_noise<T>(V, kp.vstride, p, 0, 1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
   __syncthreads();
   dft_round<T>(kp, slot, st, lds, V, kp.vstride, 1);
   const double thr = kp.verify_eta * (double)p;
@@ -503,12 +514,17 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
 }
 
 // --------------------------------------------------------------- DFTs ------
+// The DFTs of sets grp, grp + ngrp, ... (several at a time: batches grp, grp + ngrp,
+// ... of `cap` consecutive sets) with this work-group's Bluestein tables and parts
+// buffer; `noise`: the sets' noise is added first (several-groups launches, where the
+// sampling launch leaves it out).  Every set is transformed the same way whichever
+// group takes it.
 template <typename T>
-__device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds, cpx<T>* V,
-                          int vstride, int nsets) {
+__device__ __noinline__ void dft_sets(const KParams& kp, const WgState& st, char* lds, cpx<T>* V,
+                                      int vstride,
+                         int nsets, cpx<T>* chirp, cpx<T>* bhat, cpx<T>* G, int grp, int ngrp,
+                         bool noise, uint64_t seed) {
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(lds);
-  cpx<T>* chirp = ws_cpx<T>(slot, kp.lay.chirp);
-  cpx<T>* bhat = ws_cpx<T>(slot, kp.lay.bhat);
   constexpr int ML = MaxL<T>::value;
   const int R = st.L > ML ? st.L / ML : 1;  // parts through the slot beyond the LDS maximum
   const int M = st.L / R;
@@ -520,21 +536,30 @@ __device__ void dft_round(const KParams& kp, char* slot, WgState& st, char* lds,
   const bool batched = R == 1 && kp.sched_dft_batch != 1 && st.L <= MAXV * kWG &&
                        2 * st.L <= Lb;
   const BsTabs<T> tb = bs_tables<T>(st.L, M, buf + lds_padded(batched ? Lb : M));
-  cpx<T>* G = ws_cpx<T>(slot, kp.lay.big);
   // s = -1 computes chirp and filter; one call site for every FFT of the step
-  for (int s = -1; s < (batched ? 0 : nsets); ++s)
+  for (int s = -1; s < (batched ? 0 : nsets); s = (s < 0 ? grp : s + ngrp)) {
+    if (s >= 0 && noise) {
+      add_noise<T>(V, vstride, st.p, s, s + 1, seed, (uint64_t)st.sig, st.i, st.sigma);
+      __syncthreads();
+    }
     bluestein_run<T>(s < 0, s < 0 ? nullptr : V + (size_t)s * vstride, st.p, st.L, R,
                      st.log2L - (R >> 1), chirp, bhat, G, buf, tb, kp.sched_fft);
+  }
   if (batched) {
     int cap = min(Lb, MAXV * kWG) / st.L;
     if (kp.sched_dft_batch > 1) cap = min(cap, kp.sched_dft_batch);
-    for (int s0 = 0; s0 < nsets; s0 += cap) {
+    for (int s0 = grp * cap; s0 < nsets; s0 += ngrp * cap) {
       const int g = min(cap, nsets - s0);
+      if (noise) {
+        add_noise<T>(V, vstride, st.p, s0, s0 + g, seed, (uint64_t)st.sig, st.i, st.sigma);
+        __syncthreads();
+      }
       bluestein_dft_batch<T, MAXV>(V + (size_t)s0 * vstride, vstride, g, st.p, st.L, st.log2L,
                                    chirp, bhat, buf, tb.T1M, kp.sched_fft);
     }
   }
 }
+
 
 // ------------------------------------------- residual in the spectrum ------
 // Adaptive subtraction of the registry (Section 5.0) applied to the spectra:
@@ -1863,6 +1888,31 @@ split_sample_kernel(KParams kp, KBatch kb, const WgState* state, int ngrp) {
     sample_round<T, RT>(kp, kb, slot, st, (st.M_pl + 1) / 2, lds, V, kp.vstride, g, ngrp, false);
 }
 
+// Noise and DFTs of a round in the several-groups launches: group g of signal b adds
+// the noise of, and transforms, sets g, g + ngrp, ... (batches of sets when they are
+// transformed several at a time), with its own Bluestein tables and parts buffer
+// (`scr`: scr_bytes per work-group).
+template <typename T>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
+split_dft_kernel(KParams kp, KBatch kb, KOut ko, const WgState* state, int ngrp, char* scr,
+                 size_t scr_bytes) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ WgState st;
+  const int b = blockIdx.x / ngrp, g = blockIdx.x - b * ngrp;
+  if (threadIdx.x == 0) st = state[b];
+  __syncthreads();
+  if (st.split != 1) return;  // uniform over the work-group
+  char* slot = kp.ws + (size_t)b * kp.ws_slot;
+  cpx<T>* V = ws_cpx<T>(slot, kp.lay.V);
+  const SplitDftScratch sc = split_dft_scratch(kp);
+  char* mine = scr + (size_t)blockIdx.x * scr_bytes;
+  if (g == 0) phase_mark(kp, ko, st, 1);  // (the sampling launch)
+  dft_sets<T>(kp, st, lds, V, kp.vstride, kp.S1, reinterpret_cast<cpx<T>*>(mine + sc.chirp),
+              reinterpret_cast<cpx<T>*>(mine + sc.bhat), reinterpret_cast<cpx<T>*>(mine + sc.big),
+              g, ngrp, true, kb.seed);
+  if (g == 0) phase_mark(kp, ko, st, 2);
+}
+
 template <typename T, int RT>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
 split_post_kernel(KParams kp, KBatch kb, KOut ko, WgState* state) {
@@ -1876,11 +1926,7 @@ split_post_kernel(KParams kp, KBatch kb, KOut ko, WgState* state) {
   if (threadIdx.x == 0) st = state[b];
   __syncthreads();
   if (st.split != 1) return;
-  add_noise<T>(V, vstride, st.p, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
-  __syncthreads();
-  phase_mark(kp, ko, st, 1);  // (the sampling launch and the noise)
-  dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
-  phase_mark(kp, ko, st, 2);
+  // (noise and DFTs: split_dft_kernel)
   if (kp.residual == 0) subtract_registry<T>(kp, slot, st, lds, V, vstride, kp.S1, sh_part);
   phase_mark(kp, ko, st, 7);
   select_round<T>(kp, slot, st, lds, V, sh_part);
@@ -2335,7 +2381,7 @@ size_t split_state_bytes() { return sizeof(WgState); }
 // takes one round index, so no signal has more; launches past a signal's end
 // return at once.  No host synchronisation (the sequence can be captured).
 int launch_recover_split(const KParams& kp, const KBatch& kb, const KOut& ko, void* state,
-                         int ngrp, void* stream) {
+                         int ngrp, void* dft_scratch, void* stream) {
   hipStream_t hs = (hipStream_t)stream;
   WgState* stt = reinterpret_cast<WgState*>(state);
   SFFT_RT_DISPATCH(split_setup_kernel, dim3(kb.B), dim3(kWG), kp.lds_bytes, hs, kp, kb, ko, stt);
@@ -2343,6 +2389,14 @@ int launch_recover_split(const KParams& kp, const KBatch& kb, const KOut& ko, vo
   for (int r = 0; r < kp.max_rounds && e == hipSuccess; ++r) {
     SFFT_RT_DISPATCH(split_sample_kernel, dim3(kb.B * ngrp), dim3(kWG), kp.lds_bytes, hs, kp,
                      kb, (const WgState*)stt, ngrp);
+    if (kp.precision == 1)
+      hipLaunchKernelGGL(split_dft_kernel<float>, dim3(kb.B * ngrp), dim3(kWG), kp.lds_bytes, hs,
+                         kp, kb, ko, (const WgState*)stt, ngrp, (char*)dft_scratch,
+                         split_dft_scratch(kp).bytes);
+    else
+      hipLaunchKernelGGL(split_dft_kernel<double>, dim3(kb.B * ngrp), dim3(kWG), kp.lds_bytes,
+                         hs, kp, kb, ko, (const WgState*)stt, ngrp, (char*)dft_scratch,
+                         split_dft_scratch(kp).bytes);
     SFFT_RT_DISPATCH(split_post_kernel, dim3(kb.B), dim3(kWG), kp.lds_bytes, hs, kp, kb, ko, stt);
     e = hipGetLastError();
   }
@@ -2494,7 +2548,8 @@ int set_kernel_lds_limits(int lds_bytes) {
       (const void*)K<float, 4>, (const void*)K<float, 5>, (const void*)K<float, 6>,    \
       (const void*)K<float, 7>, (const void*)K<float, 8>, (const void*)K<double, 0>
       SFFT_SPLIT_FNS(split_setup_kernel), SFFT_SPLIT_FNS(split_sample_kernel),
-      SFFT_SPLIT_FNS(split_post_kernel)};
+      SFFT_SPLIT_FNS(split_post_kernel), (const void*)split_dft_kernel<float>,
+      (const void*)split_dft_kernel<double>};
 #undef SFFT_SPLIT_FNS
   for (const void* f : fns) {
     hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
