@@ -217,8 +217,9 @@ def plan_key(params) -> str:
 
 
 def profiled_traffic(workload: str, params):
-    """HBM bytes per recover_kernel launch from the committed counter summary, or None
-    when that summary was taken on other sources or another launch configuration."""
+    """HBM bytes per recover_kernel launch from the committed counter summary (one
+    traffic-record line per launch configuration profiled), or None when no record
+    there was taken on these sources with this launch configuration."""
     path = os.path.join(ROOT, "profiles", f"recover_kernel_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -226,9 +227,9 @@ def profiled_traffic(workload: str, params):
         if line.startswith("traffic-record:"):
             kv = dict(t.split("=", 1) for t in line.split()[1:])
             if kv.get("sources_sha256") != sources_sha256():
-                return None
+                continue
             if kv.get("plan", plan_key(params)) != plan_key(params):
-                return None
+                continue
             return float(kv["read_bytes"]) + float(kv["write_bytes"])
     return None
 

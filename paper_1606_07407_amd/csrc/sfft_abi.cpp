@@ -622,7 +622,9 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
   if (groups > 1 || plan->kp.tw_half) {
     // each DFT group's tables: grown on demand (hipFree waits for the launches that
     // may still use the smaller buffer)
-    const size_t need = (size_t)batch->B * groups * split_dft_scratch(plan->kp).bytes;
+    const size_t need = split_dft_launch(plan->kp)
+                            ? (size_t)batch->B * groups * split_dft_scratch(plan->kp).bytes
+                            : 0;
     if (need > plan->split_dft_bytes) {
       if (plan->d_split_dft) (void)hipFree(plan->d_split_dft);
       plan->d_split_dft = nullptr;

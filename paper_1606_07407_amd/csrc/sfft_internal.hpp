@@ -144,6 +144,15 @@ __host__ __device__ inline int sampler_m_max(const KParams& kp) {
   return kp.residual == 1 ? kp.m_max : 2 * ((kp.k_max + 1) / 2);
 }
 
+// Whether the several-groups recovery gives a round's noise and DFTs a launch of their
+// own, dealt out over the groups: when a round's DFT work is large (S1 L_max >= 2^18
+// points; measured: c5 45.2 -> 40.6 ms, the d = 1000 sweep 9-15% faster, while the d =
+// 100 sweep at k = 256 and 512, 21 sets of 4096 and 8192 points, was 19% and 4% slower
+// with the extra launch per round).  Otherwise the one-group launch transforms them.
+__host__ __device__ inline bool split_dft_launch(const KParams& kp) {
+  return (int64_t)kp.S1 * kp.L_max >= ((int64_t)1 << 18);
+}
+
 // Per-work-group Bluestein chirp, filter spectrum and parts buffer of the DFT launch
 // of the several-groups recovery (byte offsets, 256-aligned, and the total).
 struct SplitDftScratch {
@@ -216,9 +225,9 @@ int launch_mlp_accum(const float* src, float* dst, float scale, void* stream);
 int launch_fill(float* a, int n, float v, void* stream);
 int launch_recover(const KParams& kp, const KBatch& kb, const KOut& ko, int grid, void* stream);
 // Several work-groups per signal (batches smaller than the chip): `state` holds
-// kb.B round states (split_state_bytes() each), ngrp groups sample each line and
-// transform its sets, each group with split_dft_scratch(kp).bytes of `dft_scratch`
-// (kb.B * ngrp of them).
+// kb.B round states (split_state_bytes() each), ngrp groups sample each line and,
+// when split_dft_launch(kp), transform its sets, each group with
+// split_dft_scratch(kp).bytes of `dft_scratch` (kb.B * ngrp of them; else unused).
 size_t split_state_bytes();
 int launch_recover_split(const KParams& kp, const KBatch& kb, const KOut& ko, void* state,
                          int ngrp, void* dft_scratch, void* stream);

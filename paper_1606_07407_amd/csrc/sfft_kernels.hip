@@ -446,7 +446,36 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   // residue and coefficient read feeds 4 products.
   const float inv_p = 1.0f / (float)p;
   int G;
-  if constexpr (sizeof(T) == 4) {
+  constexpr int kNpMax = 16;  // points per thread of the long-line form below
+  if (sizeof(T) == 4 && p > 4 * kWG && p <= kNpMax * kWG) {
+    // lines longer than 4 points per thread: ceil(p / 256) consecutive points on every
+    // thread, in one pass (4 points per thread would leave a second pass to a few
+    // threads and double the time)
+    G = 1;
+    const int np = (p + kWG - 1) / kWG;
+    const int h0 = np * (int)threadIdx.x;
+    if (h0 < p) {
+      cpx<T> acc[kNpMax];
+#pragma unroll
+      for (int u = 0; u < kNpMax; ++u) acc[u] = cmk<T>(0, 0);
+      for (int j = 0; j < M; ++j) {
+        const uint32_t r = rr[j];
+        const cpx<T> c = coef[j];
+        uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
+#pragma unroll
+        for (int u = 0; u < kNpMax; ++u) {
+          if (u < np) {
+            acc[u] = cadd(acc[u], cmul(c, tw[idx]));
+            const uint32_t nx = idx + r;
+            idx = min(nx, nx - (uint32_t)p);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kNpMax; ++u)
+        if (u < np && h0 + u < p) V[h0 + u] = acc[u];
+    }
+  } else if constexpr (sizeof(T) == 4) {
     const int npg = (p + 3) / 4;
     G = max(1, kWG / npg);
     for (int t = threadIdx.x; t < G * npg; t += kWG) {
@@ -1915,7 +1944,7 @@ split_dft_kernel(KParams kp, KBatch kb, KOut ko, const WgState* state, int ngrp,
 
 template <typename T, int RT>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2)))
-split_post_kernel(KParams kp, KBatch kb, KOut ko, WgState* state) {
+split_post_kernel(KParams kp, KBatch kb, KOut ko, WgState* state, int dft_here) {
   extern __shared__ __align__(16) char lds[];
   __shared__ WgState st;
   __shared__ int sh_part[kWG];
@@ -1926,7 +1955,13 @@ split_post_kernel(KParams kp, KBatch kb, KOut ko, WgState* state) {
   if (threadIdx.x == 0) st = state[b];
   __syncthreads();
   if (st.split != 1) return;
-  // (noise and DFTs: split_dft_kernel)
+  if (dft_here) {
+    add_noise<T>(V, vstride, st.p, 0, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);
+    __syncthreads();
+    phase_mark(kp, ko, st, 1);  // (the sampling launch and the noise)
+    dft_round<T>(kp, slot, st, lds, V, vstride, kp.S1);
+    phase_mark(kp, ko, st, 2);
+  }  // (otherwise split_dft_kernel added the noise and transformed the sets)
   if (kp.residual == 0) subtract_registry<T>(kp, slot, st, lds, V, vstride, kp.S1, sh_part);
   phase_mark(kp, ko, st, 7);
   select_round<T>(kp, slot, st, lds, V, sh_part);
@@ -2384,20 +2419,22 @@ int launch_recover_split(const KParams& kp, const KBatch& kb, const KOut& ko, vo
                          int ngrp, void* dft_scratch, void* stream) {
   hipStream_t hs = (hipStream_t)stream;
   WgState* stt = reinterpret_cast<WgState*>(state);
+  const bool dft_launch = split_dft_launch(kp);
   SFFT_RT_DISPATCH(split_setup_kernel, dim3(kb.B), dim3(kWG), kp.lds_bytes, hs, kp, kb, ko, stt);
   hipError_t e = hipGetLastError();
   for (int r = 0; r < kp.max_rounds && e == hipSuccess; ++r) {
     SFFT_RT_DISPATCH(split_sample_kernel, dim3(kb.B * ngrp), dim3(kWG), kp.lds_bytes, hs, kp,
                      kb, (const WgState*)stt, ngrp);
-    if (kp.precision == 1)
+    if (dft_launch && kp.precision == 1)
       hipLaunchKernelGGL(split_dft_kernel<float>, dim3(kb.B * ngrp), dim3(kWG), kp.lds_bytes, hs,
                          kp, kb, ko, (const WgState*)stt, ngrp, (char*)dft_scratch,
                          split_dft_scratch(kp).bytes);
-    else
+    else if (dft_launch)
       hipLaunchKernelGGL(split_dft_kernel<double>, dim3(kb.B * ngrp), dim3(kWG), kp.lds_bytes,
                          hs, kp, kb, ko, (const WgState*)stt, ngrp, (char*)dft_scratch,
                          split_dft_scratch(kp).bytes);
-    SFFT_RT_DISPATCH(split_post_kernel, dim3(kb.B), dim3(kWG), kp.lds_bytes, hs, kp, kb, ko, stt);
+    SFFT_RT_DISPATCH(split_post_kernel, dim3(kb.B), dim3(kWG), kp.lds_bytes, hs, kp, kb, ko, stt,
+                     dft_launch ? 0 : 1);
     e = hipGetLastError();
   }
   return (int)e;

@@ -72,6 +72,8 @@ CASES = [
     ("c1_fp64_long_dft", "asan", "c1", {"p_min": 4200}, 1, 8, 1e-9, 0),
     ("c1_fp64_long_dft", "tsan", "c1", {"p_min": 4200}, 1, 8, 1e-9, 0),
     ("c3_fp32_long_dft", "asan", "c3b", {"p_min": 8300}, 1, 20, 1e-5, 0),
+    # verification lines of more than 1024 points: five consecutive points per thread
+    ("c3_fp32_long_verify", "asan", "c3b", {"p_min": 1100}, 1, 20, 1e-5, 0),
     # several work-groups per signal: three launches per round, the sampling of each
     # line dealt out over 3 (FP32) or 2 (FP64) work-groups
     # (max_rounds bounds the launches: one pair per possible round)
@@ -79,6 +81,10 @@ CASES = [
     ("c3_fp32_split", "tsan", "c3b", {"split": 3, "max_rounds": 12}, 2, 60, 1e-5, 0),
     ("c1_fp64_split", "asan", "c1", {"split": 2, "verify": True, "max_rounds": 8}, 2, 8,
      1e-9, 0),
+    # FP64 rounds whose DFTs (21 sets of 16384 points, in four parts) get a launch of
+    # their own, dealt out over the groups
+    ("e1_fp64_split_dft", "asan", "e1", {"p_min": 4200, "split": 2, "verify": False,
+                                         "max_rounds": 2}, 1, 8, 1e-9, 0),
     # lines too long for the whole twiddle table next to six row tiles of staged A
     # fragments: the sampler keeps p/2 + 1 twiddles (and the recovery runs split)
     ("c5_fp32_half_table", "asan", "c5", {"p_min": 14500, "verify": False, "max_rounds": 2},

@@ -512,6 +512,7 @@ def test_recover_deterministic_and_reusable():
     ("c5", {"c": 2.5}, 2, 4096, 3),              # and the DFT in four parts
     ("c5", {"c": 3.0}, 2, 4096, 4),              # and half the sampler's twiddle table
     ("e1", {}, 4, 512, 5),                       # FP64, d = 100
+    ("e1", {}, 2, 1024, 2),                      # and the round's DFTs in a grouped launch
     ("c3b", {"residual": 1}, 4, 200, 2),         # registry rows in the sampler
 ])
 def test_split_groups_equal_one_kernel(cname, over, B, k, groups):
