@@ -152,11 +152,16 @@ typedef struct {
    * are sampled at points h/p that split into independent column blocks (the
    * loop over the sets in Algorithm MultiPhaseshift needs no order), so a batch
    * smaller than the device runs each ordinary round's sampling on several
-   * work-groups and the rest of the round on one (three launches per round, no
-   * host synchronisation; results identical bit for bit).  0: automatic (as
-   * many as fill the device, at most 8, when the batch takes at most half of
-   * it and k_max >= 256); 1: one work-group per signal (one launch); 2..16.  Split, the phase timestamps' sampling interval (marks 0 to 1) also
-   * holds the gap between the launches and the noise. */
+   * work-groups, and, when a round's DFTs are large ((S+1) L_max >= 2^18 points,
+   * L_max the longest Bluestein length), its noise and DFTs too (each group some
+   * of the sets), and the rest of the round on one (two or three launches per
+   * round, no host synchronisation; results identical bit for bit).  Such plans
+   * reserve one set of Bluestein tables per work-group the device holds at
+   * sfft_plan_create (split_groups sets per workspace slot when it is given).
+   * 0: automatic (as many as fill the device, at most 8, when the batch takes at
+   * most half of it and k_max >= 256); 1: one work-group per signal (one
+   * launch); 2..16.  Split, the phase timestamps' sampling interval (marks 0 to
+   * 1) also holds the gap between the launches and the noise. */
   int32_t split_groups;
 } sfft_params;
 
@@ -231,8 +236,8 @@ sfft_status sfft_plan_destroy(sfft_plan plan);
  * one persistent launch in which each work-group takes signals from a queue
  * and runs all rounds of one signal (sample, DFT, select, test, decode,
  * registry update) before taking the next; or, for batches smaller than the
- * device (see split_groups), several work-groups per signal over three
- * launches per round.  Allocates nothing. */
+ * device (see split_groups), several work-groups per signal over two or
+ * three launches per round.  Allocates nothing. */
 sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch,
                          const sfft_outputs* out, void* stream);
 

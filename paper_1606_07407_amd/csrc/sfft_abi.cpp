@@ -66,7 +66,7 @@ struct sfft_plan_s {
   char* d_ws = nullptr;
   int* d_queue = nullptr;
   char* d_split = nullptr;  // round states of the several-groups-per-signal launches
-  char* d_split_dft = nullptr;   // their DFT groups' Bluestein tables (grown on demand)
+  char* d_split_dft = nullptr;   // their DFT groups' Bluestein tables
   size_t split_dft_bytes = 0;
   int capacity = 0;         // work-groups of this plan the device holds at once
 };
@@ -508,6 +508,21 @@ sfft_status sfft_plan_create(const sfft_params* params, int32_t max_batch, sfft_
     return fail(SFFT_ENOMEM, "device allocation of %zu bytes failed: %s", ws_bytes,
                 hipGetErrorString(e));
   }
+  // Bluestein tables of the grouped DFT launch of the several-groups recovery: one set
+  // per work-group, as many work-groups as sfft_recover can run (signals x groups: at
+  // most the device's capacity automatically, n_slots x split_groups when given)
+  if (split_dft_launch(kp)) {
+    const size_t nwg = P.split_groups >= 1 ? (size_t)kp.n_slots * P.split_groups
+                                           : (size_t)capacity;
+    plan->split_dft_bytes = nwg * split_dft_scratch(kp).bytes;
+    if ((e = hipMalloc((void**)&plan->d_split_dft, plan->split_dft_bytes)) != hipSuccess) {
+      const size_t want_bytes = plan->split_dft_bytes;
+      plan->d_split_dft = nullptr;
+      sfft_plan_destroy(plan);
+      return fail(SFFT_ENOMEM, "device allocation of %zu bytes failed: %s", want_bytes,
+                  hipGetErrorString(e));
+    }
+  }
   if ((e = hipMemcpy(plan->d_primes, primes.data(), primes.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(plan->d_part + part_blk, blk.data(), blk.size() * sizeof(int32_t),
@@ -620,21 +635,13 @@ sfft_status sfft_recover(sfft_plan plan, const sfft_signal_batch* batch, const s
     return fail(SFFT_ERANGE, "this plan's lines run as the several-groups recovery, one "
                 "workspace slot per signal: at most %d signals", plan->kp.n_slots);
   if (groups > 1 || plan->kp.tw_half) {
-    // each DFT group's tables: grown on demand (hipFree waits for the launches that
-    // may still use the smaller buffer)
+    // each DFT group's tables (reserved at plan creation for every batch this path takes)
     const size_t need = split_dft_launch(plan->kp)
                             ? (size_t)batch->B * groups * split_dft_scratch(plan->kp).bytes
                             : 0;
-    if (need > plan->split_dft_bytes) {
-      if (plan->d_split_dft) (void)hipFree(plan->d_split_dft);
-      plan->d_split_dft = nullptr;
-      plan->split_dft_bytes = 0;
-      const hipError_t ea = hipMalloc((void**)&plan->d_split_dft, need);
-      if (ea != hipSuccess)
-        return fail(SFFT_ENOMEM, "device allocation of %zu bytes failed: %s", need,
-                    hipGetErrorString(ea));
-      plan->split_dft_bytes = need;
-    }
+    if (need > plan->split_dft_bytes)
+      return fail(SFFT_ERANGE, "%d signals x %d groups need %zu bytes of DFT tables, the plan "
+                  "holds %zu", batch->B, groups, need, plan->split_dft_bytes);
     e = launch_recover_split(plan->kp, to_kbatch(batch), ko, plan->d_split, groups,
                              plan->d_split_dft, stream);
     if (e) return hip_fail((hipError_t)e, "recover launch (several groups per signal)");
