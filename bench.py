@@ -195,8 +195,35 @@ def cpu_baseline(cfg, pb, n_sig: int, workers: int, budget_s: float = 120.0,
     return out
 
 
+def code_of(text: str) -> str:
+    """C/C++ source without its comments, trailing blanks and empty lines (string and
+    character literals kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == "/" and i + 1 < n and text[i + 1] == "/":
+            while i < n and text[i] != "\n":
+                i += 1
+        elif c == "/" and i + 1 < n and text[i + 1] == "*":
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    lines = (l.rstrip() for l in "".join(out).split("\n"))
+    return "\n".join(l for l in lines if l)
+
+
 def sources_sha256() -> str:
-    """Hash of the device sources and the ABI header (identifies the profiled build)."""
+    """Hash of the code of the device sources and the ABI header, comments and blank
+    lines removed (identifies the profiled build; edits of comments keep it)."""
     import hashlib
     h = hashlib.sha256()
     files = [os.path.join(ROOT, "include", "sfft.h")]
@@ -205,7 +232,7 @@ def sources_sha256() -> str:
                     if f.endswith((".hip", ".hpp", ".cpp")))
     for f in files:
         h.update(os.path.basename(f).encode())
-        h.update(open(f, "rb").read())
+        h.update(code_of(open(f, encoding="utf-8").read()).encode())
     return h.hexdigest()
 
 

@@ -1765,14 +1765,16 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
 
 // ------------------------------------------ several work-groups per signal --
 // Batches smaller than the chip (fewer signals than the device holds work-groups)
-// run with ngrp work-groups per signal, three kinds of launch: split_setup_kernel
-// (one work-group per signal: the per-signal set-up and the rounds up to the first
-// ordinary one), then per ordinary round split_sample_kernel (ngrp work-groups per
-// signal, group g sampling every ngrp-th block of column tiles, each point's sum
-// formed as in the one-group sampler) and split_post_kernel (one per signal: the
-// noise, the DFTs, subtraction, selection, decode and merge, then the rounds up to
-// the next ordinary one).  Verification rounds sample a single line and run whole
-// in the one-group kernels.  Signal b uses workspace slot b; its round state stays
+// run with ngrp work-groups per signal: split_setup_kernel (one work-group per
+// signal: the per-signal set-up and the rounds up to the first ordinary one), then
+// per ordinary round split_sample_kernel (ngrp work-groups per signal, group g
+// sampling every ngrp-th block of column tiles, each point's sum formed as in the
+// one-group sampler), for plans with much DFT work per round (split_dft_launch)
+// split_dft_kernel (ngrp per signal: the noise and DFTs of every ngrp-th set or
+// batch of sets), and split_post_kernel (one per signal: the noise and DFTs when
+// they have no launch of their own, subtraction, selection, decode and merge, then
+// the rounds up to the next ordinary one).  Verification rounds sample a single
+// line and run whole in the one-group kernels.  Signal b uses workspace slot b; its round state stays
 // in global memory between launches.  The outputs equal the one-kernel recovery's
 // bit for bit.
 
