@@ -127,7 +127,8 @@ struct WgState {
   uint64_t prefix;
   int need;
   int split;         // several groups per signal: 1 while an ordinary round awaits its
-                     // samples, 2 once the signal is finished
+                     // samples, 3 while a verification line awaits its sums, 2 once the
+                     // signal is finished
 };
 
 // --------------------------------------------------- per-signal set-up -----
@@ -381,7 +382,8 @@ __device__ __forceinline__ void dft_round(const KParams& kp, char* slot, WgState
 // f(t_h) in a session, where there are no planted modes.
 template <typename T>
 __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, WgState& st,
-                            char* lds, cpx<T>* V, int* sh_part, const cpx<T>* extra) {
+                            char* lds, cpx<T>* V, int* sh_part, const cpx<T>* extra,
+                            int part_mode = 0, int h_lo = 0, int h_hi = 0) {
   const int p = st.p, d2 = kp.d2;
   const int M = st.M_pl + st.nslots;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds);
@@ -395,6 +397,9 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   const double2* ra = reg_a(kp, slot, st.sb);
   const cpx<T>* cc = ws_cpx<T>(slot, kp.lay.ccomp);
   const int64_t q = 1 + (st.i % (p - 1));
+  // part_mode 1: only the sums of points h_lo .. h_hi - 1 (one group of the
+  // several-groups sampling launch); 2: only what follows the sums (noise, DFT, count)
+  if (part_mode != 2) {
   for (int x = threadIdx.x; x < p; x += kWG) {
     double c, sn;
     expipi(2.0 * (double)x / (double)p, &c, &sn);
@@ -447,6 +452,36 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   const float inv_p = 1.0f / (float)p;
   int G;
   constexpr int kNpMax = 16;  // points per thread of the long-line form below
+  if (part_mode == 1) {
+    // this group's points: ceil(n / 256) consecutive points per thread, each point's
+    // sum over the modes in order, as in every form below with one thread per point
+    // (G = 1, which is what p > 2 * 256 gives)
+    const int np = (h_hi - h_lo + kWG - 1) / kWG;
+    const int h0 = h_lo + np * (int)threadIdx.x;
+    if (h0 < h_hi) {
+      cpx<T> acc[kNpMax];
+#pragma unroll
+      for (int u = 0; u < kNpMax; ++u) acc[u] = cmk<T>(0, 0);
+      for (int j = 0; j < M; ++j) {
+        const uint32_t r = rr[j];
+        const cpx<T> c = coef[j];
+        uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
+#pragma unroll
+        for (int u = 0; u < kNpMax; ++u) {
+          if (u < np) {
+            acc[u] = cadd(acc[u], cmul(c, tw[idx]));
+            const uint32_t nx = idx + r;
+            idx = min(nx, nx - (uint32_t)p);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kNpMax; ++u)
+        if (u < np && h0 + u < h_hi) V[h0 + u] = acc[u];
+    }
+    __syncthreads();
+    return;
+  }
   if (sizeof(T) == 4 && p > 4 * kWG && p <= kNpMax * kWG) {
     // lines longer than 4 points per thread: ceil(p / 256) consecutive points on every
     // thread, in one pass (4 points per thread would leave a second pass to a few
@@ -526,6 +561,7 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     }
     __syncthreads();
   }
+  }  // part_mode != 2
   if (extra) {
     for (int h = threadIdx.x; h < p; h += kWG) V[h] = cadd(V[h], extra[h]);
     __syncthreads();
@@ -1782,10 +1818,55 @@ recover_kernel(KParams kp, KBatch kb, KOut ko) {
 // round, which is left pending (st.split = 1, prime, axis and length set);
 // verification rounds run here whole; a finished signal writes its outputs
 // (st.split = 2).
+// What a finished verification round leaves in the state: its trace row, the sample
+// count, and either the verified flag or the number of buckets to repair (thread 0
+// writes; a barrier follows).
+__device__ inline void verify_account(const KParams& kp, const KOut& ko, WgState& st) {
+  if (threadIdx.x == 0) {
+    st.samples += st.p;
+    if (ko.trace) {
+      int32_t* tr = ko.trace + ((size_t)st.sig * kp.max_rounds + (st.i - 1)) * 8;
+      tr[0] = st.i;
+      tr[1] = 0;
+      tr[2] = st.p;
+      tr[3] = 0;
+      tr[4] = st.ncand;
+      tr[5] = 0;
+      tr[6] = st.nR;
+      tr[7] = 1;
+    }
+    st.i += 1;
+    if (st.ncand == 0) {
+      st.verified = 1;
+    } else {
+      const int room = st.k + max(16, (st.k + 7) / 8) - st.nR;
+      st.kv = min(min(st.ncand, st.k), room);
+      if (st.kv <= 0) {
+        st.kv = 0;
+        st.flag = 2;  // no room: stop with RESIDUAL_NONZERO
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// A verification line the sampling launch's groups sum (split = 3): FP32 lines of
+// 512 to 4096 points, where every one-group form sums each point in one thread.
+__host__ __device__ inline bool split_verify_line(const KParams& kp, int p) {
+  return kp.precision == 1 && p > 2 * kWG && p <= 16 * kWG;
+}
+
 template <typename T>
 __device__ void split_advance(const KParams& kp, const KBatch& kb, const KOut& ko, char* slot,
-                              WgState& st, char* lds, cpx<T>* V, int* sh_part) {
-  while (st.i <= kp.max_rounds) {
+                              WgState& st, char* lds, cpx<T>* V, int* sh_part,
+                              bool verify_summed = false) {
+  if (verify_summed) {
+    // the groups summed this verification line: the rest of the round, then on
+    verify_round<T>(kp, kb, slot, st, lds, V, sh_part, nullptr, 2);
+    phase_mark(kp, ko, st, 6);
+    verify_account(kp, ko, st);
+  }
+  while (st.flag == 0 && st.i <= kp.max_rounds) {
     const bool at_k = st.nR >= st.k && st.kv == 0;
     if (at_k && (!kp.verify || st.verified)) break;
     if (threadIdx.x == 0) {
@@ -1811,40 +1892,14 @@ __device__ void split_advance(const KParams& kp, const KBatch& kb, const KOut& k
       break;
     }
     phase_mark(kp, ko, st, 0);
-    if (!at_k) {
-      if (threadIdx.x == 0) st.split = 1;
+    if (!at_k || split_verify_line(kp, st.p)) {
+      if (threadIdx.x == 0) st.split = at_k ? 3 : 1;
       __syncthreads();
       return;
     }
     verify_round<T>(kp, kb, slot, st, lds, V, sh_part, nullptr);
     phase_mark(kp, ko, st, 6);
-    if (threadIdx.x == 0) {
-      st.samples += st.p;
-      if (ko.trace) {
-        int32_t* tr = ko.trace + ((size_t)st.sig * kp.max_rounds + (st.i - 1)) * 8;
-        tr[0] = st.i;
-        tr[1] = 0;
-        tr[2] = st.p;
-        tr[3] = 0;
-        tr[4] = st.ncand;
-        tr[5] = 0;
-        tr[6] = st.nR;
-        tr[7] = 1;
-      }
-      st.i += 1;
-      if (st.ncand == 0) {
-        st.verified = 1;
-      } else {
-        const int room = st.k + max(16, (st.k + 7) / 8) - st.nR;
-        st.kv = min(min(st.ncand, st.k), room);
-        if (st.kv <= 0) {
-          st.kv = 0;
-          st.flag = 2;  // no room: stop with RESIDUAL_NONZERO
-        }
-      }
-    }
-    __syncthreads();
-    if (st.flag) break;
+    verify_account(kp, ko, st);
   }
   if (threadIdx.x == 0 && st.status == 0)
     st.status = (st.nR < st.k) ? 1 : (st.nR > st.k || (kp.verify && !st.verified)) ? 2 : 0;
@@ -1909,9 +1964,16 @@ split_sample_kernel(KParams kp, KBatch kb, const WgState* state, int ngrp) {
   const int b = blockIdx.x / ngrp, g = blockIdx.x - b * ngrp;
   if (threadIdx.x == 0) st = state[b];
   __syncthreads();
-  if (st.split != 1) return;  // uniform over the work-group
+  if (st.split != 1 && st.split != 3) return;  // uniform over the work-group
   char* slot = kp.ws + (size_t)b * kp.ws_slot;
   cpx<T>* V = ws_cpx<T>(slot, kp.lay.V);
+  if (st.split == 3) {
+    // a verification line: this group sums its share of the points
+    const int chunk = (st.p + ngrp - 1) / ngrp;
+    const int lo = min(st.p, g * chunk), hi = min(st.p, lo + chunk);
+    verify_round<T>(kp, kb, slot, st, lds, V, nullptr, nullptr, 1, lo, hi);
+    return;
+  }
   if (sizeof(T) == 4 && kp.tw_half)
     sample_round<T, RT, true>(kp, kb, slot, st, (st.M_pl + 1) / 2, lds, V, kp.vstride, g, ngrp,
                               false);
@@ -1956,6 +2018,13 @@ split_post_kernel(KParams kp, KBatch kb, KOut ko, WgState* state, int dft_here) 
   const int vstride = kp.vstride;
   if (threadIdx.x == 0) st = state[b];
   __syncthreads();
+  if (st.split == 3) {
+    // the sampling launch summed a verification line: its noise, DFT and count, then on
+    // (split_advance sets st.split again before it returns)
+    split_advance<T>(kp, kb, ko, slot, st, lds, V, sh_part, true);
+    if (threadIdx.x == 0) state[b] = st;
+    return;
+  }
   if (st.split != 1) return;
   if (dft_here) {
     add_noise<T>(V, vstride, st.p, 0, kp.S1, kb.seed, (uint64_t)st.sig, st.i, st.sigma);

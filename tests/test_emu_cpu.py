@@ -81,6 +81,11 @@ CASES = [
     ("c3_fp32_split", "tsan", "c3b", {"split": 3, "max_rounds": 12}, 2, 60, 1e-5, 0),
     ("c1_fp64_split", "asan", "c1", {"split": 2, "verify": True, "max_rounds": 8}, 2, 8,
      1e-9, 0),
+    # verification lines of 1100+ points summed by the sampling launch's groups
+    ("c3_fp32_split_long_verify", "asan", "c3b", {"p_min": 1100, "split": 3, "max_rounds": 12},
+     1, 20, 1e-5, 0),
+    ("c3_fp32_split_long_verify", "tsan", "c3b", {"p_min": 1100, "split": 3, "max_rounds": 12},
+     1, 20, 1e-5, 0),
     # FP64 rounds whose DFTs (21 sets of 16384 points, in four parts) get a launch of
     # their own, dealt out over the groups
     ("e1_fp64_split_dft", "asan", "e1", {"p_min": 4200, "split": 2, "verify": False,
