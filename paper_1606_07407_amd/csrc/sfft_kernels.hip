@@ -372,6 +372,22 @@ __device__ __forceinline__ void dft_round(const KParams& kp, char* slot, WgState
               ws_cpx<T>(slot, kp.lay.bhat), ws_cpx<T>(slot, kp.lay.big), 0, 1, false, 0);
 }
 
+// The n (<= NMAX) twiddles omega_p^{((h0 + u) r) mod p}, u < n, of one mode of the
+// verification sums (table `tw` of p points in LDS).
+template <typename T, int NMAX>
+__device__ __forceinline__ void verify_twiddles(const cpx<T>* tw, uint32_t h0, uint32_t r, int p,
+                                                float inv_p, int n, cpx<T>* t) {
+  uint32_t idx = mulmod24(h0, r, (uint32_t)p, inv_p);
+#pragma unroll
+  for (int u = 0; u < NMAX; ++u) {
+    if (u < n) {
+      t[u] = tw[idx];
+      const uint32_t nx = idx + r;
+      idx = min(nx, nx - (uint32_t)p);
+    }
+  }
+}
+
 // Verification samples (the check at |R| = k): the residual, planted modes
 // minus registry, on the tilted line t_h = (h/p) U v, v_n = q^(n-1) mod p, so
 // the bucket of a mode is (y . v) mod p, exact in integers:
@@ -458,7 +474,33 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
     // (G = 1, which is what p > 2 * 256 gives)
     const int np = (h_hi - h_lo + kWG - 1) / kWG;
     const int h0 = h_lo + np * (int)threadIdx.x;
-    if (h0 < h_hi) {
+    if (h0 < h_hi && np <= 4) {
+      // up to 4 points per thread: the coefficient and twiddles of mode j + 1 are read
+      // while mode j's products are formed (the sums stay in mode order)
+      cpx<T> acc[4], tv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = cmk<T>(0, 0);
+      cpx<T> c = cmk<T>(0, 0);
+      if (M > 0) {
+        c = coef[0];
+        verify_twiddles<T, 4>(tw, (uint32_t)h0, rr[0], p, inv_p, np, tv);
+      }
+      for (int j = 0; j < M; ++j) {
+        const int jn = min(j + 1, M - 1);
+        const cpx<T> cn = coef[jn];
+        cpx<T> tn[4];
+        verify_twiddles<T, 4>(tw, (uint32_t)h0, rr[jn], p, inv_p, np, tn);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (u < np) acc[u] = cadd(acc[u], cmul(c, tv[u]));
+        c = cn;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tv[u] = tn[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (u < np && h0 + u < h_hi) V[h0 + u] = acc[u];
+    } else if (h0 < h_hi) {
       cpx<T> acc[kNpMax];
 #pragma unroll
       for (int u = 0; u < kNpMax; ++u) acc[u] = cmk<T>(0, 0);
