@@ -196,8 +196,8 @@ def cpu_baseline(cfg, pb, n_sig: int, workers: int, budget_s: float = 120.0,
 
 
 def code_of(text: str) -> str:
-    """C/C++ source without its comments, trailing blanks and empty lines (string and
-    character literals kept as written)."""
+    """C/C++ source without its comments, indentation, trailing blanks and empty lines
+    (string and character literals kept as written)."""
     out, i, n = [], 0, len(text)
     while i < n:
         c = text[i]
@@ -217,13 +217,14 @@ def code_of(text: str) -> str:
         else:
             out.append(c)
             i += 1
-    lines = (l.rstrip() for l in "".join(out).split("\n"))
+    lines = (l.strip() for l in "".join(out).split("\n"))
     return "\n".join(l for l in lines if l)
 
 
 def sources_sha256() -> str:
-    """Hash of the code of the device sources and the ABI header, comments and blank
-    lines removed (identifies the profiled build; edits of comments keep it)."""
+    """Hash of the code of the device sources and the ABI header, comments, indentation
+    and blank lines removed (identifies the profiled build; edits of comments or layout
+    keep it)."""
     import hashlib
     h = hashlib.sha256()
     files = [os.path.join(ROOT, "include", "sfft.h")]

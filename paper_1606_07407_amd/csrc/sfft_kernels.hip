@@ -416,193 +416,193 @@ __device__ void verify_round(const KParams& kp, const KBatch& kb, char* slot, Wg
   // part_mode 1: only the sums of points h_lo .. h_hi - 1 (one group of the
   // several-groups sampling launch); 2: only what follows the sums (noise, DFT, count)
   if (part_mode != 2) {
-  for (int x = threadIdx.x; x < p; x += kWG) {
-    double c, sn;
-    expipi(2.0 * (double)x / (double)p, &c, &sn);
-    tw[x] = cmk<T>((T)c, (T)sn);
-  }
-  const double inv_pd = 1.0 / (double)p;
-  for (int j = threadIdx.x; j < M; j += kWG) {
-    const int64_t* y = (j < st.M_pl) ? ypl + (size_t)j * d2 : ry + (size_t)(j - st.M_pl) * d2;
-    int64_t r = 0, v = 1;
-    // the coordinates are read 8 at a time (their loads in flight together), then
-    // folded in coordinate order
-    constexpr int NB8 = 8;
-    for (int n0 = 0; n0 < d2; n0 += NB8) {
-      int64_t yv[NB8];
+    for (int x = threadIdx.x; x < p; x += kWG) {
+      double c, sn;
+      expipi(2.0 * (double)x / (double)p, &c, &sn);
+      tw[x] = cmk<T>((T)c, (T)sn);
+    }
+    const double inv_pd = 1.0 / (double)p;
+    for (int j = threadIdx.x; j < M; j += kWG) {
+      const int64_t* y = (j < st.M_pl) ? ypl + (size_t)j * d2 : ry + (size_t)(j - st.M_pl) * d2;
+      int64_t r = 0, v = 1;
+      // the coordinates are read 8 at a time (their loads in flight together), then
+      // folded in coordinate order
+      constexpr int NB8 = 8;
+      for (int n0 = 0; n0 < d2; n0 += NB8) {
+        int64_t yv[NB8];
 #pragma unroll
-      for (int u = 0; u < NB8; ++u) yv[u] = (n0 + u < d2) ? y[n0 + u] : 0;
-      if constexpr (sizeof(T) == 4) {
-        int r32 = (int)r, v32 = (int)v;
+        for (int u = 0; u < NB8; ++u) yv[u] = (n0 + u < d2) ? y[n0 + u] : 0;
+        if constexpr (sizeof(T) == 4) {
+          int r32 = (int)r, v32 = (int)v;
 #pragma unroll
-        for (int u = 0; u < NB8; ++u) {
-          if (n0 + u < d2) {
-            r32 = (r32 + v32 * pmod_small(yv[u], p, inv_pd)) % p;
-            v32 = (v32 * (int)q) % p;
+          for (int u = 0; u < NB8; ++u) {
+            if (n0 + u < d2) {
+              r32 = (r32 + v32 * pmod_small(yv[u], p, inv_pd)) % p;
+              v32 = (v32 * (int)q) % p;
+            }
+          }
+          r = r32;
+          v = v32;
+        } else {
+#pragma unroll
+          for (int u = 0; u < NB8; ++u) {
+            if (n0 + u < d2) {
+              r = (r + v * pmod64(yv[u], p)) % p;
+              v = (v * q) % p;
+            }
           }
         }
-        r = r32;
-        v = v32;
+      }
+      rr[j] = (uint16_t)r;
+      if (j < st.M_pl) {
+        coef[j] = cc[(size_t)j * kp.S1];
       } else {
+        const double2 a = ra[j - st.M_pl];
+        coef[j] = cmk<T>((T)-a.x, (T)-a.y);
+      }
+    }
+    __syncthreads();
+    // G threads per point when p is small; partial sums reduced through LDS.
+    // FP32: each thread takes 4 consecutive points (index stepped by r) so one
+    // residue and coefficient read feeds 4 products.
+    const float inv_p = 1.0f / (float)p;
+    int G;
+    constexpr int kNpMax = 16;  // points per thread of the long-line form below
+    if (part_mode == 1) {
+      // this group's points: ceil(n / 256) consecutive points per thread, each point's
+      // sum over the modes in order, as in every form below with one thread per point
+      // (G = 1, which is what p > 2 * 256 gives)
+      const int np = (h_hi - h_lo + kWG - 1) / kWG;
+      const int h0 = h_lo + np * (int)threadIdx.x;
+      if (h0 < h_hi && np <= 4) {
+        // up to 4 points per thread: the coefficient and twiddles of mode j + 1 are read
+        // while mode j's products are formed (the sums stay in mode order)
+        cpx<T> acc[4], tv[4];
 #pragma unroll
-        for (int u = 0; u < NB8; ++u) {
-          if (n0 + u < d2) {
-            r = (r + v * pmod64(yv[u], p)) % p;
-            v = (v * q) % p;
-          }
+        for (int u = 0; u < 4; ++u) acc[u] = cmk<T>(0, 0);
+        cpx<T> c = cmk<T>(0, 0);
+        if (M > 0) {
+          c = coef[0];
+          verify_twiddles<T, 4>(tw, (uint32_t)h0, rr[0], p, inv_p, np, tv);
         }
-      }
-    }
-    rr[j] = (uint16_t)r;
-    if (j < st.M_pl) {
-      coef[j] = cc[(size_t)j * kp.S1];
-    } else {
-      const double2 a = ra[j - st.M_pl];
-      coef[j] = cmk<T>((T)-a.x, (T)-a.y);
-    }
-  }
-  __syncthreads();
-  // G threads per point when p is small; partial sums reduced through LDS.
-  // FP32: each thread takes 4 consecutive points (index stepped by r) so one
-  // residue and coefficient read feeds 4 products.
-  const float inv_p = 1.0f / (float)p;
-  int G;
-  constexpr int kNpMax = 16;  // points per thread of the long-line form below
-  if (part_mode == 1) {
-    // this group's points: ceil(n / 256) consecutive points per thread, each point's
-    // sum over the modes in order, as in every form below with one thread per point
-    // (G = 1, which is what p > 2 * 256 gives)
-    const int np = (h_hi - h_lo + kWG - 1) / kWG;
-    const int h0 = h_lo + np * (int)threadIdx.x;
-    if (h0 < h_hi && np <= 4) {
-      // up to 4 points per thread: the coefficient and twiddles of mode j + 1 are read
-      // while mode j's products are formed (the sums stay in mode order)
-      cpx<T> acc[4], tv[4];
+        for (int j = 0; j < M; ++j) {
+          const int jn = min(j + 1, M - 1);
+          const cpx<T> cn = coef[jn];
+          cpx<T> tn[4];
+          verify_twiddles<T, 4>(tw, (uint32_t)h0, rr[jn], p, inv_p, np, tn);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = cmk<T>(0, 0);
-      cpx<T> c = cmk<T>(0, 0);
-      if (M > 0) {
-        c = coef[0];
-        verify_twiddles<T, 4>(tw, (uint32_t)h0, rr[0], p, inv_p, np, tv);
-      }
-      for (int j = 0; j < M; ++j) {
-        const int jn = min(j + 1, M - 1);
-        const cpx<T> cn = coef[jn];
-        cpx<T> tn[4];
-        verify_twiddles<T, 4>(tw, (uint32_t)h0, rr[jn], p, inv_p, np, tn);
+          for (int u = 0; u < 4; ++u)
+            if (u < np) acc[u] = cadd(acc[u], cmul(c, tv[u]));
+          c = cn;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) tv[u] = tn[u];
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (u < np) acc[u] = cadd(acc[u], cmul(c, tv[u]));
-        c = cn;
+          if (u < np && h0 + u < h_hi) V[h0 + u] = acc[u];
+      } else if (h0 < h_hi) {
+        cpx<T> acc[kNpMax];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) tv[u] = tn[u];
+        for (int u = 0; u < kNpMax; ++u) acc[u] = cmk<T>(0, 0);
+        for (int j = 0; j < M; ++j) {
+          const uint32_t r = rr[j];
+          const cpx<T> c = coef[j];
+          uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
+#pragma unroll
+          for (int u = 0; u < kNpMax; ++u) {
+            if (u < np) {
+              acc[u] = cadd(acc[u], cmul(c, tw[idx]));
+              const uint32_t nx = idx + r;
+              idx = min(nx, nx - (uint32_t)p);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kNpMax; ++u)
+          if (u < np && h0 + u < h_hi) V[h0 + u] = acc[u];
       }
+      __syncthreads();
+      return;
+    }
+    if (sizeof(T) == 4 && p > 4 * kWG && p <= kNpMax * kWG) {
+      // lines longer than 4 points per thread: ceil(p / 256) consecutive points on every
+      // thread, in one pass (4 points per thread would leave a second pass to a few
+      // threads and double the time)
+      G = 1;
+      const int np = (p + kWG - 1) / kWG;
+      const int h0 = np * (int)threadIdx.x;
+      if (h0 < p) {
+        cpx<T> acc[kNpMax];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (u < np && h0 + u < h_hi) V[h0 + u] = acc[u];
-    } else if (h0 < h_hi) {
-      cpx<T> acc[kNpMax];
+        for (int u = 0; u < kNpMax; ++u) acc[u] = cmk<T>(0, 0);
+        for (int j = 0; j < M; ++j) {
+          const uint32_t r = rr[j];
+          const cpx<T> c = coef[j];
+          uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
 #pragma unroll
-      for (int u = 0; u < kNpMax; ++u) acc[u] = cmk<T>(0, 0);
-      for (int j = 0; j < M; ++j) {
-        const uint32_t r = rr[j];
-        const cpx<T> c = coef[j];
-        uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
+          for (int u = 0; u < kNpMax; ++u) {
+            if (u < np) {
+              acc[u] = cadd(acc[u], cmul(c, tw[idx]));
+              const uint32_t nx = idx + r;
+              idx = min(nx, nx - (uint32_t)p);
+            }
+          }
+        }
 #pragma unroll
-        for (int u = 0; u < kNpMax; ++u) {
-          if (u < np) {
+        for (int u = 0; u < kNpMax; ++u)
+          if (u < np && h0 + u < p) V[h0 + u] = acc[u];
+      }
+    } else if constexpr (sizeof(T) == 4) {
+      const int npg = (p + 3) / 4;
+      G = max(1, kWG / npg);
+      for (int t = threadIdx.x; t < G * npg; t += kWG) {
+        const int h0 = 4 * (t % npg), g = t / npg;
+        cpx<T> acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = cmk<T>(0, 0);
+        for (int j = g; j < M; j += G) {
+          const uint32_t r = rr[j];
+          const cpx<T> c = coef[j];
+          uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
             acc[u] = cadd(acc[u], cmul(c, tw[idx]));
             const uint32_t nx = idx + r;
             idx = min(nx, nx - (uint32_t)p);
           }
         }
-      }
-#pragma unroll
-      for (int u = 0; u < kNpMax; ++u)
-        if (u < np && h0 + u < h_hi) V[h0 + u] = acc[u];
-    }
-    __syncthreads();
-    return;
-  }
-  if (sizeof(T) == 4 && p > 4 * kWG && p <= kNpMax * kWG) {
-    // lines longer than 4 points per thread: ceil(p / 256) consecutive points on every
-    // thread, in one pass (4 points per thread would leave a second pass to a few
-    // threads and double the time)
-    G = 1;
-    const int np = (p + kWG - 1) / kWG;
-    const int h0 = np * (int)threadIdx.x;
-    if (h0 < p) {
-      cpx<T> acc[kNpMax];
-#pragma unroll
-      for (int u = 0; u < kNpMax; ++u) acc[u] = cmk<T>(0, 0);
-      for (int j = 0; j < M; ++j) {
-        const uint32_t r = rr[j];
-        const cpx<T> c = coef[j];
-        uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
-#pragma unroll
-        for (int u = 0; u < kNpMax; ++u) {
-          if (u < np) {
-            acc[u] = cadd(acc[u], cmul(c, tw[idx]));
-            const uint32_t nx = idx + r;
-            idx = min(nx, nx - (uint32_t)p);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kNpMax; ++u)
-        if (u < np && h0 + u < p) V[h0 + u] = acc[u];
-    }
-  } else if constexpr (sizeof(T) == 4) {
-    const int npg = (p + 3) / 4;
-    G = max(1, kWG / npg);
-    for (int t = threadIdx.x; t < G * npg; t += kWG) {
-      const int h0 = 4 * (t % npg), g = t / npg;
-      cpx<T> acc[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = cmk<T>(0, 0);
-      for (int j = g; j < M; j += G) {
-        const uint32_t r = rr[j];
-        const cpx<T> c = coef[j];
-        uint32_t idx = mulmod24((uint32_t)h0, r, (uint32_t)p, inv_p);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          acc[u] = cadd(acc[u], cmul(c, tw[idx]));
-          const uint32_t nx = idx + r;
-          idx = min(nx, nx - (uint32_t)p);
+          if (h0 + u < p) {
+            if (G == 1)
+              V[h0 + u] = acc[u];
+            else
+              part[g * p + h0 + u] = acc[u];
+          }
         }
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (h0 + u < p) {
-          if (G == 1)
-            V[h0 + u] = acc[u];
-          else
-            part[g * p + h0 + u] = acc[u];
-        }
+    } else {
+      G = (p < kWG) ? kWG / p : 1;
+      for (int t = threadIdx.x; t < G * p; t += kWG) {
+        const int h = t % p, g = t / p;
+        cpx<T> acc = cmk<T>(0, 0);
+        for (int j = g; j < M; j += G)
+          acc = cadd(acc, cmul(coef[j], tw[mulmod((uint32_t)h, (uint32_t)rr[j], p, inv_p)]));
+        if (G == 1)
+          V[h] = acc;
+        else
+          part[g * p + h] = acc;
       }
-    }
-  } else {
-    G = (p < kWG) ? kWG / p : 1;
-    for (int t = threadIdx.x; t < G * p; t += kWG) {
-      const int h = t % p, g = t / p;
-      cpx<T> acc = cmk<T>(0, 0);
-      for (int j = g; j < M; j += G)
-        acc = cadd(acc, cmul(coef[j], tw[mulmod((uint32_t)h, (uint32_t)rr[j], p, inv_p)]));
-      if (G == 1)
-        V[h] = acc;
-      else
-        part[g * p + h] = acc;
-    }
-  }
-  __syncthreads();
-  if (G > 1) {
-    for (int h = threadIdx.x; h < p; h += kWG) {
-      cpx<T> acc = part[h];
-      for (int g = 1; g < G; ++g) acc = cadd(acc, part[g * p + h]);
-      V[h] = acc;
     }
     __syncthreads();
-  }
+    if (G > 1) {
+      for (int h = threadIdx.x; h < p; h += kWG) {
+        cpx<T> acc = part[h];
+        for (int g = 1; g < G; ++g) acc = cadd(acc, part[g * p + h]);
+        V[h] = acc;
+      }
+      __syncthreads();
+    }
   }  // part_mode != 2
   if (extra) {
     for (int h = threadIdx.x; h < p; h += kWG) V[h] = cadd(V[h], extra[h]);
